@@ -1,0 +1,260 @@
+/*
+ * ccl.h -- C ABI of libccl: chunked range-mapper stencils on MI355X (gfx950).
+ *
+ * The execution model is the one the paper describes for Celerity (section
+ * 3, second listing and the paragraph after it): a data-parallel kernel runs
+ * over an N-D index range; the range is split into chunks, one per device;
+ * each accessor carries a range mapper that ties a chunk of the kernel's
+ * range to the region of a buffer the chunk reads or writes; the regions a
+ * chunk needs but does not own are inferred from the mappers and copied in
+ * before the chunk runs.  Here every chunk is device-local (its own buffer
+ * in the one GPU's memory), so the inferred transfers are device-to-device
+ * copies.  The chunk kernel is a 2D five-point / 3D seven-point leapfrog
+ * wave-equation stencil; SAXPY (the paper's first listing, section 2) is
+ * exported for bandwidth calibration, and device energy is read the way the
+ * paper's SYnergy queue exposes it (section 4, third listing).
+ *
+ * Conventions for every entry point
+ *   - Return value: CCL_OK (0) or a negative ccl_status; out-parameters are
+ *     written only on success.  ccl_last_error() returns a thread-local
+ *     message describing the most recent failure on the calling thread.
+ *   - No exception ever crosses this ABI.
+ *   - Memory: the caller owns all field memory (device pointers obtained
+ *     from hipMalloc or a framework allocator) and all streams.  The library
+ *     allocates only the opaque objects returned by *_create functions,
+ *     released by the matching *_destroy.
+ *   - Streams: `hip_stream` is a hipStream_t passed as void* (NULL = the
+ *     default stream).  Device work is enqueued asynchronously and the call
+ *     returns; launch errors are reported synchronously as CCL_E_HIP, faults
+ *     during execution surface at the caller's next synchronisation.
+ *   - Index spaces are global: chunk offsets, buffer regions and boxes are
+ *     given in the coordinates of the buffer (Celerity's virtual buffer),
+ *     dimension 0 slowest.  All integer extents are int64.
+ *   - Layout of a chunk buffer: element (i_0, ..., i_{D-1}) of the global
+ *     index space lives at base + sum_d (i_d - region.offset[d]) * pitch[d]
+ *     elements, with pitch[D-1] == 1 (row-major, innermost contiguous).
+ */
+#ifndef CCL_H
+#define CCL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ccl_status;
+
+enum {
+  CCL_OK = 0,
+  CCL_E_INVALID = -1,     /* bad argument: NULL, dims, counts, alignment   */
+  CCL_E_RANGE = -2,       /* an index box falls outside what is allowed    */
+  CCL_E_HIP = -3,         /* a HIP runtime call failed                     */
+  CCL_E_UNSUPPORTED = -4, /* feature not available (e.g. energy counter)   */
+  CCL_E_NOMEM = -5,       /* host or device allocation failed              */
+  CCL_E_STATE = -6,       /* object used in the wrong state                */
+  CCL_E_TIMEOUT = -7      /* a bounded device-side wait gave up            */
+};
+
+#define CCL_MAX_DIMS 3
+#define CCL_MAX_CHUNKS 64      /* chunks per ccl_wave_step / exchange call  */
+#define CCL_MAX_DEPTH 8        /* largest temporal depth T                  */
+
+/* An N-D box of indices: [offset[d], offset[d] + range[d]) for d < dims.
+ * Entries at d >= dims are ignored. */
+typedef struct {
+  int32_t dims;
+  int64_t offset[CCL_MAX_DIMS];
+  int64_t range[CCL_MAX_DIMS];
+} ccl_subrange;
+
+/* One chunk of a kernel's execution range.  `offset/range` is the chunk,
+ * `global_offset/global_range` the whole range it was split from (the
+ * parallel_for range).  For the wave stencil the global range is also the
+ * problem domain: cells outside it hold zero (homogeneous Dirichlet). */
+typedef struct {
+  int32_t dims;
+  int64_t offset[CCL_MAX_DIMS];
+  int64_t range[CCL_MAX_DIMS];
+  int64_t global_offset[CCL_MAX_DIMS];
+  int64_t global_range[CCL_MAX_DIMS];
+} ccl_chunk;
+
+/* Range mappers (section 3).  ONE_TO_ONE: the chunk touches exactly its own
+ * indices (the mapper of the paper's second listing).  NEIGHBORHOOD: the
+ * chunk grown by extent[d] on both sides of every dimension (a stencil's
+ * read set).  ALL: the whole buffer. */
+typedef enum {
+  CCL_MAP_ONE_TO_ONE = 0,
+  CCL_MAP_NEIGHBORHOOD = 1,
+  CCL_MAP_ALL = 2
+} ccl_mapper_kind;
+
+typedef struct {
+  int32_t kind;                   /* a ccl_mapper_kind                 */
+  int64_t extent[CCL_MAX_DIMS];   /* used by NEIGHBORHOOD, >= 0        */
+} ccl_range_mapper;
+
+/* A chunk's slice of one buffer in device memory (caller-owned). */
+typedef struct {
+  void *base;                     /* device address of region.offset   */
+  ccl_subrange region;            /* global indices held               */
+  int64_t pitch[CCL_MAX_DIMS];    /* element strides; pitch[dims-1]==1 */
+} ccl_chunk_buffer;
+
+/* One inferred transfer: box (global indices) owned by chunk `owner` and
+ * needed by chunk `reader`. */
+typedef struct {
+  int32_t owner;
+  int32_t reader;
+  ccl_subrange box;
+} ccl_transfer;
+
+/* Wave-stencil parameters. */
+typedef struct {
+  int32_t dims;              /* 2 or 3                                       */
+  float r2;                  /* (c dt / dx)^2; stable for r2 <= 1/dims       */
+  int32_t temporal_depth;    /* T in 1..CCL_MAX_DEPTH steps per HBM pass     */
+  int32_t tile_rows;         /* rows (2D) / planes (3D) per wave tile, 0=auto*/
+  int32_t flags;             /* reserved, must be 0                          */
+} ccl_wave_params;
+
+/* ----------------------------------------------------------------------- */
+
+/* Library version string (static storage). */
+const char *ccl_version(void);
+
+/* Message for the most recent failure on this thread ("" if none). */
+const char *ccl_last_error(void);
+
+/* Split a kernel range into chunks (section 3: a kernel is split across all
+ * available devices).  Along `split_dim`, chunk k of `nchunks` covers
+ * [o + floor(k n / K), o + floor((k+1) n / K)) where o, n are the range's
+ * offset and extent there; other dimensions are whole.  Chunks are disjoint,
+ * cover the range, and differ in size by at most one.
+ *   range        : the kernel range (dims in 1..3, range[d] >= 1)
+ *   chunks_out   : caller array of `nchunks` entries
+ * Errors: INVALID (NULL, dims, nchunks < 1, split_dim), RANGE (nchunks larger
+ * than the extent along split_dim). */
+ccl_status ccl_split_range(const ccl_subrange *range, int32_t nchunks,
+                           int32_t split_dim, ccl_chunk *chunks_out);
+
+/* Region of a buffer that a chunk accesses through a range mapper (section
+ * 3: the range mapper ties a chunk of the execution range to its data
+ * requirements).  NEIGHBORHOOD and ALL are clipped to [0, buffer_range).
+ *   buffer_range : extent of the (virtual) buffer, dims entries
+ * Errors: INVALID (NULL, dims mismatch, unknown kind, negative extent). */
+ccl_status ccl_region_of(const ccl_chunk *chunk, const ccl_range_mapper *mapper,
+                         const int64_t *buffer_range, ccl_subrange *region_out);
+
+/* Transfers a set of chunks needs before its kernel can run (section 3: the
+ * range mappers are used to infer the data transfers): for every ordered
+ * pair (owner k, reader j != k), region_of(chunk j, mapper) intersected with
+ * chunk k, when non-empty.  Writes at most `capacity` entries and the total
+ * count to *count (call with capacity 0 to size the array).
+ * Errors: INVALID, RANGE (count exceeds capacity: *count still written). */
+ccl_status ccl_transfers(int32_t nchunks, const ccl_chunk *chunks,
+                         const ccl_range_mapper *mapper,
+                         const int64_t *buffer_range, ccl_transfer *out,
+                         int32_t capacity, int32_t *count);
+
+/* Perform the inferred transfers between device-local chunk buffers: every
+ * box that ccl_transfers derives for `mapper` is copied from bufs[owner] to
+ * bufs[reader], all boxes in one kernel launch on `hip_stream`.
+ *   bufs       : one buffer per chunk; bufs[k].region must contain chunk k
+ *                and every box chunk k reads
+ *   elem_bytes : element size, a multiple of 4 (4 = float, 8 = double)
+ * Errors: INVALID, RANGE (a box outside a buffer's region), HIP. */
+ccl_status ccl_halo_exchange(int32_t nchunks, const ccl_chunk *chunks,
+                             const ccl_range_mapper *mapper,
+                             const ccl_chunk_buffer *bufs, int32_t elem_bytes,
+                             void *hip_stream);
+
+/* Pack boxes of chunk buffers into one contiguous staging buffer, box after
+ * box, each box row-major (what a sender hands to an interconnect), and the
+ * inverse.  Box b is read from / written to srcs[b] / dsts[b]; `staging`
+ * must hold sum of box sizes * elem_bytes bytes.  One launch each.
+ * Errors: INVALID, RANGE (box outside the buffer's region), HIP. */
+ccl_status ccl_halo_pack(int32_t nboxes, const ccl_subrange *boxes,
+                         const ccl_chunk_buffer *srcs, int32_t elem_bytes,
+                         void *staging, void *hip_stream);
+ccl_status ccl_halo_unpack(int32_t nboxes, const ccl_subrange *boxes,
+                           const ccl_chunk_buffer *dsts, int32_t elem_bytes,
+                           const void *staging, void *hip_stream);
+
+/* Advance the leapfrog wave equation by `nsteps` steps over all chunks.
+ *
+ * Per step, every cell of the domain (the chunks' global range) gets
+ *   2D: s = (u[i-1][j] + u[i+1][j]) + (u[i][j-1] + u[i][j+1]); lap = s - 4u
+ *   3D: s = ((u[z-1] + u[z+1]) + (u[y-1] + u[y+1])) + (u[x-1] + u[x+1]);
+ *       lap = s - 6u
+ *   u_next = fma(r2, lap, 2u - u_prev)            (float32, round-to-nearest)
+ * with zero outside the domain.  Work proceeds in blocks of T =
+ * temporal_depth steps (the last block may be shorter): before each block
+ * the halos are exchanged as ccl_halo_exchange does with NEIGHBORHOOD(T) for
+ * u_cur and NEIGHBORHOOD(T-1) for u_prev, then one launch advances every
+ * chunk T steps.
+ *
+ *   chunks          : nchunks chunks of one range (from ccl_split_range or
+ *                     any disjoint cover), dims == p->dims
+ *   u_prev, u_cur   : per chunk, the buffers holding u^{n-1} and u^n; their
+ *                     regions must contain the chunk grown by T-1 and T
+ *                     (clipped to the domain) respectively
+ *   w_prev, w_cur   : per chunk, a second pair of buffers of the same
+ *                     geometry, needed when T > 1 (may be NULL when T == 1,
+ *                     where u^{n+1} overwrites u^{n-1} in place)
+ *   On return the four descriptor arrays have been rotated so that u_cur
+ *   describes u^{n+nsteps} and u_prev u^{n+nsteps-1}; buffer contents in the
+ *   other pair are unspecified.  Results are bitwise independent of the
+ *   chunking, T and tile_rows.
+ * Alignment: every base 16-byte aligned, pitch[0] (and pitch[1] in 3D) a
+ * multiple of 4 elements.
+ * Errors: INVALID, RANGE, HIP. */
+ccl_status ccl_wave_step(const ccl_wave_params *p, int32_t nchunks,
+                         const ccl_chunk *chunks, ccl_chunk_buffer *u_prev,
+                         ccl_chunk_buffer *u_cur, ccl_chunk_buffer *w_prev,
+                         ccl_chunk_buffer *w_cur, int32_t nsteps,
+                         void *hip_stream);
+
+/* Cumulative energy drawn by GPU `device` (HIP ordinal), in joules, with
+ * the semantics of the paper's device-level energy query (section 4, third
+ * listing); a kernel's energy is the difference of two reads around it.
+ * If hip_stream is not NULL it is synchronised first.  The timestamp is the
+ * counter's own, in nanoseconds.  Backed by the amd-smi energy accumulator.
+ * Errors: INVALID, UNSUPPORTED (no working energy counter), HIP. */
+ccl_status ccl_energy_read(int32_t device, void *hip_stream, double *joules,
+                           uint64_t *timestamp_ns);
+
+/* Name of the energy backend in use for `device` after its first read:
+ * "amdsmi-energy-counter", "amdsmi-power-integrated" (socket power sampled
+ * every 5 ms and integrated, where the accumulator is not exposed), "fake"
+ * (forced by CCL_ENERGY_BACKEND=fake, for host-only tests), "unsupported"
+ * or "unprobed".  Static storage. */
+const char *ccl_energy_backend(int32_t device);
+
+/* z[i] = fma(a, x[i], y[i]) for i < n, float32: the kernel of the paper's
+ * first listing (section 2), used to measure achievable HBM bandwidth.
+ * x, y, z: device arrays of n floats, 16-byte aligned.  Errors: INVALID, HIP. */
+ccl_status ccl_saxpy(int64_t n, float a, const float *x, const float *y,
+                     float *z, void *hip_stream);
+
+/* Kernel launch timing, for measurement.  While enabled, every launch of
+ * the kernel families below is bracketed by HIP events recorded on the
+ * stream it is launched on.  ccl_timing_enable(on) discards earlier records
+ * and switches recording on or off; ccl_timing_query waits for the recorded
+ * events of one family and returns their count and summed duration (ms).
+ * Errors: INVALID, HIP. */
+enum {
+  CCL_KERNEL_STENCIL = 0,  /* the wave-stencil kernels (2D and 3D)          */
+  CCL_KERNEL_HALO = 1,     /* halo exchange / pack / unpack copies          */
+  CCL_KERNEL_SAXPY = 2,
+  CCL_KERNEL_KINDS = 3
+};
+ccl_status ccl_timing_enable(int32_t on);
+ccl_status ccl_timing_query(int32_t kernel, int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCL_H */

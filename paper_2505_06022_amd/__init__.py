@@ -1,0 +1,274 @@
+"""Python binding of libccl (ctypes): argument marshalling only.
+
+Every function here has the name of the C entry point it calls (see
+``include/ccl.h``) and does nothing but convert arguments; all device work
+runs in the library's HIP kernels.  If ``libccl.so`` has not been built the
+first call raises: there is no fallback path.
+
+PyTorch is used only by the helpers in ``fields`` for device memory and
+streams; this module imports it lazily.
+"""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+_PKG = Path(__file__).resolve().parent
+LIB_PATH = _PKG / "libccl.so"
+
+CCL_OK = 0
+CCL_E_INVALID = -1
+CCL_E_RANGE = -2
+CCL_E_HIP = -3
+CCL_E_UNSUPPORTED = -4
+CCL_E_NOMEM = -5
+CCL_E_STATE = -6
+CCL_E_TIMEOUT = -7
+
+CCL_MAX_DIMS = 3
+CCL_MAX_CHUNKS = 64
+CCL_MAX_DEPTH = 8
+
+ONE_TO_ONE, NEIGHBORHOOD, ALL = 0, 1, 2
+
+_I64x3 = ctypes.c_int64 * 3
+
+
+class ccl_subrange(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32), ("offset", _I64x3), ("range", _I64x3)]
+
+    def box(self):
+        d = self.dims
+        return (tuple(self.offset[:d]), tuple(self.range[:d]))
+
+
+class ccl_chunk(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32), ("offset", _I64x3), ("range", _I64x3),
+                ("global_offset", _I64x3), ("global_range", _I64x3)]
+
+    def box(self):
+        d = self.dims
+        return (tuple(self.offset[:d]), tuple(self.range[:d]))
+
+
+class ccl_range_mapper(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("extent", _I64x3)]
+
+
+class ccl_chunk_buffer(ctypes.Structure):
+    _fields_ = [("base", ctypes.c_void_p), ("region", ccl_subrange), ("pitch", _I64x3)]
+
+
+class ccl_transfer(ctypes.Structure):
+    _fields_ = [("owner", ctypes.c_int32), ("reader", ctypes.c_int32), ("box", ccl_subrange)]
+
+
+class ccl_wave_params(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32), ("r2", ctypes.c_float),
+                ("temporal_depth", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+class CclError(RuntimeError):
+    def __init__(self, fn: str, status: int, message: str):
+        super().__init__(f"{fn} failed with status {status}: {message}")
+        self.status = status
+        self.message = message
+
+
+# Every symbol include/ccl.h declares, with (restype, argtypes).
+_P = ctypes.POINTER
+_SIGS = {
+    "ccl_version": (ctypes.c_char_p, []),
+    "ccl_last_error": (ctypes.c_char_p, []),
+    "ccl_split_range": (ctypes.c_int32, [_P(ccl_subrange), ctypes.c_int32, ctypes.c_int32,
+                                         _P(ccl_chunk)]),
+    "ccl_region_of": (ctypes.c_int32, [_P(ccl_chunk), _P(ccl_range_mapper), _P(ctypes.c_int64),
+                                       _P(ccl_subrange)]),
+    "ccl_transfers": (ctypes.c_int32, [ctypes.c_int32, _P(ccl_chunk), _P(ccl_range_mapper),
+                                       _P(ctypes.c_int64), _P(ccl_transfer), ctypes.c_int32,
+                                       _P(ctypes.c_int32)]),
+    "ccl_halo_exchange": (ctypes.c_int32, [ctypes.c_int32, _P(ccl_chunk), _P(ccl_range_mapper),
+                                           _P(ccl_chunk_buffer), ctypes.c_int32,
+                                           ctypes.c_void_p]),
+    "ccl_halo_pack": (ctypes.c_int32, [ctypes.c_int32, _P(ccl_subrange), _P(ccl_chunk_buffer),
+                                       ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "ccl_halo_unpack": (ctypes.c_int32, [ctypes.c_int32, _P(ccl_subrange),
+                                         _P(ccl_chunk_buffer), ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
+    "ccl_wave_step": (ctypes.c_int32, [_P(ccl_wave_params), ctypes.c_int32, _P(ccl_chunk),
+                                       _P(ccl_chunk_buffer), _P(ccl_chunk_buffer),
+                                       _P(ccl_chunk_buffer), _P(ccl_chunk_buffer),
+                                       ctypes.c_int32, ctypes.c_void_p]),
+    "ccl_energy_read": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_void_p, _P(ctypes.c_double),
+                                         _P(ctypes.c_uint64)]),
+    "ccl_energy_backend": (ctypes.c_char_p, [ctypes.c_int32]),
+    "ccl_saxpy": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_float, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "ccl_timing_enable": (ctypes.c_int32, [ctypes.c_int32]),
+    "ccl_timing_query": (ctypes.c_int32, [ctypes.c_int32, _P(ctypes.c_int64),
+                                          _P(ctypes.c_double)]),
+}
+
+CCL_KERNEL_STENCIL, CCL_KERNEL_HALO, CCL_KERNEL_SAXPY = 0, 1, 2
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libccl.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2505_06022_amd.build` "
+                "(there is no fallback implementation)")
+        L = ctypes.CDLL(str(LIB_PATH))
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(fn: str, st: int):
+    if st != CCL_OK:
+        raise CclError(fn, st, lib().ccl_last_error().decode())
+
+
+def _stream(stream):
+    """hipStream_t as a void*: None -> the current torch stream, int/ptr as is."""
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return stream
+
+
+def _i64(vals, n=3):
+    a = _I64x3()
+    for i, v in enumerate(list(vals)[:n]):
+        a[i] = int(v)
+    return a
+
+
+def make_subrange(offset, rng) -> ccl_subrange:
+    s = ccl_subrange()
+    s.dims = len(rng)
+    s.offset = _i64(offset)
+    s.range = _i64(rng)
+    return s
+
+
+def make_mapper(kind: int, extent=(0, 0, 0)) -> ccl_range_mapper:
+    m = ccl_range_mapper()
+    m.kind = int(kind)
+    m.extent = _i64(extent)
+    return m
+
+
+def ccl_version() -> str:
+    return lib().ccl_version().decode()
+
+
+def ccl_last_error() -> str:
+    return lib().ccl_last_error().decode()
+
+
+def ccl_split_range(offset, rng, nchunks: int, split_dim: int = 0):
+    out = (ccl_chunk * max(1, nchunks))()
+    r = make_subrange(offset, rng)
+    _check("ccl_split_range", lib().ccl_split_range(ctypes.byref(r), nchunks, split_dim, out))
+    return out
+
+
+def ccl_region_of(chunk: ccl_chunk, kind: int, extent, buffer_range) -> ccl_subrange:
+    m = make_mapper(kind, extent)
+    br = _i64(buffer_range)
+    out = ccl_subrange()
+    _check("ccl_region_of", lib().ccl_region_of(ctypes.byref(chunk), ctypes.byref(m), br,
+                                                ctypes.byref(out)))
+    return out
+
+
+def ccl_transfers(chunks, kind: int, extent, buffer_range):
+    m = make_mapper(kind, extent)
+    br = _i64(buffer_range)
+    n = ctypes.c_int32(0)
+    st = lib().ccl_transfers(len(chunks), chunks, ctypes.byref(m), br, None, 0, ctypes.byref(n))
+    if st not in (CCL_OK, CCL_E_RANGE):
+        _check("ccl_transfers", st)
+    out = (ccl_transfer * max(1, n.value))()
+    _check("ccl_transfers", lib().ccl_transfers(len(chunks), chunks, ctypes.byref(m), br, out,
+                                                n.value, ctypes.byref(n)))
+    return list(out)[: n.value]
+
+
+def ccl_halo_exchange(chunks, kind: int, extent, bufs, elem_bytes: int = 4, stream=None):
+    m = make_mapper(kind, extent)
+    _check("ccl_halo_exchange", lib().ccl_halo_exchange(len(chunks), chunks, ctypes.byref(m),
+                                                        bufs, elem_bytes, _stream(stream)))
+
+
+def ccl_halo_pack(boxes, srcs, elem_bytes: int, staging_ptr: int, stream=None):
+    bx = (ccl_subrange * len(boxes))(*boxes)
+    _check("ccl_halo_pack", lib().ccl_halo_pack(len(boxes), bx, srcs, elem_bytes,
+                                                ctypes.c_void_p(staging_ptr), _stream(stream)))
+
+
+def ccl_halo_unpack(boxes, dsts, elem_bytes: int, staging_ptr: int, stream=None):
+    bx = (ccl_subrange * len(boxes))(*boxes)
+    _check("ccl_halo_unpack", lib().ccl_halo_unpack(len(boxes), bx, dsts, elem_bytes,
+                                                    ctypes.c_void_p(staging_ptr),
+                                                    _stream(stream)))
+
+
+def make_wave_params(dims: int, r2: float, temporal_depth: int = 1, tile_rows: int = 0):
+    p = ccl_wave_params()
+    p.dims, p.r2, p.temporal_depth, p.tile_rows, p.flags = dims, r2, temporal_depth, tile_rows, 0
+    return p
+
+
+def ccl_wave_step(params: ccl_wave_params, chunks, u_prev, u_cur, w_prev, w_cur, nsteps: int,
+                  stream=None):
+    """Advances nsteps; the four ccl_chunk_buffer arrays are rotated in place."""
+    _check("ccl_wave_step", lib().ccl_wave_step(ctypes.byref(params), len(chunks), chunks,
+                                                u_prev, u_cur, w_prev, w_cur, int(nsteps),
+                                                _stream(stream)))
+
+
+def ccl_energy_read(device: int = 0, stream=None):
+    """(joules, timestamp_ns).  ``stream`` (torch stream or hipStream_t int)
+    is synchronised first when given; None reads without synchronising."""
+    j = ctypes.c_double(0.0)
+    ts = ctypes.c_uint64(0)
+    s = _stream(stream) if stream is not None else None
+    _check("ccl_energy_read", lib().ccl_energy_read(device, s, ctypes.byref(j), ctypes.byref(ts)))
+    return j.value, ts.value
+
+
+def ccl_energy_backend(device: int = 0) -> str:
+    return lib().ccl_energy_backend(device).decode()
+
+
+def ccl_saxpy(n: int, a: float, x_ptr: int, y_ptr: int, z_ptr: int, stream=None):
+    _check("ccl_saxpy", lib().ccl_saxpy(int(n), float(a), ctypes.c_void_p(x_ptr),
+                                        ctypes.c_void_p(y_ptr), ctypes.c_void_p(z_ptr),
+                                        _stream(stream)))
+
+
+def ccl_timing_enable(on: bool = True):
+    _check("ccl_timing_enable", lib().ccl_timing_enable(1 if on else 0))
+
+
+def ccl_timing_query(kernel: int):
+    """(launches, total_ms) of the recorded launches of one kernel family."""
+    n = ctypes.c_int64(0)
+    ms = ctypes.c_double(0.0)
+    _check("ccl_timing_query", lib().ccl_timing_query(int(kernel), ctypes.byref(n),
+                                                      ctypes.byref(ms)))
+    return n.value, ms.value

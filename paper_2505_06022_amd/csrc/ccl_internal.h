@@ -1,0 +1,104 @@
+// Internal declarations shared by the translation units of libccl.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "ccl.h"
+
+namespace ccl {
+
+// Records a message for ccl_last_error() and returns `st`.
+ccl_status fail(ccl_status st, const char *fmt, ...);
+void clear_error();
+
+inline ccl_status hip_check(hipError_t e, const char *what) {
+  if (e == hipSuccess) return CCL_OK;
+  return fail(CCL_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Half-open interval helpers on int64 boxes.
+struct Box {
+  int32_t dims = 0;
+  int64_t lo[CCL_MAX_DIMS] = {0, 0, 0};
+  int64_t hi[CCL_MAX_DIMS] = {0, 0, 0};
+  bool empty() const {
+    for (int d = 0; d < dims; ++d)
+      if (hi[d] <= lo[d]) return true;
+    return false;
+  }
+  int64_t volume() const {
+    int64_t v = 1;
+    for (int d = 0; d < dims; ++d) v *= (hi[d] > lo[d] ? hi[d] - lo[d] : 0);
+    return v;
+  }
+};
+
+Box box_of(const ccl_subrange &s);
+Box chunk_box(const ccl_chunk &c);
+Box domain_box(const ccl_chunk &c);
+ccl_subrange subrange_of(const Box &b);
+Box intersect(const Box &a, const Box &b);
+bool contains(const Box &outer, const Box &inner);
+Box grow(const Box &b, int64_t e);  // by e along every dimension
+
+ccl_status check_chunks(int32_t nchunks, const ccl_chunk *chunks, int32_t dims);
+ccl_status check_buffer(const ccl_chunk_buffer &b, int32_t dims, const char *what,
+                        bool need_vec_align);
+
+// Brackets one kernel launch with timing events when timing is enabled.
+class TimedLaunch {
+ public:
+  TimedLaunch(int kind, hipStream_t s);
+  ~TimedLaunch();
+  TimedLaunch(const TimedLaunch &) = delete;
+  TimedLaunch &operator=(const TimedLaunch &) = delete;
+
+ private:
+  int kind_;
+  hipStream_t stream_;
+  std::pair<hipEvent_t, hipEvent_t> ev_{};
+  bool active_ = false;
+};
+
+// ---- halo copies (halo.hip) ----------------------------------------------
+// One copy job: a box of 4-byte words from src to dst.  Strides in words.
+struct CopyJob {
+  const uint32_t *src;
+  uint32_t *dst;
+  int64_t src_pitch0, src_pitch1;  // words per step of dim 0 / dim 1
+  int64_t dst_pitch0, dst_pitch1;
+  int32_t n0, n1, n2;              // extents (dim 2 in words, contiguous)
+};
+// Enqueues all jobs (any count; split into launches internally).
+ccl_status launch_copies(const CopyJob *jobs, int32_t njobs, hipStream_t stream);
+// Appends the copy jobs of every transfer that `mapper` infers among the
+// chunk buffers (reader region ∩ owner chunk), validating both buffers.
+ccl_status exchange_jobs(int32_t nchunks, const ccl_chunk *chunks, const ccl_range_mapper &mapper,
+                         const ccl_chunk_buffer *bufs, int32_t elem_bytes,
+                         std::vector<CopyJob> *jobs);
+
+// ---- wave kernels --------------------------------------------------------
+struct WaveField {      // one chunk buffer as the kernels see it
+  float *base;
+  int64_t off[CCL_MAX_DIMS];
+  int64_t pitch[CCL_MAX_DIMS];
+};
+
+struct WaveChunkPlan {  // host-side plan of one chunk for one block of steps
+  Box chunk;
+  Box domain;
+  WaveField in_prev, in_cur, out_prev, out_cur;
+  Box load_prev, load_cur;  // loadable index boxes (region of the buffer ∩ domain)
+};
+
+ccl_status launch_wave2d(int32_t depth, bool in_place, float r2, int32_t tile_rows,
+                         const WaveChunkPlan *plans, int32_t nplans, hipStream_t stream);
+ccl_status launch_wave3d(int32_t depth, bool in_place, float r2, int32_t tile_rows,
+                         const WaveChunkPlan *plans, int32_t nplans, hipStream_t stream);
+
+}  // namespace ccl

@@ -1,0 +1,160 @@
+// ccl_wave_step: blocks of T leapfrog steps over device-local chunks.
+//
+// Before each block the halos the range mappers call for are copied in
+// (NEIGHBORHOOD(T) of u^n, NEIGHBORHOOD(T-1) of u^{n-1}: section 3, the
+// transfers inferred from the mappers), then one launch advances every chunk
+// T steps.  The host only plans and enqueues; the caller's descriptor arrays
+// are rotated to name the newest levels.
+#include <cmath>
+#include <cstring>
+#include <utility>
+#include <vector>
+
+#include "ccl_internal.h"
+
+namespace ccl {
+
+int32_t wave2d_auto_rows(int32_t depth, int64_t rows, int64_t cols, int32_t nchunks);
+
+namespace {
+
+WaveField field_of(const ccl_chunk_buffer &b) {
+  WaveField f;
+  f.base = static_cast<float *>(b.base);
+  for (int d = 0; d < CCL_MAX_DIMS; ++d) {
+    f.off[d] = d < b.region.dims ? b.region.offset[d] : 0;
+    f.pitch[d] = d < b.region.dims ? b.pitch[d] : 0;
+  }
+  return f;
+}
+
+// Region requirement of a role: chunk grown by `e`, clipped to the domain.
+bool holds(const ccl_chunk_buffer &b, const ccl_chunk &c, int64_t e) {
+  Box need = intersect(grow(chunk_box(c), e), domain_box(c));
+  return contains(box_of(b.region), need);
+}
+
+}  // namespace
+}  // namespace ccl
+
+using namespace ccl;
+
+extern "C" ccl_status ccl_wave_step(const ccl_wave_params *p, int32_t nchunks,
+                                    const ccl_chunk *chunks, ccl_chunk_buffer *u_prev,
+                                    ccl_chunk_buffer *u_cur, ccl_chunk_buffer *w_prev,
+                                    ccl_chunk_buffer *w_cur, int32_t nsteps, void *hip_stream) {
+  clear_error();
+  if (!p || !u_prev || !u_cur) return fail(CCL_E_INVALID, "NULL argument");
+  const int dims = p->dims;
+  if (dims != 2 && dims != 3) return fail(CCL_E_INVALID, "wave dims=%d must be 2 or 3", dims);
+  if (!std::isfinite(p->r2) || p->r2 < 0.0f) return fail(CCL_E_INVALID, "r2 must be finite, >= 0");
+  const int T = p->temporal_depth;
+  if (T < 1 || T > CCL_MAX_DEPTH)
+    return fail(CCL_E_INVALID, "temporal_depth=%d not in 1..%d", T, CCL_MAX_DEPTH);
+  if (p->tile_rows < 0) return fail(CCL_E_INVALID, "tile_rows < 0");
+  if (p->flags != 0) return fail(CCL_E_INVALID, "flags must be 0");
+  if (nsteps < 0) return fail(CCL_E_INVALID, "nsteps < 0");
+  if (dims == 3 && T != 1) return fail(CCL_E_UNSUPPORTED, "3D stencil supports T == 1 only");
+  ccl_status st = check_chunks(nchunks, chunks, dims);
+  if (st != CCL_OK) return st;
+  const bool need_w = T > 1 && nsteps > 1;
+  if (need_w && (!w_prev || !w_cur))
+    return fail(CCL_E_INVALID, "T > 1 needs the w_prev / w_cur buffer pair");
+  for (int k = 0; k < nchunks; ++k) {
+    ccl_chunk_buffer *sets[4] = {u_prev, u_cur, need_w ? w_prev : nullptr,
+                                 need_w ? w_cur : nullptr};
+    const char *names[4] = {"u_prev", "u_cur", "w_prev", "w_cur"};
+    for (int b = 0; b < 4; ++b) {
+      if (!sets[b]) continue;
+      st = check_buffer(sets[b][k], dims, names[b], true);
+      if (st != CCL_OK) return st;
+    }
+  }
+  if (nsteps == 0) return CCL_OK;
+
+  // Dry run of the role rotation: check every block's region requirements
+  // before anything is enqueued.
+  {
+    std::vector<ccl_chunk_buffer> up(u_prev, u_prev + nchunks), uc(u_cur, u_cur + nchunks);
+    std::vector<ccl_chunk_buffer> wp, wc;
+    if (need_w) {
+      wp.assign(w_prev, w_prev + nchunks);
+      wc.assign(w_cur, w_cur + nchunks);
+    }
+    for (int done = 0; done < nsteps;) {
+      const int tb = (nsteps - done) < T ? (nsteps - done) : T;
+      for (int k = 0; k < nchunks; ++k) {
+        if (!holds(uc[k], chunks[k], tb))
+          return fail(CCL_E_RANGE, "chunk %d: u^n buffer region lacks the %d-wide halo", k, tb);
+        if (!holds(up[k], chunks[k], tb - 1))
+          return fail(CCL_E_RANGE, "chunk %d: u^{n-1} buffer region lacks the %d-wide halo", k,
+                      tb - 1);
+        if (tb > 1 && (!contains(box_of(wp[k].region), chunk_box(chunks[k])) ||
+                       !contains(box_of(wc[k].region), chunk_box(chunks[k]))))
+          return fail(CCL_E_RANGE, "chunk %d: w buffers do not hold the chunk", k);
+      }
+      if (tb == 1) {
+        std::swap(up, uc);
+      } else {
+        std::swap(up, wp);
+        std::swap(uc, wc);
+      }
+      done += tb;
+    }
+  }
+
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  std::vector<WaveChunkPlan> plans(nchunks);
+  std::vector<CopyJob> jobs;
+  for (int done = 0; done < nsteps;) {
+    const int tb = (nsteps - done) < T ? (nsteps - done) : T;
+    const bool in_place = tb == 1;
+    // 1. inferred transfers: u^n with NEIGHBORHOOD(tb), u^{n-1} with NEIGHBORHOOD(tb-1)
+    jobs.clear();
+    if (nchunks > 1) {
+      ccl_range_mapper m;
+      memset(&m, 0, sizeof(m));
+      m.kind = CCL_MAP_NEIGHBORHOOD;
+      for (int d = 0; d < dims; ++d) m.extent[d] = tb;
+      st = exchange_jobs(nchunks, chunks, m, u_cur, 4, &jobs);
+      if (st != CCL_OK) return st;
+      if (tb > 1) {
+        for (int d = 0; d < dims; ++d) m.extent[d] = tb - 1;
+        st = exchange_jobs(nchunks, chunks, m, u_prev, 4, &jobs);
+        if (st != CCL_OK) return st;
+      }
+      if (!jobs.empty()) {
+        st = launch_copies(jobs.data(), static_cast<int32_t>(jobs.size()), stream);
+        if (st != CCL_OK) return st;
+      }
+    }
+    // 2. one launch advances all chunks tb steps
+    for (int k = 0; k < nchunks; ++k) {
+      WaveChunkPlan &P = plans[k];
+      P.chunk = chunk_box(chunks[k]);
+      P.domain = domain_box(chunks[k]);
+      P.in_prev = field_of(u_prev[k]);
+      P.in_cur = field_of(u_cur[k]);
+      P.out_prev = in_place ? field_of(u_prev[k]) : field_of(w_prev[k]);
+      P.out_cur = in_place ? field_of(u_prev[k]) : field_of(w_cur[k]);
+      P.load_prev = intersect(box_of(u_prev[k].region), P.domain);
+      P.load_cur = intersect(box_of(u_cur[k].region), P.domain);
+    }
+    if (dims == 2)
+      st = launch_wave2d(tb, in_place, p->r2, p->tile_rows, plans.data(), nchunks, stream);
+    else
+      st = launch_wave3d(tb, in_place, p->r2, p->tile_rows, plans.data(), nchunks, stream);
+    if (st != CCL_OK) return st;
+    // 3. rotate roles so u_cur names the newest level
+    for (int k = 0; k < nchunks; ++k) {
+      if (in_place) {
+        std::swap(u_prev[k], u_cur[k]);
+      } else {
+        std::swap(u_prev[k], w_prev[k]);
+        std::swap(u_cur[k], w_cur[k]);
+      }
+    }
+    done += tb;
+  }
+  return CCL_OK;
+}

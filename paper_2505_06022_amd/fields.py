@@ -1,0 +1,121 @@
+"""Chunk buffers in device memory for the binding (PyTorch as allocator).
+
+``ChunkedWave`` splits a domain with ccl_split_range, sizes every chunk's
+buffers with ccl_region_of (NEIGHBORHOOD(T) against the virtual buffer),
+allocates them with torch, scatters an initial state into the chunk cells
+and gathers the chunk cells back.  Stepping is a single ccl_wave_step call;
+nothing here computes on the data.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import (NEIGHBORHOOD, ccl_chunk_buffer, ccl_region_of, ccl_split_range, ccl_wave_step,
+               make_subrange, make_wave_params)
+
+PITCH_ALIGN = 64  # elements; keeps every row start 256-byte aligned
+
+
+def _round_up(v: int, a: int) -> int:
+    return (v + a - 1) // a * a
+
+
+def alloc_buffer(region, device="cuda", fill=0.0, pitch_align=PITCH_ALIGN):
+    """A torch tensor holding `region` (offset, range) row-major with a padded
+    innermost pitch, and its ccl_chunk_buffer descriptor."""
+    import torch
+    off, rng = region
+    dims = len(rng)
+    pitch_last = _round_up(int(rng[-1]), pitch_align)
+    shape = tuple(int(r) for r in rng[:-1]) + (pitch_last,)
+    t = torch.full(shape, float(fill), dtype=torch.float32, device=device)
+    b = ccl_chunk_buffer()
+    b.base = t.data_ptr()
+    b.region = make_subrange(off, rng)
+    strides = t.stride()
+    for d in range(dims):
+        b.pitch[d] = int(strides[d])
+    return t, b
+
+
+def view_of(t, region, box):
+    """Slice of buffer tensor `t` (holding `region`) covering global `box`."""
+    (roff, _), (boff, brng) = region, box
+    sl = tuple(slice(b - r, b - r + n) for r, b, n in zip(roff, boff, brng))
+    return t[sl]
+
+
+class ChunkedWave:
+    def __init__(self, domain_offset, domain_shape, nchunks: int, r2: float, depth: int = 1,
+                 tile_rows: int = 0, buffer_range=None, split_dim: int = 0, device="cuda",
+                 fill=0.0):
+        self.dims = len(domain_shape)
+        self.domain_offset = tuple(int(v) for v in domain_offset)
+        self.domain_shape = tuple(int(v) for v in domain_shape)
+        self.buffer_range = tuple(buffer_range) if buffer_range is not None else tuple(
+            o + n for o, n in zip(self.domain_offset, self.domain_shape))
+        self.depth = depth
+        self.params = make_wave_params(self.dims, r2, depth, tile_rows)
+        self.chunks = ccl_split_range(self.domain_offset, self.domain_shape, nchunks, split_dim)
+        self.nchunks = nchunks
+        ext = (depth,) * self.dims
+        self.regions = [ccl_region_of(c, NEIGHBORHOOD, ext, self.buffer_range).box()
+                        for c in self.chunks]
+        nbuf = 4 if depth > 1 else 2
+        self.tensors = {}
+        arrays = [(ccl_chunk_buffer * nchunks)() for _ in range(4)]
+        for k, reg in enumerate(self.regions):
+            for which in range(nbuf):
+                t, b = alloc_buffer(reg, device=device, fill=fill)
+                arrays[which][k] = b
+                self.tensors[b.base] = (t, reg)
+        self.u_prev, self.u_cur, self.w_prev, self.w_cur = arrays
+        if nbuf == 2:
+            self.w_prev = self.w_cur = None
+
+    def chunk_box(self, k):
+        return self.chunks[k].box()
+
+    def _local(self, box):
+        (o, n) = box
+        return tuple(slice(a - d, a - d + m) for a, d, m in zip(o, self.domain_offset, n))
+
+    def scatter(self, u_prev, u_cur):
+        """Copy host arrays of the domain's shape into every chunk's own cells."""
+        import torch
+        for k in range(self.nchunks):
+            box = self.chunk_box(k)
+            for arr, host in ((self.u_prev, u_prev), (self.u_cur, u_cur)):
+                t, reg = self.tensors[arr[k].base]
+                src = torch.from_numpy(np.ascontiguousarray(host[self._local(box)],
+                                                            dtype=np.float32))
+                view_of(t, reg, box).copy_(src, non_blocking=False)
+
+    def gather(self, which="cur"):
+        arr = self.u_cur if which == "cur" else self.u_prev
+        out = np.empty(self.domain_shape, dtype=np.float32)
+        for k in range(self.nchunks):
+            box = self.chunk_box(k)
+            t, reg = self.tensors[arr[k].base]
+            out[self._local(box)] = view_of(t, reg, box).cpu().numpy()
+        return out
+
+    def gather_points(self, points, which="cur"):
+        """Values at global indices `points` (list of tuples) of u_cur / u_prev."""
+        arr = self.u_cur if which == "cur" else self.u_prev
+        vals = []
+        for p in points:
+            for k in range(self.nchunks):
+                (o, n) = self.chunk_box(k)
+                if all(o[d] <= p[d] < o[d] + n[d] for d in range(self.dims)):
+                    t, reg = self.tensors[arr[k].base]
+                    idx = tuple(p[d] - reg[0][d] for d in range(self.dims))
+                    vals.append(float(t[idx].item()))
+                    break
+            else:
+                raise IndexError(p)
+        return np.array(vals, dtype=np.float32)
+
+    def step(self, nsteps: int, stream=None):
+        ccl_wave_step(self.params, self.chunks, self.u_prev, self.u_cur, self.w_prev, self.w_cur,
+                      nsteps, stream)

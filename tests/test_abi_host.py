@@ -1,0 +1,217 @@
+"""Host-side tests of libccl (CPU only: no kernel is launched).
+
+* The library loads and exports every function include/ccl.h declares.
+* ccl_split_range / ccl_region_of / ccl_transfers agree with the oracle's
+  interval arithmetic, exhaustively on small ranges.
+* Argument validation returns the documented status codes before any device
+  work is enqueued.
+* The fake energy backend drives the J/step arithmetic.
+"""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import pytest
+
+import paper_2505_06022_amd as ccl
+from oracle import ranges
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    with open(os.path.join(ROOT, "include", "ccl.h")) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ccl_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 10
+    L = ccl.lib()
+    for n in names:
+        assert hasattr(L, n), f"libccl.so does not export {n}"
+    assert set(names) <= set(ccl._SIGS), "binding lacks a signature for a declared function"
+
+
+def test_version():
+    assert "gfx950" in ccl.ccl_version()
+
+
+@pytest.mark.parametrize("dims", [1, 2, 3])
+def test_split_matches_oracle(dims):
+    for n in (1, 2, 5, 17, 64):
+        for K in range(1, min(n, 16) + 1):
+            for sd in range(dims):
+                rng = [4] * dims
+                rng[sd] = n
+                off = [3, -2, 7][:dims]
+                got = [c.box() for c in ccl.ccl_split_range(off, rng, K, sd)]
+                want = ranges.split_range(tuple(off), tuple(rng), K, sd)
+                assert got == want
+                for c in ccl.ccl_split_range(off, rng, K, sd):
+                    assert tuple(c.global_offset[:dims]) == tuple(off)
+                    assert tuple(c.global_range[:dims]) == tuple(rng)
+
+
+@pytest.mark.parametrize("dims", [1, 2, 3])
+def test_region_matches_oracle(dims):
+    import numpy as np
+    rs = np.random.default_rng(11)
+    for _ in range(300):
+        buf = tuple(int(v) for v in rs.integers(1, 40, size=dims))
+        rng = tuple(int(rs.integers(1, b + 1)) for b in buf)
+        off = tuple(int(rs.integers(0, b - r + 1)) for b, r in zip(buf, rng))
+        K = int(rs.integers(1, rng[0] + 1))
+        for c in ccl.ccl_split_range(off, rng, K, 0):
+            for kind in (ccl.ONE_TO_ONE, ccl.NEIGHBORHOOD, ccl.ALL):
+                e = tuple(int(v) for v in rs.integers(0, 6, size=dims))
+                got = ccl.ccl_region_of(c, kind, e, buf).box()
+                assert got == ranges.region_of(c.box(), kind, e, buf)
+
+
+def test_transfers_match_oracle():
+    for dims, shape in ((2, (37, 11)), (3, (19, 5, 6))):
+        for K in (1, 2, 3, 7):
+            for e in (0, 1, 2, 4):
+                chunks = ccl.ccl_split_range((0,) * dims, shape, K, 0)
+                got = sorted((t.owner, t.reader, t.box.box()) for t in
+                             ccl.ccl_transfers(chunks, ccl.NEIGHBORHOOD, (e,) * dims, shape))
+                regs = [ranges.region_of(c.box(), ranges.NEIGHBORHOOD, (e,) * dims, shape)
+                        for c in chunks]
+                want = sorted(ranges.transfers([c.box() for c in chunks], regs))
+                assert got == want
+
+
+def _status(fn, *args):
+    return fn(*args)
+
+
+def test_split_errors():
+    L = ccl.lib()
+    out = (ccl.ccl_chunk * 8)()
+    r = ccl.make_subrange((0, 0), (4, 4))
+    assert L.ccl_split_range(ctypes.byref(r), 0, 0, out) == ccl.CCL_E_INVALID
+    assert L.ccl_split_range(ctypes.byref(r), 5, 0, out) == ccl.CCL_E_RANGE
+    assert "exceeds" in ccl.ccl_last_error()
+    assert L.ccl_split_range(ctypes.byref(r), 2, 2, out) == ccl.CCL_E_INVALID
+    assert L.ccl_split_range(None, 2, 0, out) == ccl.CCL_E_INVALID
+    bad = ccl.make_subrange((0, 0, 0, 0)[:3], (4, 4, 4))
+    bad.dims = 4
+    assert L.ccl_split_range(ctypes.byref(bad), 2, 0, out) == ccl.CCL_E_INVALID
+    bad.dims = 2
+    bad.range[1] = 0
+    assert L.ccl_split_range(ctypes.byref(bad), 2, 0, out) == ccl.CCL_E_INVALID
+
+
+def test_region_errors():
+    L = ccl.lib()
+    c = ccl.ccl_split_range((0, 0), (8, 8), 2)[0]
+    m = ccl.make_mapper(7)
+    out = ccl.ccl_subrange()
+    br = ccl._i64((8, 8))
+    assert L.ccl_region_of(ctypes.byref(c), ctypes.byref(m), br, ctypes.byref(out)) == ccl.CCL_E_INVALID
+    m = ccl.make_mapper(ccl.NEIGHBORHOOD, (-1, 0))
+    assert L.ccl_region_of(ctypes.byref(c), ctypes.byref(m), br, ctypes.byref(out)) == ccl.CCL_E_INVALID
+
+
+def _fake_buffers(chunks, regions, base=0x10000000, pitch_align=64):
+    arr = (ccl.ccl_chunk_buffer * len(chunks))()
+    for k, reg in enumerate(regions):
+        off, rng = reg
+        b = arr[k]
+        b.base = base + k * (1 << 30)
+        b.region = ccl.make_subrange(off, rng)
+        p = (rng[-1] + pitch_align - 1) // pitch_align * pitch_align
+        if len(rng) == 2:
+            b.pitch[0], b.pitch[1] = p, 1
+        else:
+            b.pitch[0], b.pitch[1], b.pitch[2] = p * rng[1], p, 1
+    return arr
+
+
+def test_wave_step_validation_no_launch():
+    """Every failure below is detected on the host before any launch (the
+    buffer addresses are never dereferenced)."""
+    shape = (64, 32)
+    chunks = ccl.ccl_split_range((0, 0), shape, 4)
+    L = ccl.lib()
+
+    def call(p, u_prev, u_cur, w_prev=None, w_cur=None, n=10, chunks=chunks):
+        return L.ccl_wave_step(ctypes.byref(p), len(chunks), chunks, u_prev, u_cur, w_prev,
+                               w_cur, n, None)
+
+    regs1 = [ccl.ccl_region_of(c, ccl.NEIGHBORHOOD, (1, 1), shape).box() for c in chunks]
+    regs0 = [c.box() for c in chunks]
+    good = ccl.make_wave_params(2, 0.25, 1)
+    # bad params
+    for p in (ccl.make_wave_params(4, 0.25), ccl.make_wave_params(2, -1.0),
+              ccl.make_wave_params(2, 0.25, 0), ccl.make_wave_params(2, 0.25, 9),
+              ccl.make_wave_params(2, float("nan"))):
+        assert call(p, _fake_buffers(chunks, regs1), _fake_buffers(chunks, regs1)) == ccl.CCL_E_INVALID
+    assert call(good, _fake_buffers(chunks, regs1), _fake_buffers(chunks, regs1), n=-1) == ccl.CCL_E_INVALID
+    # u^n region without its halo
+    assert call(good, _fake_buffers(chunks, regs1), _fake_buffers(chunks, regs0)) == ccl.CCL_E_RANGE
+    assert "halo" in ccl.ccl_last_error()
+    # T=1 rotates u_prev into the u^n role: one_to_one u_prev fails from step 2 on
+    assert call(good, _fake_buffers(chunks, regs0), _fake_buffers(chunks, regs1)) == ccl.CCL_E_RANGE
+    # T>1 without the second buffer pair
+    p4 = ccl.make_wave_params(2, 0.25, 4)
+    regs4 = [ccl.ccl_region_of(c, ccl.NEIGHBORHOOD, (4, 4), shape).box() for c in chunks]
+    assert call(p4, _fake_buffers(chunks, regs4), _fake_buffers(chunks, regs4)) == ccl.CCL_E_INVALID
+    # misaligned base
+    bad = _fake_buffers(chunks, regs1)
+    bad[0].base = bad[0].base + 4
+    assert call(good, bad, _fake_buffers(chunks, regs1)) == ccl.CCL_E_INVALID
+    # pitch not a multiple of 4
+    bad = _fake_buffers(chunks, regs1)
+    bad[1].pitch[0] = 34
+    assert call(good, bad, _fake_buffers(chunks, regs1)) == ccl.CCL_E_INVALID
+    # overlapping chunks
+    ov = ccl.ccl_split_range((0, 0), shape, 4)
+    ov[1].offset[0] -= 1
+    ov[1].range[0] += 1
+    assert call(good, _fake_buffers(chunks, regs1), _fake_buffers(chunks, regs1),
+                chunks=ov) == ccl.CCL_E_RANGE
+    # 3D with T > 1 is not available
+    c3 = ccl.ccl_split_range((0, 0, 0), (8, 8, 8), 1)
+    p3 = ccl.make_wave_params(3, 0.1, 2)
+    r3 = [c3[0].box()]
+    assert call(p3, _fake_buffers(c3, r3), _fake_buffers(c3, r3), chunks=c3) == ccl.CCL_E_UNSUPPORTED
+    # zero steps is a no-op that succeeds without touching memory
+    assert call(good, _fake_buffers(chunks, regs1), _fake_buffers(chunks, regs1), n=0) == ccl.CCL_OK
+
+
+def test_halo_exchange_validation_no_launch():
+    shape = (32, 16)
+    chunks = ccl.ccl_split_range((0, 0), shape, 2)
+    L = ccl.lib()
+    m = ccl.make_mapper(ccl.NEIGHBORHOOD, (2, 2))
+    small = _fake_buffers(chunks, [c.box() for c in chunks])
+    assert L.ccl_halo_exchange(2, chunks, ctypes.byref(m), small, 4, None) == ccl.CCL_E_RANGE
+    regs = [ccl.ccl_region_of(c, ccl.NEIGHBORHOOD, (2, 2), shape).box() for c in chunks]
+    assert L.ccl_halo_exchange(2, chunks, ctypes.byref(m), _fake_buffers(chunks, regs), 3,
+                               None) == ccl.CCL_E_INVALID
+
+
+def test_saxpy_validation_no_launch():
+    L = ccl.lib()
+    assert L.ccl_saxpy(-1, 1.0, None, None, None, None) == ccl.CCL_E_INVALID
+    assert L.ccl_saxpy(0, 1.0, None, None, None, None) == ccl.CCL_OK
+    assert L.ccl_saxpy(16, 1.0, ctypes.c_void_p(0x1004), ctypes.c_void_p(0x2000),
+                       ctypes.c_void_p(0x3000), None) == ccl.CCL_E_INVALID
+
+
+def test_fake_energy_backend():
+    code = ("import time, paper_2505_06022_amd as c; a,_=c.ccl_energy_read(0); time.sleep(0.2); "
+            "b,_=c.ccl_energy_read(0); print(c.ccl_energy_backend(0), b-a)")
+    env = dict(os.environ, CCL_ENERGY_BACKEND="fake", PYTHONPATH=ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                       timeout=120)
+    assert r.returncode == 0, r.stderr
+    name, delta = r.stdout.split()
+    assert name == "fake"
+    assert 0.2 * 250 * 0.9 <= float(delta) <= 0.2 * 250 * 3  # 250 W scripted
