@@ -46,9 +46,10 @@ def load_traffic(depth: int):
     return doc.get("bytes_per_launch")
 
 
-def cpu_baseline(w, seconds_hint: float = 15.0):
+def cpu_baseline(w, seconds: float = 15.0):
     """The float32 oracle on the host cores over a bounded sample of the
-    workload: the full 8192 x 8192 share for a few steps."""
+    workload: the full 8192 x 8192 share for as many of its steps as fit in
+    about `seconds` (sized from a 5-step probe run)."""
     import numpy as np
 
     import oracle
@@ -56,17 +57,17 @@ def cpu_baseline(w, seconds_hint: float = 15.0):
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or oracle.max_threads()
     u0 = synth.gaussian_field(w["shape"], w["sigma"], w["seed"])
     t0 = time.perf_counter()
-    oracle.wave(u0.copy(), u0, w["r2"], 1, threads=threads)
-    one = max(time.perf_counter() - t0, 1e-3)
-    steps = int(max(2, min(200, seconds_hint / one)))
+    oracle.wave(u0.copy(), u0, w["r2"], 5, threads=threads)
+    per_step = max((time.perf_counter() - t0) / 5, 1e-4)
+    steps = int(max(5, min(w["steps"], seconds / per_step)))
     t0 = time.perf_counter()
     oracle.wave(u0.copy(), u0, w["r2"], steps, threads=threads)
     dt = time.perf_counter() - t0
     cells = int(np.prod(w["shape"]))
-    return {"value": cells * steps / dt / 1e6, "unit": "Mcells/s", "cores": threads,
+    return {"value": round(cells * steps / dt / 1e6, 1), "unit": "Mcells/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"float32 oracle, {w['shape'][0]}x{w['shape'][1]} share, {steps} steps "
-                      f"(of the workload's {w['steps']}), {dt:.1f} s"}
+            "sample": f"float32 oracle, {w['shape'][0]}x{w['shape'][1]} share, {steps} of the "
+                      f"workload's {w['steps']} steps, {dt:.1f} s on {threads} host threads"}
 
 
 def saxpy_calibration(n: int = 1 << 28, reps: int = 10):

@@ -238,6 +238,48 @@ const char *ccl_energy_backend(int32_t device);
 ccl_status ccl_saxpy(int64_t n, float a, const float *x, const float *y,
                      float *z, void *hip_stream);
 
+/* ---- Batched grids ------------------------------------------------------
+ * Many independent 2D grids (each its own domain, Dirichlet zero outside)
+ * advanced by one persistent kernel launch, captured once in a HIP graph so
+ * that a run is a single graph launch.  Each grid uses the same per-cell
+ * expression as ccl_wave_step, so its result is bitwise equal to stepping
+ * it alone. */
+typedef struct {
+  int64_t ny, nx;          /* rows, columns                                 */
+  int64_t pitch;           /* elements between rows: >= nx, multiple of 4   */
+  int32_t steps;           /* leapfrog steps to take, >= 0                  */
+  int32_t temporal_depth;  /* T in 1..8 steps per pass over the grid        */
+  int32_t tile_rows;       /* rows per tile, >= T; 0 = automatic           */
+  float r2;                /* (c dt / dx)^2                                 */
+  float *buf[4];           /* device buffers of ny*pitch floats, 16-byte
+                              aligned: buf[0] = u^{-1}, buf[1] = u^0 on
+                              entry; buf[2], buf[3] are the second pair     */
+} ccl_batch_grid;
+
+typedef struct ccl_batch ccl_batch;  /* opaque */
+
+#define CCL_BATCH_NO_GRAPH 1  /* ccl_batch_run launches kernels directly */
+
+/* Plans a batch: tile tables, progress counters and the captured graph
+ * (library-owned device memory, released by ccl_batch_destroy).  The grid
+ * buffers stay caller-owned and must outlive the batch.
+ * Errors: INVALID, RANGE, NOMEM, HIP. */
+ccl_status ccl_batch_create(int32_t ngrids, const ccl_batch_grid *grids, int32_t flags,
+                            ccl_batch **out);
+/* Enqueues one run on `hip_stream`: every grid advances its `steps` from
+ * buf[0], buf[1]; a run always starts from that pair.  Errors: INVALID, HIP. */
+ccl_status ccl_batch_run(ccl_batch *b, void *hip_stream);
+/* Synchronises `hip_stream` and reports TIMEOUT if, during the last run, a
+ * tile's wait for its neighbours passed the wait limit (its results are then
+ * incomplete).  Errors: INVALID, HIP, TIMEOUT. */
+ccl_status ccl_batch_check(ccl_batch *b, void *hip_stream);
+/* Wait limit of the dependency waits, in microseconds (default 10 s). */
+ccl_status ccl_batch_set_wait_limit(ccl_batch *b, int64_t microseconds);
+/* Which buffers hold u^{steps-1} and u^{steps} of `grid` after a run. */
+ccl_status ccl_batch_result(const ccl_batch *b, int32_t grid, int32_t *prev_buf,
+                            int32_t *cur_buf);
+ccl_status ccl_batch_destroy(ccl_batch *b);
+
 /* Kernel launch timing, for measurement.  While enabled, every launch of
  * the kernel families below is bracketed by HIP events recorded on the
  * stream it is launched on.  ccl_timing_enable(on) discards earlier records
@@ -245,10 +287,11 @@ ccl_status ccl_saxpy(int64_t n, float a, const float *x, const float *y,
  * events of one family and returns their count and summed duration (ms).
  * Errors: INVALID, HIP. */
 enum {
-  CCL_KERNEL_STENCIL = 0,  /* the wave-stencil kernels (2D and 3D)          */
+  CCL_KERNEL_STENCIL = 0,  /* the wave-stencil kernels (2D, 3D, batched)    */
   CCL_KERNEL_HALO = 1,     /* halo exchange / pack / unpack copies          */
   CCL_KERNEL_SAXPY = 2,
-  CCL_KERNEL_KINDS = 3
+  CCL_KERNEL_BATCH = 3,    /* whole batched runs (one graph launch each)    */
+  CCL_KERNEL_KINDS = 4
 };
 ccl_status ccl_timing_enable(int32_t on);
 ccl_status ccl_timing_query(int32_t kernel, int64_t *launches, double *total_ms);

@@ -69,6 +69,16 @@ class ccl_wave_params(ctypes.Structure):
                 ("flags", ctypes.c_int32)]
 
 
+class ccl_batch_grid(ctypes.Structure):
+    _fields_ = [("ny", ctypes.c_int64), ("nx", ctypes.c_int64), ("pitch", ctypes.c_int64),
+                ("steps", ctypes.c_int32), ("temporal_depth", ctypes.c_int32),
+                ("tile_rows", ctypes.c_int32), ("r2", ctypes.c_float),
+                ("buf", ctypes.c_void_p * 4)]
+
+
+CCL_BATCH_NO_GRAPH = 1
+
+
 class CclError(RuntimeError):
     def __init__(self, fn: str, status: int, message: str):
         super().__init__(f"{fn} failed with status {status}: {message}")
@@ -105,12 +115,20 @@ _SIGS = {
     "ccl_energy_backend": (ctypes.c_char_p, [ctypes.c_int32]),
     "ccl_saxpy": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_float, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "ccl_batch_create": (ctypes.c_int32, [ctypes.c_int32, _P(ccl_batch_grid), ctypes.c_int32,
+                                          _P(ctypes.c_void_p)]),
+    "ccl_batch_run": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "ccl_batch_check": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "ccl_batch_set_wait_limit": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64]),
+    "ccl_batch_result": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_int32),
+                                          _P(ctypes.c_int32)]),
+    "ccl_batch_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
     "ccl_timing_enable": (ctypes.c_int32, [ctypes.c_int32]),
     "ccl_timing_query": (ctypes.c_int32, [ctypes.c_int32, _P(ctypes.c_int64),
                                           _P(ctypes.c_double)]),
 }
 
-CCL_KERNEL_STENCIL, CCL_KERNEL_HALO, CCL_KERNEL_SAXPY = 0, 1, 2
+CCL_KERNEL_STENCIL, CCL_KERNEL_HALO, CCL_KERNEL_SAXPY, CCL_KERNEL_BATCH = 0, 1, 2, 3
 
 _lib = None
 
@@ -272,3 +290,35 @@ def ccl_timing_query(kernel: int):
     _check("ccl_timing_query", lib().ccl_timing_query(int(kernel), ctypes.byref(n),
                                                       ctypes.byref(ms)))
     return n.value, ms.value
+
+
+def ccl_batch_create(grids, flags: int = 0) -> ctypes.c_void_p:
+    arr = (ccl_batch_grid * len(grids))(*grids)
+    h = ctypes.c_void_p()
+    _check("ccl_batch_create", lib().ccl_batch_create(len(grids), arr, int(flags),
+                                                      ctypes.byref(h)))
+    return h
+
+
+def ccl_batch_run(h, stream=None):
+    _check("ccl_batch_run", lib().ccl_batch_run(h, _stream(stream)))
+
+
+def ccl_batch_check(h, stream=None):
+    _check("ccl_batch_check", lib().ccl_batch_check(h, _stream(stream)))
+
+
+def ccl_batch_set_wait_limit(h, microseconds: int):
+    _check("ccl_batch_set_wait_limit", lib().ccl_batch_set_wait_limit(h, int(microseconds)))
+
+
+def ccl_batch_result(h, grid: int):
+    p = ctypes.c_int32(0)
+    c = ctypes.c_int32(0)
+    _check("ccl_batch_result", lib().ccl_batch_result(h, int(grid), ctypes.byref(p),
+                                                      ctypes.byref(c)))
+    return p.value, c.value
+
+
+def ccl_batch_destroy(h):
+    _check("ccl_batch_destroy", lib().ccl_batch_destroy(h))

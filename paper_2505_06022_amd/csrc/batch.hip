@@ -1,0 +1,438 @@
+// Many independent 2D grids stepped by one persistent launch, captured in a
+// HIP graph.
+//
+// Every grid is cut into the same 2D tiles as the chunked launch (a strip of
+// 256 columns by a segment of rows, processed by one wave with the code in
+// wave2d_tile.h) and advanced in blocks of T steps, double-buffered: block b
+// reads buffer pair b%2 and writes the other.  A tile's block b may start
+// once the 3x3 tiles around it (itself included) have finished block b-1:
+// that covers both the halo it reads (T <= segment rows, A <= strip width)
+// and the cells of pair (b+1)%2 it overwrites, which those tiles read during
+// block b-1.  Each tile keeps a progress counter (blocks done), released
+// after its stores; waiters acquire it before reading.
+//
+// Work order: a single queue holds all (block, grid, tile) items sorted by
+// block, then grid, then tile.  Waves pop items with an atomic counter.  An
+// item of block b depends only on items of block b-1, all of which sit
+// earlier in the queue and were popped by waves that are running, so every
+// wait ends without any assumption about how many waves are resident.  A
+// wait also ends after a time limit (an error flag is raised and all waves
+// drain the queue without computing), so the launch always completes.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "ccl_internal.h"
+#include "wave2d_tile.h"
+
+namespace ccl {
+namespace {
+
+constexpr int kWavesPerBlock = 4;
+constexpr int kThreads = 64 * kWavesPerBlock;
+
+struct GridDev {
+  float *buf[4];
+  int32_t ny, nx, pitch;
+  int32_t T, last_T, A;
+  int32_t tile_rows, nstrips, nsegs, nblocks;
+  int32_t counter_base;
+  float r2;
+};
+
+struct BatchTables {
+  const GridDev *grids;          // sorted by nblocks, descending
+  const int32_t *prefix_tiles;   // [ngrids + 1] over the sorted grids
+  const int32_t *level_start;    // [max_blocks + 1] queue index of block b's first item
+  const int32_t *active;         // [max_blocks] grids with nblocks > b (a prefix)
+  int32_t *counters;             // per tile: blocks completed
+  int32_t *ctl;                  // [0] queue head, [1] error flag
+  const int64_t *wait_ticks;     // wall-clock ticks a wait may last
+  int32_t total;
+  int32_t max_blocks;
+  int32_t ncounters;
+};
+
+__global__ __launch_bounds__(256) void batch_reset_kernel(int32_t *counters, int32_t n,
+                                                          int32_t *ctl) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) counters[i] = 0;
+  if (i < 2) ctl[i] = 0;
+}
+
+__device__ __forceinline__ int upper_index(const int32_t *a, int n, int32_t v) {
+  // largest i in [0, n) with a[i] <= v (a ascending, a[0] <= v)
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a[mid] <= v)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int32_t load_acquire(const int32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits until counters[idx] >= want.  Returns false if the batch's error
+// flag is (or gets) raised, or the wait limit passes (then raises it).
+__device__ bool wait_for(const BatchTables &t, int idx, int32_t want, uint64_t t0,
+                         int64_t limit) {
+  while (load_acquire(&t.counters[idx]) < want) {
+    if (load_acquire(&t.ctl[1]) != 0) return false;
+    if (static_cast<int64_t>(wall_clock64() - t0) > limit) {
+      __hip_atomic_store(&t.ctl[1], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return true;
+}
+
+// Runs tile<tb> for the block's depth tb (<= TMAX, the largest depth of any
+// grid in the batch, which bounds the registers the kernel needs).
+template <int TMAX, int T = 1>
+__device__ __forceinline__ void dispatch_depth(int tb, const w2::Chunk &C, const w2::Domain &D,
+                                               float r2, int tile_rows, int seg, int strip,
+                                               int lane, int A) {
+  if (tb == T || T == TMAX) {
+    w2::tile<T, false>(C, D, r2, tile_rows, seg, strip, lane, A);
+  } else if constexpr (T < TMAX) {
+    dispatch_depth<TMAX, T + 1>(tb, C, D, r2, tile_rows, seg, strip, lane, A);
+  }
+}
+
+template <int TMAX>
+__global__ __launch_bounds__(kThreads) void batch_kernel(const BatchTables t) {
+  const int lane = threadIdx.x & 63;
+  const int64_t limit = *t.wait_ticks;
+  for (;;) {
+    int32_t q = 0;
+    if (lane == 0) q = __hip_atomic_fetch_add(&t.ctl[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    q = __builtin_amdgcn_readfirstlane(q);
+    if (q >= t.total) break;
+    const int b = upper_index(t.level_start, t.max_blocks, q);
+    const int32_t local = q - t.level_start[b];
+    const int g = upper_index(t.prefix_tiles, t.active[b], local);
+    const GridDev G = t.grids[g];
+    const int tl = local - t.prefix_tiles[g];
+    const int seg = tl / G.nstrips;
+    const int strip = tl - seg * G.nstrips;
+
+    bool ok = load_acquire(&t.ctl[1]) == 0;
+    if (ok && b > 0) {
+      const uint64_t t0 = wall_clock64();
+      for (int ds = -1; ds <= 1 && ok; ++ds) {
+        const int s2 = seg + ds;
+        if (s2 < 0 || s2 >= G.nsegs) continue;
+        for (int dx = -1; dx <= 1 && ok; ++dx) {
+          const int x2 = strip + dx;
+          if (x2 < 0 || x2 >= G.nstrips) continue;
+          ok = wait_for(t, G.counter_base + s2 * G.nstrips + x2, b, t0, limit);
+        }
+      }
+    }
+    if (!ok) continue;  // error raised: drain the queue without computing
+
+    const int set = b & 1;
+    w2::Chunk C;
+    C.in_prev = G.buf[2 * set];
+    C.in_cur = G.buf[2 * set + 1];
+    C.out_prev = G.buf[2 * (1 - set)];
+    C.out_cur = G.buf[2 * (1 - set) + 1];
+    C.ip_y0 = C.ic_y0 = C.op_y0 = C.oc_y0 = 0;
+    C.ip_x0 = C.ic_x0 = C.op_x0 = C.oc_x0 = 0;
+    C.ip_pitch = C.ic_pitch = C.op_pitch = C.oc_pitch = G.pitch;
+    C.lp_y0 = C.lc_y0 = C.cy0 = 0;
+    C.lp_y1 = C.lc_y1 = C.cy1 = G.ny;
+    C.lp_x0 = C.lc_x0 = C.cx0 = 0;
+    C.lp_x1 = C.lc_x1 = C.cx1 = G.nx;
+    C.xs0 = -G.A;
+    C.nstrips = G.nstrips;
+    C.tile_begin = 0;
+    const w2::Domain D{0, G.ny, 0, G.nx};
+    const int tb = (b == G.nblocks - 1) ? G.last_T : G.T;
+    dispatch_depth<TMAX>(tb, C, D, G.r2, G.tile_rows, seg, strip, lane, G.A);
+    // publish: every lane's stores complete and visible device-wide, then
+    // the counter moves to b+1
+    __threadfence();
+    if (lane == 0)
+      __hip_atomic_store(&t.counters[G.counter_base + tl], b + 1, __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <int TMAX>
+const void *batch_kernel_ptr() {
+  return reinterpret_cast<const void *>(&batch_kernel<TMAX>);
+}
+
+}  // namespace
+
+struct BatchImpl {
+  int32_t ngrids = 0;
+  int32_t tmax = 1;
+  int32_t flags = 0;
+  std::vector<ccl_batch_grid> grids;  // caller order
+  std::vector<int32_t> nblocks;       // caller order
+  void *dev = nullptr;                // one allocation for all tables
+  BatchTables tables{};
+  int blocks = 0;                     // persistent grid size
+  int counter_blocks = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t *wait_ticks_dev = nullptr;
+};
+
+static ccl_status enqueue_batch(BatchImpl *B, hipStream_t s) {
+  const BatchTables &t = B->tables;
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(B->counter_blocks), dim3(256), 0, s, t.counters,
+                     t.ncounters, t.ctl);
+  ccl_status st = hip_check(hipGetLastError(), "batch_reset_kernel launch");
+  if (st != CCL_OK) return st;
+  TimedLaunch tl(CCL_KERNEL_STENCIL, s);
+  switch (B->tmax) {
+    case 1: hipLaunchKernelGGL(batch_kernel<1>, dim3(B->blocks), dim3(kThreads), 0, s, t); break;
+    case 2: hipLaunchKernelGGL(batch_kernel<2>, dim3(B->blocks), dim3(kThreads), 0, s, t); break;
+    case 4: hipLaunchKernelGGL(batch_kernel<4>, dim3(B->blocks), dim3(kThreads), 0, s, t); break;
+    default: hipLaunchKernelGGL(batch_kernel<8>, dim3(B->blocks), dim3(kThreads), 0, s, t); break;
+  }
+  return hip_check(hipGetLastError(), "batch_kernel launch");
+}
+
+static void release(BatchImpl *B) {
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
+  if (B->dev) (void)hipFree(B->dev);
+  delete B;
+}
+
+}  // namespace ccl
+
+using namespace ccl;
+
+struct ccl_batch {
+  BatchImpl *impl;
+};
+
+extern "C" ccl_status ccl_batch_create(int32_t ngrids, const ccl_batch_grid *grids,
+                                       int32_t flags, ccl_batch **out) {
+  clear_error();
+  if (!out || (ngrids > 0 && !grids)) return fail(CCL_E_INVALID, "NULL argument");
+  if (ngrids < 1) return fail(CCL_E_INVALID, "ngrids=%d < 1", ngrids);
+  if ((flags & ~CCL_BATCH_NO_GRAPH) != 0) return fail(CCL_E_INVALID, "unknown flags");
+  std::vector<GridDev> gd(ngrids);
+  std::vector<int32_t> nblk(ngrids);
+  int tmax = 1;
+  int64_t counters = 0;
+  for (int g = 0; g < ngrids; ++g) {
+    const ccl_batch_grid &G = grids[g];
+    if (G.ny < 1 || G.nx < 1 || G.ny > (1 << 30) || G.nx > (1 << 30))
+      return fail(CCL_E_INVALID, "grid %d: extents out of range", g);
+    if (G.pitch < G.nx || (G.pitch % 4) != 0 || G.pitch > (int64_t(1) << 31) / 2)
+      return fail(CCL_E_INVALID, "grid %d: pitch must be >= nx and a multiple of 4", g);
+    if (G.steps < 0) return fail(CCL_E_INVALID, "grid %d: steps < 0", g);
+    if (G.temporal_depth < 1 || G.temporal_depth > CCL_MAX_DEPTH)
+      return fail(CCL_E_INVALID, "grid %d: temporal depth %d not in 1..8", g, G.temporal_depth);
+    if (!std::isfinite(G.r2) || G.r2 < 0.0f) return fail(CCL_E_INVALID, "grid %d: bad r2", g);
+    if (G.tile_rows != 0 && G.tile_rows < G.temporal_depth)
+      return fail(CCL_E_INVALID, "grid %d: tile_rows must be >= T", g);
+    for (int k = 0; k < 4; ++k)
+      if (!G.buf[k] || (reinterpret_cast<uintptr_t>(G.buf[k]) & 15u) != 0)
+        return fail(CCL_E_INVALID, "grid %d: buf[%d] NULL or not 16-byte aligned", g, k);
+    GridDev &D = gd[g];
+    for (int k = 0; k < 4; ++k) D.buf[k] = G.buf[k];
+    D.ny = static_cast<int32_t>(G.ny);
+    D.nx = static_cast<int32_t>(G.nx);
+    D.pitch = static_cast<int32_t>(G.pitch);
+    D.T = G.temporal_depth;
+    D.A = w2::overlap(D.T);
+    D.tile_rows = G.tile_rows > 0 ? G.tile_rows : std::max(32, 16 * D.T);
+    D.nstrips = static_cast<int32_t>((G.nx + w2::strip_width(D.T) - 1) / w2::strip_width(D.T));
+    D.nsegs = static_cast<int32_t>((G.ny + D.tile_rows - 1) / D.tile_rows);
+    D.nblocks = (G.steps + D.T - 1) / D.T;
+    D.last_T = G.steps - D.T * (D.nblocks > 0 ? D.nblocks - 1 : 0);
+    D.r2 = G.r2;
+    D.counter_base = static_cast<int32_t>(counters);
+    counters += static_cast<int64_t>(D.nstrips) * D.nsegs;
+    if (counters > INT32_MAX / 4) return fail(CCL_E_RANGE, "too many tiles");
+    nblk[g] = D.nblocks;
+    tmax = std::max(tmax, D.T);
+  }
+  tmax = tmax <= 1 ? 1 : tmax <= 2 ? 2 : tmax <= 4 ? 4 : 8;
+  // sort by number of blocks, descending (stable): the grids active at any
+  // block are then a prefix of the sorted list
+  std::vector<int> order(ngrids);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return gd[a].nblocks > gd[b].nblocks; });
+  std::vector<GridDev> sorted(ngrids);
+  std::vector<int32_t> prefix(ngrids + 1, 0);
+  for (int i = 0; i < ngrids; ++i) {
+    sorted[i] = gd[order[i]];
+    prefix[i + 1] = prefix[i] + sorted[i].nstrips * sorted[i].nsegs;
+  }
+  const int32_t max_blocks = sorted[0].nblocks;
+  std::vector<int32_t> active(std::max(1, max_blocks), 0), level(max_blocks + 1, 0);
+  int64_t total = 0;
+  for (int b = 0; b < max_blocks; ++b) {
+    int a = 0;
+    while (a < ngrids && sorted[a].nblocks > b) ++a;
+    active[b] = a;
+    level[b] = static_cast<int32_t>(total);
+    total += prefix[a];
+    if (total > INT32_MAX / 2) return fail(CCL_E_RANGE, "batch queue too long");
+  }
+  level[max_blocks] = static_cast<int32_t>(total);
+
+  BatchImpl *B = new BatchImpl();
+  B->ngrids = ngrids;
+  B->tmax = tmax;
+  B->flags = flags;
+  B->grids.assign(grids, grids + ngrids);
+  B->nblocks = nblk;
+  // device layout: grids | prefix | level | active | counters | ctl | wait_ticks
+  auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+  const size_t o_grids = 0;
+  const size_t o_prefix = al(o_grids + sizeof(GridDev) * ngrids);
+  const size_t o_level = al(o_prefix + sizeof(int32_t) * (ngrids + 1));
+  const size_t o_active = al(o_level + sizeof(int32_t) * (max_blocks + 1));
+  const size_t o_count = al(o_active + sizeof(int32_t) * active.size());
+  const size_t o_ctl = al(o_count + sizeof(int32_t) * std::max<int64_t>(counters, 1));
+  const size_t o_wait = al(o_ctl + sizeof(int32_t) * 2);
+  const size_t bytes = al(o_wait + sizeof(int64_t));
+  ccl_status st = hip_check(hipMalloc(&B->dev, bytes), "hipMalloc(batch tables)");
+  if (st != CCL_OK) {
+    delete B;
+    return st == CCL_E_HIP ? fail(CCL_E_NOMEM, "batch tables: %s", ccl_last_error()) : st;
+  }
+  char *d = static_cast<char *>(B->dev);
+  const int64_t wait_ticks = int64_t(100000000) * 10;  // 10 s of the 100 MHz wall clock
+  hipError_t e = hipSuccess;
+  e = e ? e : hipMemcpy(d + o_grids, sorted.data(), sizeof(GridDev) * ngrids, hipMemcpyHostToDevice);
+  e = e ? e : hipMemcpy(d + o_prefix, prefix.data(), sizeof(int32_t) * (ngrids + 1), hipMemcpyHostToDevice);
+  e = e ? e : hipMemcpy(d + o_level, level.data(), sizeof(int32_t) * (max_blocks + 1), hipMemcpyHostToDevice);
+  e = e ? e : hipMemcpy(d + o_active, active.data(), sizeof(int32_t) * active.size(), hipMemcpyHostToDevice);
+  e = e ? e : hipMemcpy(d + o_wait, &wait_ticks, sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    release(B);
+    return hip_check(e, "hipMemcpy(batch tables)");
+  }
+  BatchTables &t = B->tables;
+  t.grids = reinterpret_cast<const GridDev *>(d + o_grids);
+  t.prefix_tiles = reinterpret_cast<const int32_t *>(d + o_prefix);
+  t.level_start = reinterpret_cast<const int32_t *>(d + o_level);
+  t.active = reinterpret_cast<const int32_t *>(d + o_active);
+  t.counters = reinterpret_cast<int32_t *>(d + o_count);
+  t.ctl = reinterpret_cast<int32_t *>(d + o_ctl);
+  t.wait_ticks = reinterpret_cast<const int64_t *>(d + o_wait);
+  B->wait_ticks_dev = reinterpret_cast<int64_t *>(d + o_wait);
+  t.total = static_cast<int32_t>(total);
+  t.max_blocks = max_blocks;
+  t.ncounters = static_cast<int32_t>(counters);
+  B->counter_blocks = static_cast<int>((std::max<int64_t>(counters, 2) + 255) / 256);
+
+  // persistent grid: as many blocks as fit on the device at once
+  int dev = 0, cus = 0, per_cu = 0;
+  e = hipGetDevice(&dev);
+  e = e ? e : hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const void *kfn = tmax == 1   ? batch_kernel_ptr<1>()
+                    : tmax == 2 ? batch_kernel_ptr<2>()
+                    : tmax == 4 ? batch_kernel_ptr<4>()
+                                : batch_kernel_ptr<8>();
+  e = e ? e : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, kThreads, 0);
+  if (e != hipSuccess) {
+    release(B);
+    return hip_check(e, "occupancy query");
+  }
+  B->blocks = std::max(1, cus * std::max(1, per_cu));
+  if (total == 0) B->blocks = 1;
+
+  if (!(flags & CCL_BATCH_NO_GRAPH)) {
+    e = hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking);
+    e = e ? e : hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      release(B);
+      return hip_check(e, "graph capture start");
+    }
+    st = enqueue_batch(B, B->cap_stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(B->cap_stream, &graph);
+    B->graph = graph;
+    if (st != CCL_OK || e != hipSuccess) {
+      release(B);
+      return st != CCL_OK ? st : hip_check(e, "graph capture end");
+    }
+    e = hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      release(B);
+      return hip_check(e, "hipGraphInstantiate");
+    }
+  }
+  ccl_batch *h = new ccl_batch{B};
+  *out = h;
+  return CCL_OK;
+}
+
+extern "C" ccl_status ccl_batch_run(ccl_batch *b, void *hip_stream) {
+  clear_error();
+  if (!b || !b->impl) return fail(CCL_E_INVALID, "NULL batch");
+  BatchImpl *B = b->impl;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (B->exec) {
+    TimedLaunch tl(CCL_KERNEL_BATCH, s);
+    return hip_check(hipGraphLaunch(B->exec, s), "hipGraphLaunch");
+  }
+  return enqueue_batch(B, s);
+}
+
+extern "C" ccl_status ccl_batch_check(ccl_batch *b, void *hip_stream) {
+  clear_error();
+  if (!b || !b->impl) return fail(CCL_E_INVALID, "NULL batch");
+  BatchImpl *B = b->impl;
+  ccl_status st = hip_check(hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)),
+                            "hipStreamSynchronize");
+  if (st != CCL_OK) return st;
+  int32_t ctl[2] = {0, 0};
+  st = hip_check(hipMemcpy(ctl, B->tables.ctl, sizeof(ctl), hipMemcpyDeviceToHost),
+                 "hipMemcpy(batch status)");
+  if (st != CCL_OK) return st;
+  if (ctl[1] != 0) return fail(CCL_E_TIMEOUT, "a tile's dependency wait passed its limit");
+  return CCL_OK;
+}
+
+extern "C" ccl_status ccl_batch_set_wait_limit(ccl_batch *b, int64_t microseconds) {
+  clear_error();
+  if (!b || !b->impl) return fail(CCL_E_INVALID, "NULL batch");
+  if (microseconds < 0) return fail(CCL_E_INVALID, "negative wait limit");
+  const int64_t ticks = microseconds * 100;  // 100 MHz wall clock
+  return hip_check(hipMemcpy(b->impl->wait_ticks_dev, &ticks, sizeof(ticks),
+                             hipMemcpyHostToDevice),
+                   "hipMemcpy(wait limit)");
+}
+
+extern "C" ccl_status ccl_batch_result(const ccl_batch *b, int32_t grid, int32_t *prev_buf,
+                                       int32_t *cur_buf) {
+  clear_error();
+  if (!b || !b->impl || !prev_buf || !cur_buf) return fail(CCL_E_INVALID, "NULL argument");
+  if (grid < 0 || grid >= b->impl->ngrids) return fail(CCL_E_INVALID, "grid %d out of range", grid);
+  const int set = b->impl->nblocks[grid] & 1;
+  *prev_buf = 2 * set;
+  *cur_buf = 2 * set + 1;
+  return CCL_OK;
+}
+
+extern "C" ccl_status ccl_batch_destroy(ccl_batch *b) {
+  clear_error();
+  if (!b) return CCL_OK;
+  if (b->impl) release(b->impl);
+  delete b;
+  return CCL_OK;
+}

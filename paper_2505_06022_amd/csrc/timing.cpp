@@ -26,6 +26,8 @@ Timing &timing() {
 }  // namespace
 
 TimedLaunch::TimedLaunch(int kind, hipStream_t s) : kind_(kind), stream_(s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   Timing &t = timing();
   std::lock_guard<std::mutex> lock(t.mu);
   if (!t.on || kind < 0 || kind >= CCL_KERNEL_KINDS || t.rec[kind].size() >= kMaxRecords) return;

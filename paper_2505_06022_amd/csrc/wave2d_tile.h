@@ -1,0 +1,230 @@
+// Device code of one 2D wave tile, shared by the chunked launch (wave2d.hip)
+// and the batched persistent launch (batch.hip).
+//
+// Work unit: one wave (64 lanes) owns a tile = a strip of 256 columns (four
+// consecutive floats per lane, 16-byte loads) and a segment of output rows.
+// The wave streams down the rows: at iteration i it loads row i of u^n and
+// row i-1 of u^{n-1}, then computes level 2 at row i-1, level 3 at row i-2,
+// ..., level T+1 at row i-T, keeping the last three rows of every level in
+// registers.  North/south neighbours come from that register ring; west/east
+// neighbours from the adjacent lane through DPP wave shifts (no LDS, no
+// barriers).  A level-(k+1) value is only valid where its whole dependency
+// cone was loaded, so strips overlap by 4*ceil(T/4) columns on each side and
+// segments re-read T rows above and below; outputs are written only for the
+// valid interior.  Every cell value is produced by the same float32
+// expression, so results are bitwise independent of T, tiling and chunking.
+//
+// In place (T == 1 only): u^{n+1} overwrites u^{n-1}; each lane then reads
+// u^{n-1} only at the cells it writes.  Otherwise u^{n+T-1} and u^{n+T} go to
+// a second buffer pair, because neighbouring tiles still read the halo cells
+// of the inputs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ccl {
+namespace w2 {
+
+constexpr int kPrefetch = 3;
+
+// Overlap columns per side and output columns per strip for depth T.
+__host__ __device__ constexpr int overlap(int T) { return 4 * ((T + 3) / 4); }
+__host__ __device__ constexpr int strip_width(int T) { return 256 - 2 * overlap(T); }
+
+struct Chunk {
+  const float *in_prev;
+  const float *in_cur;
+  float *out_prev;
+  float *out_cur;
+  int32_t ip_y0, ip_x0, ip_pitch;
+  int32_t ic_y0, ic_x0, ic_pitch;
+  int32_t op_y0, op_x0, op_pitch;
+  int32_t oc_y0, oc_x0, oc_pitch;
+  int32_t lp_y0, lp_y1, lp_x0, lp_x1;  // loadable box of in_prev (region ∩ domain)
+  int32_t lc_y0, lc_y1, lc_x0, lc_x1;  // loadable box of in_cur
+  int32_t cy0, cy1, cx0, cx1;          // chunk (output) box
+  int32_t xs0;                         // first column of strip 0
+  int32_t nstrips;
+  int32_t tile_begin;
+};
+
+struct Domain {
+  int32_t gy0, gy1, gx0, gx1;  // zero outside
+};
+
+__device__ __forceinline__ float dpp_from_left(float v) {
+  // lane l receives lane l-1's value (wave_shr:1); lane 0 receives 0
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float dpp_from_right(float v) {
+  // lane l receives lane l+1's value (wave_shl:1); lane 63 receives 0
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+
+// One cell: s = (N + S) + (W + E); lap = s - 4C; u+ = fma(r2, lap, 2C - P).
+__device__ __forceinline__ float cell(float n, float s, float w, float e, float c, float p,
+                                      float r2) {
+  const float sum = (n + s) + (w + e);
+  const float lap = sum - 4.0f * c;
+  return fmaf(r2, lap, 2.0f * c - p);
+}
+
+__device__ __forceinline__ float4 step4(const float4 &n, const float4 &c, const float4 &s,
+                                        const float4 &p, float r2) {
+  const float left = dpp_from_left(c.w);
+  const float right = dpp_from_right(c.x);
+  float4 o;
+  o.x = cell(n.x, s.x, left, c.y, c.x, p.x, r2);
+  o.y = cell(n.y, s.y, c.x, c.z, c.y, p.y, r2);
+  o.z = cell(n.z, s.z, c.y, c.w, c.z, p.z, r2);
+  o.w = cell(n.w, s.w, c.z, right, c.w, p.w, r2);
+  return o;
+}
+
+__device__ __forceinline__ float4 zero4() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+
+// Which of the lane's four columns [xl, xl+4) lie in [x0, x1).  Columns are
+// grouped in aligned fours relative to the buffer, and a buffer's pitch is a
+// multiple of 4 that covers its extent, so a group that meets [x0, x1) is
+// always inside the allocated row.
+struct Cols {
+  bool any, m0, m1, m2, m3;
+};
+
+__device__ __forceinline__ Cols cols_of(int xl, int x0, int x1) {
+  Cols c;
+  c.m0 = xl + 0 >= x0 && xl + 0 < x1;
+  c.m1 = xl + 1 >= x0 && xl + 1 < x1;
+  c.m2 = xl + 2 >= x0 && xl + 2 < x1;
+  c.m3 = xl + 3 >= x0 && xl + 3 < x1;
+  c.any = c.m0 || c.m1 || c.m2 || c.m3;
+  return c;
+}
+
+// Loads the lane's group of `row` (zero outside the loadable box).
+__device__ __forceinline__ float4 load4(const float *base, int32_t by0, int32_t bx0,
+                                        int32_t pitch, int row, int xl, int ly0, int ly1,
+                                        const Cols &c) {
+  float4 v = zero4();
+  if (row < ly0 || row >= ly1) return v;  // wave-uniform
+  if (c.any)
+    v = *reinterpret_cast<const float4 *>(base + static_cast<int64_t>(row - by0) * pitch +
+                                          (xl - bx0));
+  v.x = c.m0 ? v.x : 0.0f;
+  v.y = c.m1 ? v.y : 0.0f;
+  v.z = c.m2 ? v.z : 0.0f;
+  v.w = c.m3 ? v.w : 0.0f;
+  return v;
+}
+
+// Stores the lane's group of `row` where the output mask allows.  Partial
+// groups occur only at a chunk's left or right edge; their other columns are
+// halo cells of this chunk's own buffer that no wave writes during the
+// launch, so they are read and written back unchanged (one 16-byte store).
+__device__ __forceinline__ void store4(float *base, int32_t by0, int32_t bx0, int32_t pitch,
+                                       int row, int xl, const Cols &c, const float4 &v) {
+  if (!c.any) return;
+  float4 *p = reinterpret_cast<float4 *>(base + static_cast<int64_t>(row - by0) * pitch +
+                                         (xl - bx0));
+  float4 w = v;
+  if (!(c.m0 && c.m1 && c.m2 && c.m3)) {
+    const float4 o = *p;
+    w.x = c.m0 ? v.x : o.x;
+    w.y = c.m1 ? v.y : o.y;
+    w.z = c.m2 ? v.z : o.z;
+    w.w = c.m3 ? v.w : o.w;
+  }
+  *p = w;
+}
+
+__device__ __forceinline__ float4 force_zero(float4 v, bool row_in, const Cols &d) {
+  v.x = (row_in && d.m0) ? v.x : 0.0f;
+  v.y = (row_in && d.m1) ? v.y : 0.0f;
+  v.z = (row_in && d.m2) ? v.z : 0.0f;
+  v.w = (row_in && d.m3) ? v.w : 0.0f;
+  return v;
+}
+
+// Advances one tile (segment `seg`, strip `strip` of chunk C) by T steps.
+// Strips are 256 columns wide and overlap their neighbours by A columns on
+// each side (A >= T, a multiple of 4); each writes SW = 256 - 2A columns.
+template <int T, bool IN_PLACE>
+__device__ __forceinline__ void tile(const Chunk &C, const Domain &D, float r2, int tile_rows,
+                                     int seg, int strip, int lane, int A) {
+  const int SW = 256 - 2 * A;
+  const int y0 = C.cy0 + seg * tile_rows;
+  const int y1 = min(C.cy1, y0 + tile_rows);
+  const int xs = C.xs0 + strip * SW;
+  const int xl = xs + 4 * lane;
+  const int vx0 = max(C.cx0, xs + A);
+  const int vx1 = min(C.cx1, xs + A + SW);
+
+  const Cols dom = cols_of(xl, D.gx0, D.gx1);
+  const Cols out = cols_of(xl, vx0, vx1);
+  const Cols lc = cols_of(xl, C.lc_x0, C.lc_x1);
+  // In place, u^{n-1} is read only where this lane writes.
+  const int lpy0 = IN_PLACE ? max(C.lp_y0, y0) : C.lp_y0;
+  const int lpy1 = IN_PLACE ? min(C.lp_y1, y1) : C.lp_y1;
+  const Cols lp = cols_of(xl, IN_PLACE ? max(C.lp_x0, vx0) : C.lp_x0,
+                          IN_PLACE ? min(C.lp_x1, vx1) : C.lp_x1);
+
+  float4 ring[T][3];
+#pragma unroll
+  for (int k = 0; k < T; ++k) ring[k][0] = ring[k][1] = ring[k][2] = zero4();
+
+  const int i0 = y0 - T;
+  const int iend = y1 + T;  // exclusive
+  float4 q1[kPrefetch], q0[kPrefetch];
+#pragma unroll
+  for (int u = 0; u < kPrefetch; ++u) {
+    q1[u] = load4(C.in_cur, C.ic_y0, C.ic_x0, C.ic_pitch, i0 + u, xl, C.lc_y0, C.lc_y1, lc);
+    q0[u] = load4(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch, i0 + u - 1, xl, lpy0, lpy1, lp);
+  }
+
+  for (int base = i0; base < iend; base += kPrefetch) {
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u) {
+      const int i = base + u;
+      const float4 v1 = q1[u];
+      const float4 v0 = q0[u];
+      q1[u] = load4(C.in_cur, C.ic_y0, C.ic_x0, C.ic_pitch, i + kPrefetch, xl, C.lc_y0, C.lc_y1,
+                    lc);
+      q0[u] = load4(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch, i + kPrefetch - 1, xl, lpy0, lpy1,
+                    lp);
+      ring[0][0] = ring[0][1];
+      ring[0][1] = ring[0][2];
+      ring[0][2] = v1;
+      float4 pv = v0;
+#pragma unroll
+      for (int k = 1; k <= T; ++k) {
+        const int r = i - k;  // row of level k+1 computed now
+        float4 nv = step4(ring[k - 1][0], ring[k - 1][1], ring[k - 1][2], pv, r2);
+        nv = force_zero(nv, r >= D.gy0 && r < D.gy1, dom);
+        if (k < T) {
+          pv = ring[k - 1][0];
+          ring[k][0] = ring[k][1];
+          ring[k][1] = ring[k][2];
+          ring[k][2] = nv;
+        } else if (r >= y0 && r < y1) {
+          store4(C.out_cur, C.oc_y0, C.oc_x0, C.oc_pitch, r, xl, out, nv);
+          if (!IN_PLACE)
+            store4(C.out_prev, C.op_y0, C.op_x0, C.op_pitch, r, xl, out, ring[T - 1][1]);
+        }
+      }
+    }
+  }
+}
+
+// Maps a block index so that consecutive logical blocks land on the same
+// XCD (blocks are dispatched to the 8 XCDs round-robin); neighbouring tiles
+// then share an L2 for the rows and columns they both read.
+__device__ __forceinline__ int xcd_block(int bid, int nblocks) {
+  const int q = nblocks >> 3, r = nblocks & 7;
+  const int xcd = bid & 7, idx = bid >> 3;
+  return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + idx;
+}
+
+}  // namespace w2
+}  // namespace ccl

@@ -10,8 +10,9 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import (NEIGHBORHOOD, ccl_chunk_buffer, ccl_region_of, ccl_split_range, ccl_wave_step,
-               make_subrange, make_wave_params)
+from . import (NEIGHBORHOOD, ccl_batch_create, ccl_batch_destroy, ccl_batch_grid,
+               ccl_batch_result, ccl_batch_run, ccl_chunk_buffer, ccl_region_of, ccl_split_range,
+               ccl_wave_step, make_subrange, make_wave_params)
 
 PITCH_ALIGN = 64  # elements; keeps every row start 256-byte aligned
 
@@ -119,3 +120,56 @@ class ChunkedWave:
     def step(self, nsteps: int, stream=None):
         ccl_wave_step(self.params, self.chunks, self.u_prev, self.u_cur, self.w_prev, self.w_cur,
                       nsteps, stream)
+
+
+class BatchedWaves:
+    """Buffers (four per grid, pitched rows) and a ccl_batch over them.
+
+    ``specs``: list of dicts with ny, nx, steps, r2, depth and optionally
+    tile_rows."""
+
+    def __init__(self, specs, device="cuda", flags=0, fill=0.0):
+        import torch
+        self.specs = [dict(s) for s in specs]
+        self.tensors = []
+        self.grids = []
+        for s in self.specs:
+            pitch = _round_up(int(s["nx"]), PITCH_ALIGN)
+            ts = [torch.full((int(s["ny"]), pitch), float(fill), dtype=torch.float32,
+                             device=device) for _ in range(4)]
+            g = ccl_batch_grid()
+            g.ny, g.nx, g.pitch = int(s["ny"]), int(s["nx"]), pitch
+            g.steps = int(s["steps"])
+            g.temporal_depth = int(s.get("depth", 1))
+            g.tile_rows = int(s.get("tile_rows", 0))
+            g.r2 = float(s["r2"])
+            for k in range(4):
+                g.buf[k] = ts[k].data_ptr()
+            self.tensors.append(ts)
+            self.grids.append(g)
+        self.handle = ccl_batch_create(self.grids, flags)
+
+    def scatter(self, g, u_prev, u_cur):
+        import torch
+        nx = self.specs[g]["nx"]
+        self.tensors[g][0][:, :nx].copy_(torch.from_numpy(np.ascontiguousarray(u_prev, np.float32)))
+        self.tensors[g][1][:, :nx].copy_(torch.from_numpy(np.ascontiguousarray(u_cur, np.float32)))
+
+    def run(self, stream=None):
+        ccl_batch_run(self.handle, stream)
+
+    def gather(self, g, which="cur"):
+        p, c = ccl_batch_result(self.handle, g)
+        nx = self.specs[g]["nx"]
+        return self.tensors[g][c if which == "cur" else p][:, :nx].cpu().numpy()
+
+    def close(self):
+        if self.handle is not None:
+            ccl_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

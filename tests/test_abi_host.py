@@ -215,3 +215,28 @@ def test_fake_energy_backend():
     name, delta = r.stdout.split()
     assert name == "fake"
     assert 0.2 * 250 * 0.9 <= float(delta) <= 0.2 * 250 * 3  # 250 W scripted
+
+
+def test_batch_create_validation_no_launch():
+    L = ccl.lib()
+    h = ctypes.c_void_p()
+    g = ccl.ccl_batch_grid()
+    g.ny, g.nx, g.pitch, g.steps, g.temporal_depth, g.r2 = 16, 16, 16, 4, 1, 0.25
+    for k in range(4):
+        g.buf[k] = 0x10000000 + k * 4096
+    arr = (ccl.ccl_batch_grid * 1)(g)
+    assert L.ccl_batch_create(0, arr, 0, ctypes.byref(h)) == ccl.CCL_E_INVALID
+    bad = ccl.ccl_batch_grid.from_buffer_copy(g)
+    bad.pitch = 18
+    assert L.ccl_batch_create(1, (ccl.ccl_batch_grid * 1)(bad), 0, ctypes.byref(h)) == ccl.CCL_E_INVALID
+    bad = ccl.ccl_batch_grid.from_buffer_copy(g)
+    bad.temporal_depth = 9
+    assert L.ccl_batch_create(1, (ccl.ccl_batch_grid * 1)(bad), 0, ctypes.byref(h)) == ccl.CCL_E_INVALID
+    bad = ccl.ccl_batch_grid.from_buffer_copy(g)
+    bad.temporal_depth, bad.tile_rows = 4, 2
+    assert L.ccl_batch_create(1, (ccl.ccl_batch_grid * 1)(bad), 0, ctypes.byref(h)) == ccl.CCL_E_INVALID
+    bad = ccl.ccl_batch_grid.from_buffer_copy(g)
+    bad.buf[2] = 0x10000004
+    assert L.ccl_batch_create(1, (ccl.ccl_batch_grid * 1)(bad), 0, ctypes.byref(h)) == ccl.CCL_E_INVALID
+    assert L.ccl_batch_create(1, arr, 8, ctypes.byref(h)) == ccl.CCL_E_INVALID
+    assert L.ccl_batch_destroy(None) == ccl.CCL_OK
