@@ -280,6 +280,80 @@ ccl_status ccl_batch_result(const ccl_batch *b, int32_t grid, int32_t *prev_buf,
                             int32_t *cur_buf);
 ccl_status ccl_batch_destroy(ccl_batch *b);
 
+/* ---- Autotuner ------------------------------------------------------------
+ * A launch configuration of ccl_wave_step for one domain shape (offset 0,
+ * split along dimension 0), and what measuring it gave. */
+typedef struct {
+  int32_t dims;             /* 2 or 3                                        */
+  int64_t shape[3];         /* domain extents, dimension 0 slowest           */
+  int32_t nchunks;          /* K device-local chunks                         */
+  int32_t temporal_depth;   /* T                                             */
+  int32_t tile_rows;        /* rows (2D) / planes (3D) per tile, 0 = auto    */
+} ccl_tune_config;
+
+typedef struct {
+  double seconds_per_step;  /* median over the timed runs                    */
+  double joules_per_step;   /* device energy per step, NaN if not measured   */
+  double window_seconds;    /* length of the energy window                   */
+  int32_t runs_in_window;
+} ccl_tune_sample;
+
+/* Measures each config: ccl_wave_step over zero-filled scratch buffers
+ * (allocated for the call and freed before it returns), one warm-up run of
+ * `steps` steps, `reps` timed runs (median kept), and — when
+ * energy_window_s > 0 and device energy is readable — repeated runs filling
+ * at least that many seconds between two ccl_energy_read calls.
+ * Synchronises `hip_stream`.  Errors: INVALID, RANGE, UNSUPPORTED, HIP. */
+ccl_status ccl_autotune_measure(int32_t n, const ccl_tune_config *cfgs, float r2,
+                                int32_t steps, int32_t reps, double energy_window_s,
+                                int32_t device, void *hip_stream, ccl_tune_sample *out);
+
+/* Cost-model features of each config (host array n x CCL_MLP_IN):
+ * log2 of the three extents (0 for the third in 2D), is-3D, log2 cells,
+ * log2 K, log2 tile rows, T, 1/T, log2(1 + halo bytes per step), modelled
+ * HBM bytes per cell-step (12 for T = 1, 16/T otherwise), log2 waves per
+ * launch.  Errors: INVALID. */
+ccl_status ccl_costmodel_features(int32_t n, const ccl_tune_config *cfgs, float *x_host);
+
+/* ---- Launch-config cost model ------------------------------------------
+ * A 12-64-64-2 float32 MLP (ReLU hidden layers) that maps the features of a
+ * launch config to predicted [log time, log energy] per cell-step
+ * (standardised by the caller).  Trained on the GPU by the library's own
+ * forward/backward kernels with L = 1/(2n) sum |y - t|^2 and Adam; gradients
+ * are summed in a fixed order, so training is deterministic.  Parameters are
+ * packed W1 (64x12), b1 (64), W2 (64x64), b2 (64), W3 (2x64), b3 (2),
+ * row-major W[out][in].  All sample arrays are device memory, row-major
+ * n x 12 (x) and n x 2 (t, y). */
+#define CCL_MLP_IN 12
+#define CCL_MLP_HIDDEN 64
+#define CCL_MLP_OUT 2
+#define CCL_MLP_NPARAMS 5122
+enum { CCL_MLP_PARAMS = 0, CCL_MLP_GRADS = 1, CCL_MLP_LOSS = 2 };
+typedef struct ccl_mlp ccl_mlp;  /* opaque: parameters, gradient, Adam state */
+
+/* Copies CCL_MLP_NPARAMS host floats into a new model.
+ * Errors: INVALID (NULL, non-finite), HIP. */
+ccl_status ccl_mlp_create(const float *params, ccl_mlp **out);
+ccl_status ccl_mlp_destroy(ccl_mlp *m);
+/* Copies parameters, the last gradient, or the last loss (1 float) to host. */
+ccl_status ccl_mlp_get(const ccl_mlp *m, int32_t what, float *host_out);
+/* y = net(x) for n samples. */
+ccl_status ccl_mlp_forward(ccl_mlp *m, int32_t n, const float *x, float *y, void *hip_stream);
+/* Gradient and loss of L over the n samples (x, t), kept in the model. */
+ccl_status ccl_mlp_grad(ccl_mlp *m, int32_t n, const float *x, const float *t,
+                        void *hip_stream);
+/* One Adam step with the kept gradient (bias-corrected; step count kept). */
+ccl_status ccl_mlp_adam(ccl_mlp *m, float lr, float beta1, float beta2, float eps,
+                        void *hip_stream);
+/* `epochs` full-batch steps of grad + Adam (beta1 0.9, beta2 0.999, eps 1e-8). */
+ccl_status ccl_mlp_train(ccl_mlp *m, int32_t n, const float *x, const float *t,
+                         int32_t epochs, float lr, void *hip_stream);
+/* Scores score_i = w_time*y_i0 + w_energy*y_i1 of n candidates and writes the
+ * index of the smallest (ties: lowest index) to *best (device int32);
+ * `scores` (device, n floats) may be NULL. */
+ccl_status ccl_mlp_pick(ccl_mlp *m, int32_t n, const float *x, float w_time, float w_energy,
+                        float *scores, int32_t *best, void *hip_stream);
+
 /* Kernel launch timing, for measurement.  While enabled, every launch of
  * the kernel families below is bracketed by HIP events recorded on the
  * stream it is launched on.  ccl_timing_enable(on) discards earlier records

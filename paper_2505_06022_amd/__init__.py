@@ -79,6 +79,20 @@ class ccl_batch_grid(ctypes.Structure):
 CCL_BATCH_NO_GRAPH = 1
 
 
+class ccl_tune_config(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32), ("shape", _I64x3), ("nchunks", ctypes.c_int32),
+                ("temporal_depth", ctypes.c_int32), ("tile_rows", ctypes.c_int32)]
+
+
+class ccl_tune_sample(ctypes.Structure):
+    _fields_ = [("seconds_per_step", ctypes.c_double), ("joules_per_step", ctypes.c_double),
+                ("window_seconds", ctypes.c_double), ("runs_in_window", ctypes.c_int32)]
+
+
+CCL_MLP_IN, CCL_MLP_HIDDEN, CCL_MLP_OUT, CCL_MLP_NPARAMS = 12, 64, 2, 5122
+CCL_MLP_PARAMS, CCL_MLP_GRADS, CCL_MLP_LOSS = 0, 1, 2
+
+
 class CclError(RuntimeError):
     def __init__(self, fn: str, status: int, message: str):
         super().__init__(f"{fn} failed with status {status}: {message}")
@@ -123,6 +137,27 @@ _SIGS = {
     "ccl_batch_result": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_int32),
                                           _P(ctypes.c_int32)]),
     "ccl_batch_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
+    "ccl_autotune_measure": (ctypes.c_int32, [ctypes.c_int32, _P(ccl_tune_config), ctypes.c_float,
+                                              ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                              ctypes.c_int32, ctypes.c_void_p,
+                                              _P(ccl_tune_sample)]),
+    "ccl_costmodel_features": (ctypes.c_int32, [ctypes.c_int32, _P(ccl_tune_config),
+                                                _P(ctypes.c_float)]),
+    "ccl_mlp_create": (ctypes.c_int32, [_P(ctypes.c_float), _P(ctypes.c_void_p)]),
+    "ccl_mlp_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
+    "ccl_mlp_get": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_float)]),
+    "ccl_mlp_forward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
+    "ccl_mlp_grad": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p]),
+    "ccl_mlp_adam": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_float, ctypes.c_float,
+                                      ctypes.c_float, ctypes.c_float, ctypes.c_void_p]),
+    "ccl_mlp_train": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_int32, ctypes.c_float,
+                                       ctypes.c_void_p]),
+    "ccl_mlp_pick": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.c_float, ctypes.c_float, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p]),
     "ccl_timing_enable": (ctypes.c_int32, [ctypes.c_int32]),
     "ccl_timing_query": (ctypes.c_int32, [ctypes.c_int32, _P(ctypes.c_int64),
                                           _P(ctypes.c_double)]),
@@ -322,3 +357,83 @@ def ccl_batch_result(h, grid: int):
 
 def ccl_batch_destroy(h):
     _check("ccl_batch_destroy", lib().ccl_batch_destroy(h))
+
+
+def make_tune_config(shape, nchunks: int, temporal_depth: int, tile_rows: int = 0):
+    c = ccl_tune_config()
+    c.dims = len(shape)
+    c.shape = _i64(shape)
+    c.nchunks, c.temporal_depth, c.tile_rows = int(nchunks), int(temporal_depth), int(tile_rows)
+    return c
+
+
+def ccl_autotune_measure(cfgs, r2: float, steps: int, reps: int = 3,
+                         energy_window_s: float = 0.0, device: int = 0, stream=None):
+    arr = (ccl_tune_config * len(cfgs))(*cfgs)
+    out = (ccl_tune_sample * len(cfgs))()
+    _check("ccl_autotune_measure",
+           lib().ccl_autotune_measure(len(cfgs), arr, float(r2), int(steps), int(reps),
+                                      float(energy_window_s), int(device), _stream(stream), out))
+    return list(out)
+
+
+def ccl_costmodel_features(cfgs):
+    import numpy as np
+    arr = (ccl_tune_config * len(cfgs))(*cfgs)
+    x = np.zeros((len(cfgs), CCL_MLP_IN), dtype=np.float32)
+    _check("ccl_costmodel_features", lib().ccl_costmodel_features(
+        len(cfgs), arr, x.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return x
+
+
+def ccl_mlp_create(params):
+    import numpy as np
+    p = np.ascontiguousarray(params, dtype=np.float32).ravel()
+    if p.size != CCL_MLP_NPARAMS:
+        raise ValueError(f"expected {CCL_MLP_NPARAMS} parameters, got {p.size}")
+    h = ctypes.c_void_p()
+    _check("ccl_mlp_create", lib().ccl_mlp_create(p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                  ctypes.byref(h)))
+    return h
+
+
+def ccl_mlp_destroy(h):
+    _check("ccl_mlp_destroy", lib().ccl_mlp_destroy(h))
+
+
+def ccl_mlp_get(h, what: int):
+    import numpy as np
+    out = np.zeros(1 if what == CCL_MLP_LOSS else CCL_MLP_NPARAMS, dtype=np.float32)
+    _check("ccl_mlp_get", lib().ccl_mlp_get(h, int(what),
+                                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return out
+
+
+def ccl_mlp_forward(h, n: int, x_ptr: int, y_ptr: int, stream=None):
+    _check("ccl_mlp_forward", lib().ccl_mlp_forward(h, int(n), ctypes.c_void_p(x_ptr),
+                                                    ctypes.c_void_p(y_ptr), _stream(stream)))
+
+
+def ccl_mlp_grad(h, n: int, x_ptr: int, t_ptr: int, stream=None):
+    _check("ccl_mlp_grad", lib().ccl_mlp_grad(h, int(n), ctypes.c_void_p(x_ptr),
+                                              ctypes.c_void_p(t_ptr), _stream(stream)))
+
+
+def ccl_mlp_adam(h, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check("ccl_mlp_adam", lib().ccl_mlp_adam(h, float(lr), float(beta1), float(beta2),
+                                              float(eps), _stream(stream)))
+
+
+def ccl_mlp_train(h, n: int, x_ptr: int, t_ptr: int, epochs: int, lr: float = 1e-3,
+                  stream=None):
+    _check("ccl_mlp_train", lib().ccl_mlp_train(h, int(n), ctypes.c_void_p(x_ptr),
+                                                ctypes.c_void_p(t_ptr), int(epochs), float(lr),
+                                                _stream(stream)))
+
+
+def ccl_mlp_pick(h, n: int, x_ptr: int, w_time: float, w_energy: float, scores_ptr: int,
+                 best_ptr: int, stream=None):
+    _check("ccl_mlp_pick", lib().ccl_mlp_pick(h, int(n), ctypes.c_void_p(x_ptr), float(w_time),
+                                              float(w_energy),
+                                              ctypes.c_void_p(scores_ptr) if scores_ptr else None,
+                                              ctypes.c_void_p(best_ptr), _stream(stream)))

@@ -1,0 +1,221 @@
+// Autotuner: measures launch configurations of the chunked stencil and
+// encodes configs as cost-model features.
+//
+// A measurement runs the real entry point (ccl_wave_step, halo exchanges
+// included) on zero-filled scratch buffers of the candidate's shape, split
+// into its chunk count with regions sized by NEIGHBORHOOD(T): one warm-up
+// run, then `reps` timed runs (HIP events on the caller's stream; the median
+// is kept), then, if asked, repeated runs inside a window of at least
+// `energy_window_s` seconds bracketed by device-energy reads.  The scratch
+// pool is library-owned for the duration of the call.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+#include "ccl_internal.h"
+
+namespace ccl {
+namespace {
+
+struct Plan {
+  std::vector<ccl_chunk> chunks;
+  std::vector<ccl_subrange> regions;
+  std::vector<int64_t> elems;   // per buffer
+  int nbuf = 2;
+  size_t bytes = 0;
+};
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+ccl_status plan_of(const ccl_tune_config &c, Plan *P) {
+  const int dims = c.dims;
+  if (dims != 2 && dims != 3) return fail(CCL_E_INVALID, "dims=%d must be 2 or 3", dims);
+  if (c.temporal_depth < 1 || c.temporal_depth > CCL_MAX_DEPTH)
+    return fail(CCL_E_INVALID, "temporal depth %d", c.temporal_depth);
+  if (dims == 3 && c.temporal_depth != 1) return fail(CCL_E_UNSUPPORTED, "3D needs T == 1");
+  ccl_subrange r;
+  memset(&r, 0, sizeof(r));
+  r.dims = dims;
+  for (int d = 0; d < dims; ++d) r.range[d] = c.shape[d];
+  P->chunks.resize(std::max(1, c.nchunks));
+  ccl_status st = ccl_split_range(&r, c.nchunks, 0, P->chunks.data());
+  if (st != CCL_OK) return st;
+  ccl_range_mapper m;
+  memset(&m, 0, sizeof(m));
+  m.kind = CCL_MAP_NEIGHBORHOOD;
+  for (int d = 0; d < dims; ++d) m.extent[d] = c.temporal_depth;
+  P->nbuf = c.temporal_depth > 1 ? 4 : 2;
+  P->regions.resize(c.nchunks);
+  P->elems.resize(c.nchunks);
+  P->bytes = 0;
+  for (int k = 0; k < c.nchunks; ++k) {
+    st = ccl_region_of(&P->chunks[k], &m, c.shape, &P->regions[k]);
+    if (st != CCL_OK) return st;
+    int64_t e = round_up(P->regions[k].range[dims - 1], 64);
+    for (int d = 0; d + 1 < dims; ++d) e *= P->regions[k].range[d];
+    P->elems[k] = e;
+    P->bytes += static_cast<size_t>(round_up(e * 4, 256)) * P->nbuf;
+  }
+  return CCL_OK;
+}
+
+}  // namespace
+}  // namespace ccl
+
+using namespace ccl;
+
+extern "C" ccl_status ccl_autotune_measure(int32_t n, const ccl_tune_config *cfgs, float r2,
+                                           int32_t steps, int32_t reps,
+                                           double energy_window_s, int32_t device,
+                                           void *hip_stream, ccl_tune_sample *out) {
+  clear_error();
+  if (n < 0 || (n > 0 && (!cfgs || !out))) return fail(CCL_E_INVALID, "bad arguments");
+  if (steps < 1 || reps < 1) return fail(CCL_E_INVALID, "steps and reps must be >= 1");
+  if (!std::isfinite(r2) || r2 < 0.0f) return fail(CCL_E_INVALID, "bad r2");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  std::vector<Plan> plans(n);
+  size_t pool_bytes = 0;
+  for (int i = 0; i < n; ++i) {
+    ccl_status st = plan_of(cfgs[i], &plans[i]);
+    if (st != CCL_OK) return fail(st, "config %d: %s", i, ccl_last_error());
+    pool_bytes = std::max(pool_bytes, plans[i].bytes);
+  }
+  void *pool = nullptr;
+  ccl_status st = hip_check(hipMalloc(&pool, std::max<size_t>(pool_bytes, 256)),
+                            "hipMalloc(autotune pool)");
+  if (st != CCL_OK) return st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  st = hip_check(hipEventCreate(&e0), "hipEventCreate");
+  if (st == CCL_OK) st = hip_check(hipEventCreate(&e1), "hipEventCreate");
+  const bool want_energy = energy_window_s > 0.0;
+  for (int i = 0; i < n && st == CCL_OK; ++i) {
+    const ccl_tune_config &c = cfgs[i];
+    Plan &P = plans[i];
+    const int dims = c.dims;
+    st = hip_check(hipMemsetAsync(pool, 0, P.bytes, s), "hipMemsetAsync");
+    if (st != CCL_OK) break;
+    std::vector<ccl_chunk_buffer> bufs(4 * c.nchunks);
+    char *cursor = static_cast<char *>(pool);
+    for (int b = 0; b < P.nbuf; ++b)
+      for (int k = 0; k < c.nchunks; ++k) {
+        ccl_chunk_buffer &B = bufs[b * c.nchunks + k];
+        memset(&B, 0, sizeof(B));
+        B.base = cursor;
+        B.region = P.regions[k];
+        const int64_t row = round_up(P.regions[k].range[dims - 1], 64);
+        B.pitch[dims - 1] = 1;
+        B.pitch[dims - 2] = row;
+        if (dims == 3) B.pitch[0] = row * P.regions[k].range[1];
+        cursor += round_up(P.elems[k] * 4, 256);
+      }
+    ccl_chunk_buffer *up = &bufs[0], *uc = &bufs[c.nchunks];
+    ccl_chunk_buffer *wp = P.nbuf == 4 ? &bufs[2 * c.nchunks] : nullptr;
+    ccl_chunk_buffer *wc = P.nbuf == 4 ? &bufs[3 * c.nchunks] : nullptr;
+    ccl_wave_params wp_params;
+    memset(&wp_params, 0, sizeof(wp_params));
+    wp_params.dims = dims;
+    wp_params.r2 = r2;
+    wp_params.temporal_depth = c.temporal_depth;
+    wp_params.tile_rows = c.tile_rows;
+    auto run = [&]() {
+      return ccl_wave_step(&wp_params, c.nchunks, P.chunks.data(), up, uc, wp, wc, steps, s);
+    };
+    st = run();  // warm-up
+    if (st != CCL_OK) break;
+    std::vector<float> times;
+    for (int r = 0; r < reps && st == CCL_OK; ++r) {
+      st = hip_check(hipEventRecord(e0, s), "hipEventRecord");
+      if (st == CCL_OK) st = run();
+      if (st == CCL_OK) st = hip_check(hipEventRecord(e1, s), "hipEventRecord");
+      if (st == CCL_OK) st = hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+      float ms = 0.0f;
+      if (st == CCL_OK) st = hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+      times.push_back(ms);
+    }
+    if (st != CCL_OK) break;
+    std::sort(times.begin(), times.end());
+    const double med_s = 1e-3 * times[times.size() / 2];
+    ccl_tune_sample &o = out[i];
+    o.seconds_per_step = med_s / steps;
+    o.joules_per_step = std::numeric_limits<double>::quiet_NaN();
+    o.window_seconds = 0.0;
+    o.runs_in_window = 0;
+    if (want_energy) {
+      double j0 = 0.0, j1 = 0.0;
+      if (ccl_energy_read(device, s, &j0, nullptr) == CCL_OK) {
+        const auto t0 = std::chrono::steady_clock::now();
+        int runs = 0;
+        double el = 0.0;
+        do {
+          st = run();
+          if (st != CCL_OK) break;
+          ++runs;
+          if (runs % 4 == 0 || med_s * runs >= energy_window_s) {
+            st = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+            if (st != CCL_OK) break;
+            el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+          }
+        } while (el < energy_window_s);
+        if (st != CCL_OK) break;
+        if (ccl_energy_read(device, s, &j1, nullptr) == CCL_OK) {
+          el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+          o.joules_per_step = (j1 - j0) / (static_cast<double>(runs) * steps);
+          o.window_seconds = el;
+          o.runs_in_window = runs;
+        }
+      }
+      clear_error();
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(pool);
+  return st;
+}
+
+extern "C" ccl_status ccl_costmodel_features(int32_t n, const ccl_tune_config *cfgs,
+                                             float *x_host) {
+  clear_error();
+  if (n < 0 || (n > 0 && (!cfgs || !x_host))) return fail(CCL_E_INVALID, "bad arguments");
+  for (int i = 0; i < n; ++i) {
+    const ccl_tune_config &c = cfgs[i];
+    if ((c.dims != 2 && c.dims != 3) || c.nchunks < 1 || c.temporal_depth < 1 ||
+        c.temporal_depth > CCL_MAX_DEPTH || c.tile_rows < 0)
+      return fail(CCL_E_INVALID, "config %d is malformed", i);
+    for (int d = 0; d < c.dims; ++d)
+      if (c.shape[d] < 1) return fail(CCL_E_INVALID, "config %d has an empty extent", i);
+    const double n0 = static_cast<double>(c.shape[0]);
+    const double n1 = static_cast<double>(c.shape[1]);
+    const double n2 = c.dims == 3 ? static_cast<double>(c.shape[2]) : 1.0;
+    const double cells = n0 * n1 * n2;
+    const double T = c.temporal_depth;
+    const double K = c.nchunks;
+    const double rows = c.tile_rows > 0 ? c.tile_rows : 64.0;
+    // halo bytes per step: 2 directions x (K-1) boundaries x (2T-1) rows/planes
+    // of u^n and u^{n-1}, read and written, per T steps
+    const double row_bytes = 4.0 * n1 * n2;
+    const double halo = 2.0 * (K - 1.0) * (2.0 * T - 1.0) * row_bytes * 2.0 / T;
+    const double model_bytes = c.temporal_depth == 1 ? 12.0 : 16.0 / T;
+    const double strip = c.dims == 2 ? 256.0 - 2.0 * 4.0 * std::ceil(T / 4.0) : 256.0;
+    const double waves = K * std::ceil(n0 / K / rows) * std::ceil((c.dims == 2 ? n1 : n2) / strip) *
+                         (c.dims == 3 ? std::ceil(n1 / 4.0) : 1.0);
+    float *x = x_host + static_cast<size_t>(i) * CCL_MLP_IN;
+    x[0] = static_cast<float>(std::log2(n0));
+    x[1] = static_cast<float>(std::log2(n1));
+    x[2] = static_cast<float>(c.dims == 3 ? std::log2(n2) : 0.0);
+    x[3] = c.dims == 3 ? 1.0f : 0.0f;
+    x[4] = static_cast<float>(std::log2(cells));
+    x[5] = static_cast<float>(std::log2(K));
+    x[6] = static_cast<float>(std::log2(rows));
+    x[7] = static_cast<float>(T);
+    x[8] = static_cast<float>(1.0 / T);
+    x[9] = static_cast<float>(std::log2(1.0 + halo));
+    x[10] = static_cast<float>(model_bytes);
+    x[11] = static_cast<float>(std::log2(std::max(1.0, waves)));
+  }
+  return CCL_OK;
+}

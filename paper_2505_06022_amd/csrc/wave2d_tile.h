@@ -64,11 +64,15 @@ __device__ __forceinline__ float dpp_from_right(float v) {
 }
 
 // One cell: s = (N + S) + (W + E); lap = s - 4C; u+ = fma(r2, lap, 2C - P).
+// 4C and 2C are exact in binary floating point, so s - 4C and 2C - P are
+// each the exact value rounded once, which is what the fma forms below
+// compute: the result is bitwise the same as the separate multiply and
+// subtract, with two fewer instructions.
 __device__ __forceinline__ float cell(float n, float s, float w, float e, float c, float p,
                                       float r2) {
   const float sum = (n + s) + (w + e);
-  const float lap = sum - 4.0f * c;
-  return fmaf(r2, lap, 2.0f * c - p);
+  const float lap = fmaf(-4.0f, c, sum);
+  return fmaf(r2, lap, fmaf(2.0f, c, -p));
 }
 
 __device__ __forceinline__ float4 step4(const float4 &n, const float4 &c, const float4 &s,
@@ -103,15 +107,23 @@ __device__ __forceinline__ Cols cols_of(int xl, int x0, int x1) {
   return c;
 }
 
-// Loads the lane's group of `row` (zero outside the loadable box).
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// Loads the lane's group of `row` (zero outside the loadable box).  STREAM
+// marks data read once (u^{n-1}): a nontemporal load keeps it from
+// displacing the u^n rows that neighbouring tiles re-read from cache.
+template <bool STREAM>
 __device__ __forceinline__ float4 load4(const float *base, int32_t by0, int32_t bx0,
                                         int32_t pitch, int row, int xl, int ly0, int ly1,
                                         const Cols &c) {
   float4 v = zero4();
   if (row < ly0 || row >= ly1) return v;  // wave-uniform
-  if (c.any)
-    v = *reinterpret_cast<const float4 *>(base + static_cast<int64_t>(row - by0) * pitch +
-                                          (xl - bx0));
+  if (c.any) {
+    const f4v *p = reinterpret_cast<const f4v *>(base + static_cast<int64_t>(row - by0) * pitch +
+                                                 (xl - bx0));
+    const f4v r = STREAM ? __builtin_nontemporal_load(p) : *p;
+    v = make_float4(r.x, r.y, r.z, r.w);
+  }
   v.x = c.m0 ? v.x : 0.0f;
   v.y = c.m1 ? v.y : 0.0f;
   v.z = c.m2 ? v.z : 0.0f;
@@ -119,24 +131,24 @@ __device__ __forceinline__ float4 load4(const float *base, int32_t by0, int32_t 
   return v;
 }
 
-// Stores the lane's group of `row` where the output mask allows.  Partial
-// groups occur only at a chunk's left or right edge; their other columns are
-// halo cells of this chunk's own buffer that no wave writes during the
-// launch, so they are read and written back unchanged (one 16-byte store).
+// Stores the lane's group of `row` where the output mask allows (nontemporal:
+// nothing in this launch reads it back).  Partial groups occur only at a
+// chunk's left or right edge; their other columns are halo cells of this
+// chunk's own buffer that no wave writes during the launch, so they are read
+// and written back unchanged (one 16-byte store).
 __device__ __forceinline__ void store4(float *base, int32_t by0, int32_t bx0, int32_t pitch,
                                        int row, int xl, const Cols &c, const float4 &v) {
   if (!c.any) return;
-  float4 *p = reinterpret_cast<float4 *>(base + static_cast<int64_t>(row - by0) * pitch +
-                                         (xl - bx0));
-  float4 w = v;
+  f4v *p = reinterpret_cast<f4v *>(base + static_cast<int64_t>(row - by0) * pitch + (xl - bx0));
+  f4v w = {v.x, v.y, v.z, v.w};
   if (!(c.m0 && c.m1 && c.m2 && c.m3)) {
-    const float4 o = *p;
+    const f4v o = *p;
     w.x = c.m0 ? v.x : o.x;
     w.y = c.m1 ? v.y : o.y;
     w.z = c.m2 ? v.z : o.z;
     w.w = c.m3 ? v.w : o.w;
   }
-  *p = w;
+  __builtin_nontemporal_store(w, p);
 }
 
 __device__ __forceinline__ float4 force_zero(float4 v, bool row_in, const Cols &d) {
@@ -170,6 +182,9 @@ __device__ __forceinline__ void tile(const Chunk &C, const Domain &D, float r2, 
   const Cols lp = cols_of(xl, IN_PLACE ? max(C.lp_x0, vx0) : C.lp_x0,
                           IN_PLACE ? min(C.lp_x1, vx1) : C.lp_x1);
 
+  // a strip whose 256 columns all lie in the domain needs no column mask
+  const bool interior_cols = xs >= D.gx0 && xs + 256 <= D.gx1;
+
   float4 ring[T][3];
 #pragma unroll
   for (int k = 0; k < T; ++k) ring[k][0] = ring[k][1] = ring[k][2] = zero4();
@@ -179,8 +194,10 @@ __device__ __forceinline__ void tile(const Chunk &C, const Domain &D, float r2, 
   float4 q1[kPrefetch], q0[kPrefetch];
 #pragma unroll
   for (int u = 0; u < kPrefetch; ++u) {
-    q1[u] = load4(C.in_cur, C.ic_y0, C.ic_x0, C.ic_pitch, i0 + u, xl, C.lc_y0, C.lc_y1, lc);
-    q0[u] = load4(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch, i0 + u - 1, xl, lpy0, lpy1, lp);
+    q1[u] = load4<false>(C.in_cur, C.ic_y0, C.ic_x0, C.ic_pitch, i0 + u, xl, C.lc_y0, C.lc_y1,
+                         lc);
+    q0[u] = load4<true>(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch, i0 + u - 1, xl, lpy0, lpy1,
+                        lp);
   }
 
   for (int base = i0; base < iend; base += kPrefetch) {
@@ -189,10 +206,10 @@ __device__ __forceinline__ void tile(const Chunk &C, const Domain &D, float r2, 
       const int i = base + u;
       const float4 v1 = q1[u];
       const float4 v0 = q0[u];
-      q1[u] = load4(C.in_cur, C.ic_y0, C.ic_x0, C.ic_pitch, i + kPrefetch, xl, C.lc_y0, C.lc_y1,
-                    lc);
-      q0[u] = load4(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch, i + kPrefetch - 1, xl, lpy0, lpy1,
-                    lp);
+      q1[u] = load4<false>(C.in_cur, C.ic_y0, C.ic_x0, C.ic_pitch, i + kPrefetch, xl, C.lc_y0,
+                           C.lc_y1, lc);
+      q0[u] = load4<true>(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch, i + kPrefetch - 1, xl, lpy0,
+                          lpy1, lp);
       ring[0][0] = ring[0][1];
       ring[0][1] = ring[0][2];
       ring[0][2] = v1;
@@ -201,7 +218,8 @@ __device__ __forceinline__ void tile(const Chunk &C, const Domain &D, float r2, 
       for (int k = 1; k <= T; ++k) {
         const int r = i - k;  // row of level k+1 computed now
         float4 nv = step4(ring[k - 1][0], ring[k - 1][1], ring[k - 1][2], pv, r2);
-        nv = force_zero(nv, r >= D.gy0 && r < D.gy1, dom);
+        const bool row_in = r >= D.gy0 && r < D.gy1;  // wave-uniform
+        if (!(row_in && interior_cols)) nv = force_zero(nv, row_in, dom);
         if (k < T) {
           pv = ring[k - 1][0];
           ring[k][0] = ring[k][1];

@@ -50,12 +50,14 @@ __device__ __forceinline__ float dpp_from_right(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
 
-// s = ((Z- + Z+) + (Y- + Y+)) + (X- + X+); lap = s - 6C; u+ = fma(r2, lap, 2C - P)
+// s = ((Z- + Z+) + (Y- + Y+)) + (X- + X+); lap = s - 6C; u+ = fma(r2, lap, 2C - P).
+// 6C is rounded (6 needs two significant bits), so it stays a separate
+// multiply; 2C is exact, so fma(2, C, -P) equals the rounded 2C - P.
 __device__ __forceinline__ float cell3(float zm, float zp, float ym, float yp, float xm, float xp,
                                        float c, float p, float r2) {
   const float sum = ((zm + zp) + (ym + yp)) + (xm + xp);
   const float lap = sum - 6.0f * c;
-  return fmaf(r2, lap, 2.0f * c - p);
+  return fmaf(r2, lap, fmaf(2.0f, c, -p));
 }
 
 __device__ __forceinline__ float4 zero4() { return make_float4(0.f, 0.f, 0.f, 0.f); }

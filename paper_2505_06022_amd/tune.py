@@ -1,0 +1,226 @@
+"""Autotuner and learned cost model for ccl_wave_step launch configs.
+
+* ``candidates(shape)`` — the discrete config space of one shape: chunk
+  counts K in {1, 2, 4, 8, 16} (K <= rows), rows per tile in
+  {16, 32, 64, 128}, temporal depth T in 1..8 (2D) or 1 (3D).
+* ``measure(cfgs)`` — time (and device energy) per step of each config,
+  measured by the library's autotuner on the GPU (ccl_autotune_measure).
+* ``CostModel`` — the 12-64-64-2 MLP, trained on the GPU by the library's
+  kernels (ccl_mlp_*) on standardised features (ccl_costmodel_features) and
+  standardised targets [log s/cell-step, log J/cell-step]; ``pick`` scores
+  every candidate of a shape on the GPU (ccl_mlp_pick) and returns the best
+  by time, energy or energy-delay product.
+* ``sweep`` — the exhaustive measurement of every candidate: the fallback
+  when no model is available and the judge of a model's picks.
+
+The sample and held-out shape sets are drawn from ``synth`` (seeded).
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import (CCL_MLP_NPARAMS, CCL_MLP_PARAMS, CCL_MLP_LOSS, ccl_autotune_measure,
+               ccl_costmodel_features, ccl_mlp_create, ccl_mlp_destroy, ccl_mlp_get,
+               ccl_mlp_pick, ccl_mlp_train, make_tune_config)
+
+K_SET = (1, 2, 4, 8, 16)
+ROWS_SET = (16, 32, 64, 128)
+T_SET_2D = tuple(range(1, 9))
+
+OBJECTIVES = {"time": (1.0, 0.0), "energy": (0.0, 1.0), "edp": (1.0, 1.0)}
+
+
+def candidates(shape):
+    dims = len(shape)
+    ts = T_SET_2D if dims == 2 else (1,)
+    out = []
+    for K in K_SET:
+        if K > shape[0]:
+            continue
+        for rows in ROWS_SET:
+            for T in ts:
+                out.append(make_tune_config(shape, K, T, rows))
+    return out
+
+
+def cfg_key(c):
+    return (tuple(c.shape[:c.dims]), c.nchunks, c.temporal_depth, c.tile_rows)
+
+
+def steps_for(shape, target_cell_steps=3e9):
+    cells = float(np.prod(shape))
+    s = int(round(target_cell_steps / cells / 24.0)) * 24
+    return int(min(960, max(24, s)))
+
+
+def measure(cfgs, r2=0.25, reps=3, energy_window_s=0.0, steps=None):
+    """Measures configs grouped by shape; returns one dict per config."""
+    by_shape = {}
+    for i, c in enumerate(cfgs):
+        by_shape.setdefault(tuple(c.shape[:c.dims]), []).append(i)
+    out = [None] * len(cfgs)
+    for shape, idx in by_shape.items():
+        st = steps or steps_for(shape)
+        res = ccl_autotune_measure([cfgs[i] for i in idx], r2, st, reps, energy_window_s)
+        cells = float(np.prod(shape))
+        for i, r in zip(idx, res):
+            out[i] = dict(key=cfg_key(cfgs[i]), steps=st, s_per_step=r.seconds_per_step,
+                          j_per_step=r.joules_per_step, s_per_cell_step=r.seconds_per_step / cells,
+                          j_per_cell_step=r.joules_per_step / cells, window_s=r.window_seconds)
+    return out
+
+
+def sweep(shape, r2=0.25, reps=3, energy_window_s=0.0):
+    cfgs = candidates(shape)
+    return cfgs, measure(cfgs, r2, reps, energy_window_s)
+
+
+def targets_of(samples):
+    t = np.array([[math.log(s["s_per_cell_step"]),
+                   math.log(s["j_per_cell_step"]) if np.isfinite(s["j_per_cell_step"]) and
+                   s["j_per_cell_step"] > 0 else math.log(s["s_per_cell_step"])]
+                  for s in samples], dtype=np.float64)
+    return t
+
+
+@dataclass
+class Standardiser:
+    mean: np.ndarray
+    std: np.ndarray
+
+    def apply(self, a):
+        return ((a - self.mean) / self.std).astype(np.float32)
+
+    def invert(self, a):
+        return a * self.std + self.mean
+
+
+class CostModel:
+    """The MLP plus its feature and target standardisation."""
+
+    def __init__(self, params, xs: Standardiser, ys: Standardiser, meta=None):
+        self.params = np.asarray(params, dtype=np.float32).ravel()
+        self.xs, self.ys = xs, ys
+        self.meta = dict(meta or {})
+        self.handle = ccl_mlp_create(self.params)
+
+    @staticmethod
+    def init_params(seed: int):
+        import synth
+        ws, bs = synth.mlp_params((12, 64, 64, 2), seed, dtype=np.float32)
+        return pack(ws, bs)
+
+    @classmethod
+    def fit(cls, X, Y, epochs=3000, lr=3e-3, seed=0, stream=None):
+        import torch
+        xs = Standardiser(X.mean(0), np.where(X.std(0) > 1e-9, X.std(0), 1.0))
+        ys = Standardiser(Y.mean(0), np.where(Y.std(0) > 1e-9, Y.std(0), 1.0))
+        m = cls(cls.init_params(seed), xs, ys, meta=dict(epochs=epochs, lr=lr, seed=seed,
+                                                         n=int(len(X))))
+        xd = torch.from_numpy(xs.apply(X)).cuda()
+        yd = torch.from_numpy(ys.apply(Y)).cuda()
+        t0 = time.perf_counter()
+        ccl_mlp_train(m.handle, len(X), xd.data_ptr(), yd.data_ptr(), epochs, lr, stream)
+        torch.cuda.synchronize()
+        m.meta["train_seconds"] = time.perf_counter() - t0
+        m.meta["final_loss"] = float(ccl_mlp_get(m.handle, CCL_MLP_LOSS)[0])
+        m.params = ccl_mlp_get(m.handle, CCL_MLP_PARAMS)
+        return m
+
+    def predict(self, X):
+        """Predicted [log s/cell-step, log J/cell-step] (host arrays)."""
+        import torch
+
+        from . import ccl_mlp_forward
+        xd = torch.from_numpy(self.xs.apply(X)).cuda()
+        yd = torch.empty((len(X), 2), dtype=torch.float32, device="cuda")
+        ccl_mlp_forward(self.handle, len(X), xd.data_ptr(), yd.data_ptr())
+        torch.cuda.synchronize()
+        return self.ys.invert(yd.cpu().numpy().astype(np.float64))
+
+    def pick(self, shape, objective="time"):
+        """Best candidate of `shape` by the model (index into candidates())."""
+        import torch
+        cfgs = candidates(shape)
+        X = ccl_costmodel_features(cfgs)
+        w = OBJECTIVES[objective]
+        # scores in standardised target units, weighted back to log units
+        wt, we = w[0] * float(self.ys.std[0]), w[1] * float(self.ys.std[1])
+        xd = torch.from_numpy(self.xs.apply(X)).cuda()
+        best = torch.zeros(1, dtype=torch.int32, device="cuda")
+        ccl_mlp_pick(self.handle, len(cfgs), xd.data_ptr(), wt, we, 0, best.data_ptr())
+        torch.cuda.synchronize()
+        i = int(best.item())
+        return cfgs[i], i
+
+    def to_json(self):
+        return dict(params=self.params.tolist(), x_mean=self.xs.mean.tolist(),
+                    x_std=self.xs.std.tolist(), y_mean=self.ys.mean.tolist(),
+                    y_std=self.ys.std.tolist(), meta=self.meta)
+
+    @classmethod
+    def from_json(cls, d):
+        return cls(np.array(d["params"], np.float32),
+                   Standardiser(np.array(d["x_mean"]), np.array(d["x_std"])),
+                   Standardiser(np.array(d["y_mean"]), np.array(d["y_std"])), d.get("meta"))
+
+    def save(self, path):
+        with open(path, "w") as f:
+            json.dump(self.to_json(), f)
+
+    @classmethod
+    def load(cls, path):
+        with open(path) as f:
+            return cls.from_json(json.load(f))
+
+    def close(self):
+        if self.handle is not None:
+            ccl_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pack(ws, bs):
+    parts = []
+    for w, b in zip(ws, bs):
+        parts.append(np.asarray(w, np.float32).ravel())
+        parts.append(np.asarray(b, np.float32).ravel())
+    p = np.concatenate(parts)
+    assert p.size == CCL_MLP_NPARAMS
+    return p
+
+
+def unpack(p, sizes=(12, 64, 64, 2)):
+    p = np.asarray(p)
+    ws, bs, o = [], [], 0
+    for fi, fo in zip(sizes[:-1], sizes[1:]):
+        ws.append(p[o:o + fi * fo].reshape(fo, fi))
+        o += fi * fo
+        bs.append(p[o:o + fo])
+        o += fo
+    return ws, bs
+
+
+def sample_space(n_shapes: int, seed: int, per_shape: int, rng_seed: int):
+    """Training configs: `n_shapes` seeded 2D shapes (sides log-uniform on
+    256..16384), `per_shape` candidates each drawn without replacement."""
+    import synth
+    shapes = synth.cost_model_shapes(n_shapes, seed)
+    rs = np.random.default_rng(rng_seed)
+    cfgs = []
+    for sh in shapes:
+        cands = candidates(sh)
+        pick = rs.choice(len(cands), size=min(per_shape, len(cands)), replace=False)
+        cfgs.extend(cands[i] for i in sorted(pick))
+    return shapes, cfgs

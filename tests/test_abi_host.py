@@ -240,3 +240,26 @@ def test_batch_create_validation_no_launch():
     assert L.ccl_batch_create(1, (ccl.ccl_batch_grid * 1)(bad), 0, ctypes.byref(h)) == ccl.CCL_E_INVALID
     assert L.ccl_batch_create(1, arr, 8, ctypes.byref(h)) == ccl.CCL_E_INVALID
     assert L.ccl_batch_destroy(None) == ccl.CCL_OK
+
+
+def test_costmodel_features_host():
+    """Features of two configs written out by hand."""
+    import math
+    import numpy as np
+    c2 = ccl.make_tune_config((1024, 4096), 4, 8, 64)
+    c3 = ccl.make_tune_config((96, 768, 768), 8, 1, 32)
+    x = ccl.ccl_costmodel_features([c2, c3])
+    halo2 = 2 * 3 * 15 * (4 * 4096) * 2 / 8
+    waves2 = 4 * math.ceil(1024 / 4 / 64) * math.ceil(4096 / 240)
+    want2 = [10, 12, 0, 0, 22, 2, 6, 8, 1 / 8, math.log2(1 + halo2), 2.0, math.log2(waves2)]
+    halo3 = 2 * 7 * 1 * (4 * 768 * 768) * 2 / 1
+    waves3 = 8 * math.ceil(96 / 8 / 32) * math.ceil(768 / 256) * math.ceil(768 / 4)
+    want3 = [math.log2(96), math.log2(768), math.log2(768), 1, math.log2(96 * 768 * 768), 3, 5, 1,
+             1, math.log2(1 + halo3), 12.0, math.log2(waves3)]
+    assert np.allclose(x[0], want2, rtol=1e-6)
+    assert np.allclose(x[1], want3, rtol=1e-6)
+    L = ccl.lib()
+    bad = ccl.make_tune_config((16, 16), 0, 1, 16)
+    arr = (ccl.ccl_tune_config * 1)(bad)
+    out = (ctypes.c_float * 12)()
+    assert L.ccl_costmodel_features(1, arr, out) == ccl.CCL_E_INVALID

@@ -1,0 +1,155 @@
+"""GPU tests of the cost-model kernels and the autotuner, through the C ABI.
+
+* Forward, gradient, loss and one Adam step of the 12-64-64-2 MLP against
+  the float64 oracle (relative L2 per tensor <= 1e-4 for gradients).
+* Training is deterministic (two runs give identical parameters) and tracks
+  the float64 oracle's loss trajectory.
+* ccl_mlp_pick returns the argmin of the oracle's scores (ties aside).
+* ccl_autotune_measure returns positive times for every config and fails
+  cleanly on a bad one.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+SIZES = (12, 64, 64, 2)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    import paper_2505_06022_amd as ccl
+    ccl.lib()
+    yield
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def make(seed, n):
+    from paper_2505_06022_amd.tune import pack
+    ws, bs = synth.mlp_params(SIZES, seed)
+    for b in bs:  # non-zero biases exercise the bias gradients
+        b[:] = np.random.default_rng(seed + 1).uniform(-0.1, 0.1, size=b.shape)
+    x, t = synth.mlp_batch(n, 12, 2, seed + 2)
+    # round inputs to float32 so both sides see the same numbers
+    ws = [w.astype(np.float32).astype(np.float64) for w in ws]
+    bs = [b.astype(np.float32).astype(np.float64) for b in bs]
+    x = x.astype(np.float32).astype(np.float64)
+    t = t.astype(np.float32).astype(np.float64)
+    return ws, bs, x, t, pack(ws, bs)
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 200, 4000])
+def test_forward_grad_loss_vs_oracle(n):
+    import paper_2505_06022_amd as ccl
+    from paper_2505_06022_amd.tune import unpack
+    ws, bs, x, t, p = make(3, n)
+    h = ccl.ccl_mlp_create(p)
+    xd = torch.from_numpy(x.astype(np.float32)).cuda()
+    td = torch.from_numpy(t.astype(np.float32)).cuda()
+    yd = torch.empty((n, 2), device="cuda")
+    ccl.ccl_mlp_forward(h, n, xd.data_ptr(), yd.data_ptr())
+    ccl.ccl_mlp_grad(h, n, xd.data_ptr(), td.data_ptr())
+    torch.cuda.synchronize()
+    acts = omlp.forward(ws, bs, x)
+    assert rel_l2(yd.cpu().numpy(), acts[-1]) <= 1e-5
+    gw, gb = omlp.backward(ws, bs, acts, t)
+    g = ccl.ccl_mlp_get(h, ccl.CCL_MLP_GRADS)
+    uw, ub = unpack(g)
+    for li in range(3):
+        assert rel_l2(uw[li], gw[li]) <= 1e-4, f"dW{li + 1}"
+        assert rel_l2(ub[li], gb[li]) <= 1e-4, f"db{li + 1}"
+    loss = ccl.ccl_mlp_get(h, ccl.CCL_MLP_LOSS)[0]
+    assert abs(loss - omlp.loss(acts[-1], t)) <= 1e-5 * max(1.0, omlp.loss(acts[-1], t))
+    ccl.ccl_mlp_destroy(h)
+
+
+def test_adam_steps_vs_oracle():
+    import paper_2505_06022_amd as ccl
+    from paper_2505_06022_amd.tune import pack, unpack
+    ws, bs, x, t, p = make(5, 300)
+    h = ccl.ccl_mlp_create(p)
+    xd = torch.from_numpy(x.astype(np.float32)).cuda()
+    td = torch.from_numpy(t.astype(np.float32)).cuda()
+    params = ws + bs
+    m = [np.zeros_like(q) for q in params]
+    v = [np.zeros_like(q) for q in params]
+    for step in range(1, 6):
+        ccl.ccl_mlp_grad(h, 300, xd.data_ptr(), td.data_ptr())
+        ccl.ccl_mlp_adam(h, 1e-3)
+        acts = omlp.forward(ws, bs, x)
+        gw, gb = omlp.backward(ws, bs, acts, t)
+        omlp.adam_step(params, gw + gb, m, v, step, lr=1e-3)
+    torch.cuda.synchronize()
+    got = ccl.ccl_mlp_get(h, ccl.CCL_MLP_PARAMS)
+    want = pack(ws, bs)
+    # parameters moved by ~5e-3; require the GPU's move to match to 1e-3 of it
+    assert np.max(np.abs(got - want)) <= 1e-3 * np.max(np.abs(want - p)) + 1e-6
+    ccl.ccl_mlp_destroy(h)
+
+
+def test_training_deterministic_and_tracks_oracle():
+    import paper_2505_06022_amd as ccl
+    ws, bs, x, t, p = make(7, 1000)
+    xd = torch.from_numpy(x.astype(np.float32)).cuda()
+    td = torch.from_numpy(t.astype(np.float32)).cuda()
+    outs = []
+    for _ in range(2):
+        h = ccl.ccl_mlp_create(p)
+        ccl.ccl_mlp_train(h, 1000, xd.data_ptr(), td.data_ptr(), 200, 1e-3)
+        torch.cuda.synchronize()
+        outs.append((ccl.ccl_mlp_get(h, ccl.CCL_MLP_PARAMS), ccl.ccl_mlp_get(h, ccl.CCL_MLP_LOSS)))
+        ccl.ccl_mlp_destroy(h)
+    assert np.array_equal(outs[0][0], outs[1][0])
+    params = ws + bs
+    m = [np.zeros_like(q) for q in params]
+    v = [np.zeros_like(q) for q in params]
+    for step in range(1, 201):
+        acts = omlp.forward(ws, bs, x)
+        gw, gb = omlp.backward(ws, bs, acts, t)
+        last = omlp.loss(acts[-1], t)
+        omlp.adam_step(params, gw + gb, m, v, step, lr=1e-3)
+    # the GPU reports the loss of its last gradient evaluation (before the
+    # last Adam step), as `last` here
+    assert abs(outs[0][1][0] - last) <= 1e-3 * last
+
+
+def test_pick_is_oracle_argmin():
+    import paper_2505_06022_amd as ccl
+    ws, bs, x, t, p = make(9, 777)
+    h = ccl.ccl_mlp_create(p)
+    xd = torch.from_numpy(x.astype(np.float32)).cuda()
+    best = torch.zeros(1, dtype=torch.int32, device="cuda")
+    scores = torch.empty(777, device="cuda")
+    for w0, w1 in ((1.0, 0.0), (0.0, 1.0), (0.7, 0.3)):
+        ccl.ccl_mlp_pick(h, 777, xd.data_ptr(), w0, w1, scores.data_ptr(), best.data_ptr())
+        torch.cuda.synchronize()
+        y = omlp.forward(ws, bs, x)[-1]
+        s = w0 * y[:, 0] + w1 * y[:, 1]
+        b = int(best.item())
+        assert s[b] <= s.min() + 1e-5 * max(1.0, abs(s.min()))
+        got_scores = scores.cpu().numpy()
+        assert b == int(np.argmin(got_scores))
+    ccl.ccl_mlp_destroy(h)
+
+
+def test_autotune_measure():
+    import paper_2505_06022_amd as ccl
+    cfgs = [ccl.make_tune_config((512, 1024), K, T, rows)
+            for K, T, rows in ((1, 1, 32), (4, 4, 64), (2, 8, 16), (16, 2, 128))]
+    cfgs.append(ccl.make_tune_config((64, 48, 300), 3, 1, 8))
+    res = ccl.ccl_autotune_measure(cfgs, 0.25, 24, reps=3)
+    for r in res:
+        assert r.seconds_per_step > 0 and np.isnan(r.joules_per_step)
+    bad = [ccl.make_tune_config((512, 1024), 1, 9, 32)]
+    with pytest.raises(ccl.CclError):
+        ccl.ccl_autotune_measure(bad, 0.25, 24)
