@@ -1,13 +1,20 @@
 #!/usr/bin/env python3
 """Throughput of the chunked leapfrog wave stencil on one MI355X.
 
-One bench step = one full run of the workload: 1000 leapfrog steps of the
-8192 x 8192 row share (rows [8192, 16384) of a 32768 x 8192 domain, Dirichlet
-zero outside the share) split into 4 device-local chunks, with the halo
-exchanges between them, through ccl_wave_step.  Inputs are resident in HBM
+One bench step = one full run of the headline workload: 1000 leapfrog
+steps of the 8192 x 8192 row share (rows [8192, 16384) of a 32768 x 8192
+domain, Dirichlet zero outside the share) split into 4 device-local chunks,
+halo exchanges included, through ccl_wave_step.  Inputs are resident in HBM
 before the timed region; the timed region is bracketed by synchronisation.
 
-Prints one JSON line: value = Mcells/s (cell updates per second / 1e6).
+The launch config (temporal depth T, rows per tile) is the learned cost
+model's pick when a trained model is present, else the best of a quick
+autotuner sweep; ``--depth``/``--tile-rows`` override both.  Besides the
+headline ("tuned") form the line reports the plain form (T = 1), device
+energy per step, and the 64-grid batched workload run as one graph launch
+against a per-grid loop of plain calls.
+
+Prints one JSON line; value = Mcells/s (cell updates per second / 1e6).
 """
 from __future__ import annotations
 
@@ -21,27 +28,33 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+MODEL_PATH = os.path.join(ROOT, "paper_2505_06022_amd", "costmodel.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("wave2d.hip", "wave_step.cpp", "halo.hip"):
+    for name in ("wave2d_tile.h", "wave2d.hip", "wave_step.cpp", "halo.hip"):
         with open(os.path.join(ROOT, "paper_2505_06022_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(depth: int):
+def load_traffic(depth: int, rows: int):
     """HBM bytes per stencil launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source and depth."""
+    summary, if it was taken on the current kernel source and config."""
     path = os.path.join(ROOT, "profiles", "traffic_wave2d_8192_share_k4.json")
     try:
         with open(path) as f:
             doc = json.load(f)
     except (OSError, ValueError):
         return None
-    if doc.get("kernel_hash") != kernel_source_hash() or doc.get("depth") != depth:
+    if (doc.get("kernel_hash") != kernel_source_hash() or doc.get("depth") != depth
+            or doc.get("tile_rows") != rows):
         return None
     return doc.get("bytes_per_launch")
 
@@ -89,15 +102,139 @@ def saxpy_calibration(n: int = 1 << 28, reps: int = 10):
     return 12.0 * n / (ms / launches * 1e-3) / 1e9
 
 
+def average_power(run_once, min_span=2.0, limit=30.0):
+    """Mean device power (W) over back-to-back runs, between two updates of
+    the device energy counter at least `min_span` s apart (the counter
+    advances in coarse steps, so the window is aligned to its updates)."""
+    import torch
+
+    import paper_2505_06022_amd as ccl
+    _, ts0 = ccl.ccl_energy_read(0, None)
+    first = last = None
+    t0 = time.perf_counter()
+    while last is None:
+        run_once()
+        torch.cuda.synchronize()
+        e, ts = ccl.ccl_energy_read(0, None)
+        if first is None:
+            if ts != ts0:
+                first = (e, ts)
+        elif (ts - first[1]) * 1e-9 >= min_span:
+            last = (e, ts)
+        if time.perf_counter() - t0 > limit:
+            raise RuntimeError("energy counter did not advance")
+    return (last[0] - first[0]) / ((last[1] - first[1]) * 1e-9)
+
+
+def pick_config(w, args):
+    """(T, rows, how) for the headline share."""
+    if args.depth and args.tile_rows:
+        return args.depth, args.tile_rows, "given"
+    import numpy as np
+
+    import paper_2505_06022_amd as ccl
+    from paper_2505_06022_amd import tune
+    shape = w["shape"]
+    if os.path.exists(MODEL_PATH) and not args.sweep:
+        m = tune.CostModel.load(MODEL_PATH)
+        cands = [c for c in tune.candidates(shape) if c.nchunks == w["chunks"]]
+        X = ccl.ccl_costmodel_features(cands)
+        y = m.predict(X)
+        i = int(np.argmin(y[:, 0]))
+        m.close()
+        return cands[i].temporal_depth, cands[i].tile_rows, "cost model"
+    cands = [c for c in tune.candidates(shape) if c.nchunks == w["chunks"]]
+    res = tune.measure(cands, w["r2"], reps=3, steps=48)
+    i = int(np.argmin([r["s_per_step"] for r in res]))
+    return cands[i].temporal_depth, cands[i].tile_rows, "autotuner sweep"
+
+
+def time_runs(cw, steps, runs):
+    import torch
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(runs):
+        cw.step(steps)
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) * 1e-3
+
+
+def batched_forms(log_energy=False):
+    """The 64-grid workload: one graph launch (per-grid depth picked by the
+    cost model or T=4) vs a loop of plain T=1 ccl_wave_step calls."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2505_06022_amd import tune
+    from paper_2505_06022_amd.fields import BatchedWaves, ChunkedWave
+    grids = synth.batched_grids()
+    model = tune.CostModel.load(MODEL_PATH) if os.path.exists(MODEL_PATH) else None
+    specs = []
+    for d in grids:
+        depth, rows = 4, 64
+        if model is not None:
+            c, _ = model.pick((d["ny"], d["nx"]), "time", nchunks=1)
+            depth, rows = c.temporal_depth, max(c.tile_rows, c.temporal_depth)
+        specs.append(dict(ny=d["ny"], nx=d["nx"], steps=d["steps"], r2=0.25, depth=depth,
+                          tile_rows=rows))
+    if model is not None:
+        model.close()
+    bw = BatchedWaves(specs)
+    for g, d in enumerate(grids):
+        u0 = synth.gaussian_field((d["ny"], d["nx"]), d["sigma"], d["seed"])
+        bw.scatter(g, u0, u0)
+    torch.cuda.synchronize()
+    import paper_2505_06022_amd as ccl
+    bw.run()
+    ccl.ccl_batch_check(bw.handle)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    reps = 3
+    a.record()
+    for _ in range(reps):
+        bw.run()
+    b.record()
+    ccl.ccl_batch_check(bw.handle)
+    t_batched = a.elapsed_time(b) * 1e-3 / reps
+    cell_steps = sum(d["ny"] * d["nx"] * d["steps"] for d in grids)
+    p_batched = average_power(bw.run) if log_energy else None
+    bw.close()
+    del bw
+    torch.cuda.empty_cache()
+    # per-grid loop of plain calls on the same grids
+    t_loop = 0.0
+    for d in grids:
+        cw = ChunkedWave((0, 0), (d["ny"], d["nx"]), 1, 0.25, depth=1)
+        cw.step(d["steps"])
+        t_loop += time_runs(cw, d["steps"], 1)
+        del cw
+    torch.cuda.empty_cache()
+    return {"grids": len(grids), "cell_steps": cell_steps,
+            "batched_mcells": round(cell_steps / t_batched / 1e6, 1),
+            "batched_ms": round(t_batched * 1e3, 3),
+            "per_grid_loop_mcells": round(cell_steps / t_loop / 1e6, 1),
+            "per_grid_loop_ms": round(t_loop * 1e3, 3),
+            "batched_nj_per_cell_step": None if p_batched is None else
+            round(p_batched * t_batched / cell_steps * 1e9, 4),
+            "configs": "cost model" if model is not None else "T=4, 64 rows"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10, help="timed bench steps (full runs)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--depth", type=int, default=4, help="temporal depth T")
-    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--depth", type=int, default=0, help="temporal depth T (0 = pick)")
+    ap.add_argument("--tile-rows", type=int, default=0, help="rows per tile (0 = pick)")
+    ap.add_argument("--sweep", action="store_true", help="pick by autotuner sweep, not model")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-saxpy", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip SAXPY, energy, plain and batched forms")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -118,47 +255,29 @@ def main():
     torch.cuda.set_device(0)
     name = "wave2d_8192_share_k4"
     w = synth.WORKLOADS[name]
-    print(f"[bench] workload {name}: T={args.depth}, generating input", file=sys.stderr,
-          flush=True)
+    depth, rows, how = pick_config(w, args)
+    if args.depth:
+        depth = args.depth
+    if args.tile_rows:
+        rows = args.tile_rows
+    log(f"workload {name}: T={depth}, tile rows={rows} ({how}); generating input")
     u0 = synth.gaussian_field(w["shape"], w["sigma"], w["seed"])
-    cw = ChunkedWave(w["share_offset"], w["shape"], w["chunks"], w["r2"], depth=args.depth,
-                     tile_rows=args.tile_rows, buffer_range=w["global_shape"])
+    cw = ChunkedWave(w["share_offset"], w["shape"], w["chunks"], w["r2"], depth=depth,
+                     tile_rows=rows, buffer_range=w["global_shape"])
     cw.scatter(u0, u0)
     torch.cuda.synchronize()
-
-    saxpy_gbs = None if args.no_saxpy else saxpy_calibration()
 
     for i in range(args.warmup):
         cw.step(w["steps"])
         torch.cuda.synchronize()
-        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+        log(f"warmup {i + 1}/{args.warmup} done")
 
-    stream = torch.cuda.current_stream()
-    energy_ok = True
-    try:
-        e0, _ = ccl.ccl_energy_read(0, stream)
-        backend = ccl.ccl_energy_backend(0)
-    except ccl.CclError as e:
-        energy_ok, backend = False, f"unavailable ({e.message})"
     ccl.ccl_timing_enable(True)
-    torch.cuda.synchronize()
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_stop = torch.cuda.Event(enable_timing=True)
-    wall0 = time.perf_counter()
-    t_start.record(stream)
-    for _ in range(args.steps):
-        cw.step(w["steps"])
-    t_stop.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    e1 = ccl.ccl_energy_read(0, stream)[0] if energy_ok else None
-    elapsed = t_start.elapsed_time(t_stop) * 1e-3
+    elapsed = time_runs(cw, w["steps"], args.steps)
     n_launch, st_ms = ccl.ccl_timing_query(ccl.CCL_KERNEL_STENCIL)
     h_launch, h_ms = ccl.ccl_timing_query(ccl.CCL_KERNEL_HALO)
     ccl.ccl_timing_enable(False)
-    print(f"[bench] timed {args.steps} runs in {elapsed:.3f} s (wall {wall:.3f} s)",
-          file=sys.stderr, flush=True)
-
+    log(f"timed {args.steps} runs in {elapsed:.3f} s")
     sample = cw.gather_points([(w["share_offset"][0] + 4096, 4096)])
     if not np.all(np.isfinite(sample)):
         raise SystemExit("bench: non-finite field")
@@ -166,13 +285,11 @@ def main():
     cells = int(np.prod(w["shape"]))
     cell_steps = cells * w["steps"] * args.steps
     mcells = cell_steps / elapsed / 1e6
-    # dominant kernel: the stencil launch; algorithmic bytes per launch
-    per_cell = 12 if args.depth == 1 else 16  # in place: 2 reads + 1 write; else 2 + 2
+    per_cell = 12 if depth == 1 else 16  # in place: 2 reads + 1 write; else 2 + 2
     bytes_per_launch = per_cell * cells
     avg_s = st_ms / n_launch * 1e-3
     achieved = bytes_per_launch / avg_s / 1e9
     roof_equiv = HBM_PEAK_GBS * 1e9 / 12.0 / 1e6  # Mcells/s at 12 B/cell-step
-    traffic = load_traffic(args.depth)
 
     out = {
         "metric": "wave-stencil Mcells/s", "value": round(mcells, 1), "unit": "Mcells/s",
@@ -182,20 +299,42 @@ def main():
         "data": "synthetic",
         "config": {"workload": "2D leapfrog wave, 8192x8192 share of 32768x8192, FP32, "
                                "r2=0.25, 1000 steps, 4 device-local row chunks",
-                   "temporal_depth": args.depth, "cells": cells, "leapfrog_steps": w["steps"],
-                   "chunks": w["chunks"]},
+                   "temporal_depth": depth, "tile_rows": rows, "picked_by": how,
+                   "cells": cells, "leapfrog_steps": w["steps"], "chunks": w["chunks"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic},
+                     "traffic": load_traffic(depth, rows)},
         "hbm_roofline_equiv_pct": round(100.0 * mcells / roof_equiv, 2),
         "stencil_launch_ms": round(st_ms / n_launch, 4), "stencil_launches": n_launch,
-        "halo_ms_total": round(h_ms, 3), "halo_launches": h_launch,
-        "saxpy_gbs": None if saxpy_gbs is None else round(saxpy_gbs, 1),
-        "energy_backend": backend,
-        "j_per_step": None if e1 is None else round((e1 - e0) / (w["steps"] * args.steps), 6),
+        "halo_launch_ms": round(h_ms / max(h_launch, 1), 4), "halo_launches": h_launch,
     }
+    if not args.no_extras:
+        log("energy window")
+        try:
+            power = average_power(lambda: cw.step(w["steps"]))
+            out["power_w"] = round(power, 1)
+            out["j_per_step"] = round(power * elapsed / (w["steps"] * args.steps), 6)
+            out["energy_backend"] = ccl.ccl_energy_backend(0)
+        except (ccl.CclError, RuntimeError) as e:
+            out["j_per_step"] = None
+            out["energy_backend"] = f"unavailable ({e})"
+        del cw
+        torch.cuda.empty_cache()
+        log("plain form (T=1)")
+        cp = ChunkedWave(w["share_offset"], w["shape"], w["chunks"], w["r2"], depth=1,
+                         buffer_range=w["global_shape"])
+        cp.scatter(u0, u0)
+        cp.step(w["steps"])
+        t_plain = time_runs(cp, w["steps"], 2)
+        out["plain_mcells"] = round(cells * w["steps"] * 2 / t_plain / 1e6, 1)
+        del cp
+        torch.cuda.empty_cache()
+        log("SAXPY calibration")
+        out["saxpy_gbs"] = round(saxpy_calibration(), 1)
+        log("batched workload")
+        out["batched"] = batched_forms(log_energy=out.get("j_per_step") is not None)
     if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
 

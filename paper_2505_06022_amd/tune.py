@@ -144,10 +144,13 @@ class CostModel:
         torch.cuda.synchronize()
         return self.ys.invert(yd.cpu().numpy().astype(np.float64))
 
-    def pick(self, shape, objective="time"):
-        """Best candidate of `shape` by the model (index into candidates())."""
+    def pick(self, shape, objective="time", nchunks=None):
+        """Best candidate of `shape` by the model (only those with `nchunks`
+        chunks when given); returns (config, index into that list)."""
         import torch
         cfgs = candidates(shape)
+        if nchunks is not None:
+            cfgs = [c for c in cfgs if c.nchunks == nchunks]
         X = ccl_costmodel_features(cfgs)
         w = OBJECTIVES[objective]
         # scores in standardised target units, weighted back to log units
@@ -212,11 +215,14 @@ def unpack(p, sizes=(12, 64, 64, 2)):
     return ws, bs
 
 
-def sample_space(n_shapes: int, seed: int, per_shape: int, rng_seed: int):
+def sample_space(n_shapes: int, seed: int, per_shape: int, rng_seed: int, n_shapes_3d: int = 0):
     """Training configs: `n_shapes` seeded 2D shapes (sides log-uniform on
-    256..16384), `per_shape` candidates each drawn without replacement."""
+    256..16384) and `n_shapes_3d` 3D shapes (sides 64..768), `per_shape`
+    candidates each drawn without replacement."""
     import synth
     shapes = synth.cost_model_shapes(n_shapes, seed)
+    if n_shapes_3d:
+        shapes = shapes + synth.cost_model_shapes_3d(n_shapes_3d, seed + 100)
     rs = np.random.default_rng(rng_seed)
     cfgs = []
     for sh in shapes:

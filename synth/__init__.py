@@ -123,6 +123,20 @@ def cost_model_shapes(count: int, seed: int, lo: int = 256, hi: int = 16384,
     return out
 
 
+def cost_model_shapes_3d(count: int, seed: int, lo: int = 64, hi: int = 768, align: int = 32,
+                         max_cells: int = 1 << 29):
+    """3D shapes with each side log-uniform on [lo, hi], rounded to ``align``,
+    at most ``max_cells`` cells."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        s = np.exp(rng.uniform(np.log(lo), np.log(hi), size=3))
+        s = np.clip((np.round(s / align) * align).astype(int), lo, hi)
+        if int(np.prod(s)) <= max_cells:
+            out.append((int(s[0]), int(s[1]), int(s[2])))
+    return out
+
+
 def mlp_params(sizes, seed: int, dtype=np.float64):
     """He-uniform initial weights W_l (out x in) and zero biases."""
     rng = np.random.default_rng(seed)
