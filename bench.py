@@ -19,7 +19,6 @@ Prints one JSON line; value = Mcells/s (cell updates per second / 1e6).
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -36,22 +35,16 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for name in ("wave2d_tile.h", "wave2d.hip", "wave_step.cpp", "halo.hip"):
-        with open(os.path.join(ROOT, "paper_2505_06022_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
-
-
 def load_traffic(depth: int, rows: int):
     """HBM bytes per stencil launch from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source and config."""
-    path = os.path.join(ROOT, "profiles", "traffic_wave2d_8192_share_k4.json")
+    from paper_2505_06022_amd.profile_run import kernel_source_hash
+    path = os.path.join(ROOT, "profiles", "traffic_wave2d_8192_share_k4.md")
     try:
         with open(path) as f:
-            doc = json.load(f)
-    except (OSError, ValueError):
+            line = next(l for l in f if l.startswith("traffic-json: "))
+        doc = json.loads(line[len("traffic-json: "):])
+    except (OSError, ValueError, StopIteration):
         return None
     if (doc.get("kernel_hash") != kernel_source_hash() or doc.get("depth") != depth
             or doc.get("tile_rows") != rows):

@@ -294,23 +294,32 @@ typedef struct {
 typedef struct {
   double seconds_per_step;  /* median over the timed runs                    */
   double joules_per_step;   /* device energy per step, NaN if not measured   */
-  double window_seconds;    /* length of the energy window                   */
+  double window_seconds;    /* counter time between the two energy reads     */
   int32_t runs_in_window;
 } ccl_tune_sample;
 
 /* Measures each config: ccl_wave_step over zero-filled scratch buffers
  * (allocated for the call and freed before it returns), one warm-up run of
  * `steps` steps, `reps` timed runs (median kept), and — when
- * energy_window_s > 0 and device energy is readable — repeated runs filling
- * at least that many seconds between two ccl_energy_read calls.
+ * energy_window_s > 0 and device energy is readable — back-to-back runs
+ * until two updates of the device energy counter at least that many seconds
+ * apart (by the counter's timestamps) have been seen: joules_per_step is the
+ * mean power between them times seconds_per_step.
  * Synchronises `hip_stream`.  Errors: INVALID, RANGE, UNSUPPORTED, HIP. */
 ccl_status ccl_autotune_measure(int32_t n, const ccl_tune_config *cfgs, float r2,
                                 int32_t steps, int32_t reps, double energy_window_s,
                                 int32_t device, void *hip_stream, ccl_tune_sample *out);
 
+/* Rows (2D) / planes (3D) per tile that ccl_wave_step uses for `c` when its
+ * tile_rows is 0: the value minimising (resident-wave rounds) x (rows + 2
+ * halo rows) for the device's occupancy of the depth-T kernel; tile_rows
+ * itself when it is positive.  Errors: INVALID, RANGE. */
+ccl_status ccl_wave_plan_rows(const ccl_tune_config *c, int32_t *rows);
+
 /* Cost-model features of each config (host array n x CCL_MLP_IN):
  * log2 of the three extents (0 for the third in 2D), is-3D, log2 cells,
- * log2 K, log2 tile rows, T, 1/T, log2(1 + halo bytes per step), modelled
+ * log2 K, log2 tile rows (as ccl_wave_plan_rows gives them), T, 1/T,
+ * log2(1 + halo bytes per step), modelled
  * HBM bytes per cell-step (12 for T = 1, 16/T otherwise), log2 waves per
  * launch.  Errors: INVALID. */
 ccl_status ccl_costmodel_features(int32_t n, const ccl_tune_config *cfgs, float *x_host);
@@ -319,7 +328,7 @@ ccl_status ccl_costmodel_features(int32_t n, const ccl_tune_config *cfgs, float 
  * A 12-64-64-2 float32 MLP (ReLU hidden layers) that maps the features of a
  * launch config to predicted [log time, log energy] per cell-step
  * (standardised by the caller).  Trained on the GPU by the library's own
- * forward/backward kernels with L = 1/(2n) sum |y - t|^2 and Adam; gradients
+ * forward/backward kernels with L = 1/(2n) sum w |y - t|^2 and Adam; gradients
  * are summed in a fixed order, so training is deterministic.  Parameters are
  * packed W1 (64x12), b1 (64), W2 (64x64), b2 (64), W3 (2x64), b3 (2),
  * row-major W[out][in].  All sample arrays are device memory, row-major
@@ -342,12 +351,17 @@ ccl_status ccl_mlp_forward(ccl_mlp *m, int32_t n, const float *x, float *y, void
 /* Gradient and loss of L over the n samples (x, t), kept in the model. */
 ccl_status ccl_mlp_grad(ccl_mlp *m, int32_t n, const float *x, const float *t,
                         void *hip_stream);
+/* The same with per-output sample weights w (device, n x 2, may be NULL):
+ * L = 1/(2n) sum w_bk (y_bk - t_bk)^2; a zero weight masks a missing label. */
+ccl_status ccl_mlp_grad_weighted(ccl_mlp *m, int32_t n, const float *x, const float *t,
+                                 const float *w, void *hip_stream);
 /* One Adam step with the kept gradient (bias-corrected; step count kept). */
 ccl_status ccl_mlp_adam(ccl_mlp *m, float lr, float beta1, float beta2, float eps,
                         void *hip_stream);
-/* `epochs` full-batch steps of grad + Adam (beta1 0.9, beta2 0.999, eps 1e-8). */
+/* `epochs` full-batch steps of weighted grad + Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8); w may be NULL. */
 ccl_status ccl_mlp_train(ccl_mlp *m, int32_t n, const float *x, const float *t,
-                         int32_t epochs, float lr, void *hip_stream);
+                         const float *w, int32_t epochs, float lr, void *hip_stream);
 /* Scores score_i = w_time*y_i0 + w_energy*y_i1 of n candidates and writes the
  * index of the smallest (ties: lowest index) to *best (device int32);
  * `scores` (device, n floats) may be NULL. */

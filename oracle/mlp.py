@@ -2,7 +2,8 @@
 
 Network: x (B x 12) -> h1 = relu(x W1^T + b1) (64) -> h2 = relu(h1 W2^T + b2)
 (64) -> y = h2 W3^T + b3 (2).  Weights W_l are (out x in), row-major.
-Loss: L = 1/(2B) sum_{b,k} (y_bk - t_bk)^2.  relu'(0) is taken as 0.
+Loss: L = 1/(2B) sum_{b,k} w_bk (y_bk - t_bk)^2 (w = 1 unless given; a zero
+weight masks a missing target).  relu'(0) is taken as 0.
 Backward: the chain rule written out layer by layer.
 Optimiser: Adam (Kingma and Ba, 2015) with bias correction:
   m <- b1 m + (1-b1) g;  v <- b2 v + (1-b2) g^2;
@@ -23,14 +24,16 @@ def forward(ws, bs, x):
     return acts
 
 
-def loss(y, t):
-    return 0.5 * float(np.sum((y - t) ** 2)) / y.shape[0]
+def loss(y, t, w=None):
+    w = 1.0 if w is None else w
+    return 0.5 * float(np.sum(w * (y - t) ** 2)) / y.shape[0]
 
 
-def backward(ws, bs, acts, t):
+def backward(ws, bs, acts, t, w=None):
     """Gradients (dW_l, db_l) of the loss for every layer, float64."""
     B = t.shape[0]
-    g = (acts[-1] - t) / B  # dL/dy
+    w = 1.0 if w is None else w
+    g = w * (acts[-1] - t) / B  # dL/dy
     dws, dbs = [None] * len(ws), [None] * len(ws)
     for li in range(len(ws) - 1, -1, -1):
         h_in = acts[li]

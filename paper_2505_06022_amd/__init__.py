@@ -141,6 +141,7 @@ _SIGS = {
                                               ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                               ctypes.c_int32, ctypes.c_void_p,
                                               _P(ccl_tune_sample)]),
+    "ccl_wave_plan_rows": (ctypes.c_int32, [_P(ccl_tune_config), _P(ctypes.c_int32)]),
     "ccl_costmodel_features": (ctypes.c_int32, [ctypes.c_int32, _P(ccl_tune_config),
                                                 _P(ctypes.c_float)]),
     "ccl_mlp_create": (ctypes.c_int32, [_P(ctypes.c_float), _P(ctypes.c_void_p)]),
@@ -150,11 +151,14 @@ _SIGS = {
                                          ctypes.c_void_p, ctypes.c_void_p]),
     "ccl_mlp_grad": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p]),
+    "ccl_mlp_grad_weighted": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_void_p]),
     "ccl_mlp_adam": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_float, ctypes.c_float,
                                       ctypes.c_float, ctypes.c_float, ctypes.c_void_p]),
     "ccl_mlp_train": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
-                                       ctypes.c_void_p, ctypes.c_int32, ctypes.c_float,
-                                       ctypes.c_void_p]),
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                       ctypes.c_float, ctypes.c_void_p]),
     "ccl_mlp_pick": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                       ctypes.c_float, ctypes.c_float, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p]),
@@ -377,6 +381,12 @@ def ccl_autotune_measure(cfgs, r2: float, steps: int, reps: int = 3,
     return list(out)
 
 
+def ccl_wave_plan_rows(cfg) -> int:
+    r = ctypes.c_int32(0)
+    _check("ccl_wave_plan_rows", lib().ccl_wave_plan_rows(ctypes.byref(cfg), ctypes.byref(r)))
+    return r.value
+
+
 def ccl_costmodel_features(cfgs):
     import numpy as np
     arr = (ccl_tune_config * len(cfgs))(*cfgs)
@@ -419,16 +429,23 @@ def ccl_mlp_grad(h, n: int, x_ptr: int, t_ptr: int, stream=None):
                                               ctypes.c_void_p(t_ptr), _stream(stream)))
 
 
+def ccl_mlp_grad_weighted(h, n: int, x_ptr: int, t_ptr: int, w_ptr: int, stream=None):
+    _check("ccl_mlp_grad_weighted", lib().ccl_mlp_grad_weighted(
+        h, int(n), ctypes.c_void_p(x_ptr), ctypes.c_void_p(t_ptr),
+        ctypes.c_void_p(w_ptr) if w_ptr else None, _stream(stream)))
+
+
 def ccl_mlp_adam(h, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     _check("ccl_mlp_adam", lib().ccl_mlp_adam(h, float(lr), float(beta1), float(beta2),
                                               float(eps), _stream(stream)))
 
 
 def ccl_mlp_train(h, n: int, x_ptr: int, t_ptr: int, epochs: int, lr: float = 1e-3,
-                  stream=None):
+                  stream=None, w_ptr: int = 0):
     _check("ccl_mlp_train", lib().ccl_mlp_train(h, int(n), ctypes.c_void_p(x_ptr),
-                                                ctypes.c_void_p(t_ptr), int(epochs), float(lr),
-                                                _stream(stream)))
+                                                ctypes.c_void_p(t_ptr),
+                                                ctypes.c_void_p(w_ptr) if w_ptr else None,
+                                                int(epochs), float(lr), _stream(stream)))
 
 
 def ccl_mlp_pick(h, n: int, x_ptr: int, w_time: float, w_energy: float, scores_ptr: int,

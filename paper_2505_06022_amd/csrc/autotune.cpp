@@ -144,29 +144,40 @@ extern "C" ccl_status ccl_autotune_measure(int32_t n, const ccl_tune_config *cfg
     o.window_seconds = 0.0;
     o.runs_in_window = 0;
     if (want_energy) {
-      double j0 = 0.0, j1 = 0.0;
-      if (ccl_energy_read(device, s, &j0, nullptr) == CCL_OK) {
-        const auto t0 = std::chrono::steady_clock::now();
-        int runs = 0;
-        double el = 0.0;
-        do {
+      // The device counter advances in coarse steps (about once a second on
+      // the MI355X boxes): run back to back and take the energy between two
+      // counter updates at least energy_window_s apart, by the counter's own
+      // timestamps; J/step = mean power x the timed seconds per step.
+      double j = 0.0, ja = 0.0;
+      uint64_t ts = 0, ts0 = 0, tsa = 0;
+      bool have_a = false, done = false;
+      int runs = 0;
+      const auto t0 = std::chrono::steady_clock::now();
+      if (ccl_energy_read(device, s, &j, &ts0) == CCL_OK) {
+        while (!done) {
           st = run();
           if (st != CCL_OK) break;
           ++runs;
-          if (runs % 4 == 0 || med_s * runs >= energy_window_s) {
-            st = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-            if (st != CCL_OK) break;
-            el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+          if (ccl_energy_read(device, s, &j, &ts) != CCL_OK) break;
+          if (!have_a) {
+            if (ts != ts0) {
+              have_a = true;
+              ja = j;
+              tsa = ts;
+            }
+          } else if (static_cast<double>(ts - tsa) * 1e-9 >= energy_window_s) {
+            const double watts = (j - ja) / (static_cast<double>(ts - tsa) * 1e-9);
+            o.joules_per_step = watts * o.seconds_per_step;
+            o.window_seconds = static_cast<double>(ts - tsa) * 1e-9;
+            o.runs_in_window = runs;
+            done = true;
           }
-        } while (el < energy_window_s);
-        if (st != CCL_OK) break;
-        if (ccl_energy_read(device, s, &j1, nullptr) == CCL_OK) {
-          el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-          o.joules_per_step = (j1 - j0) / (static_cast<double>(runs) * steps);
-          o.window_seconds = el;
-          o.runs_in_window = runs;
+          const double el =
+              std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+          if (el > 10.0 * energy_window_s + 5.0) break;  // counter not advancing
         }
       }
+      if (st != CCL_OK) break;
       clear_error();
     }
   }
@@ -175,6 +186,25 @@ extern "C" ccl_status ccl_autotune_measure(int32_t n, const ccl_tune_config *cfg
   (void)hipStreamSynchronize(s);
   (void)hipFree(pool);
   return st;
+}
+
+extern "C" ccl_status ccl_wave_plan_rows(const ccl_tune_config *c, int32_t *rows) {
+  clear_error();
+  if (!c || !rows) return fail(CCL_E_INVALID, "NULL argument");
+  if ((c->dims != 2 && c->dims != 3) || c->nchunks < 1 || c->temporal_depth < 1 ||
+      c->temporal_depth > CCL_MAX_DEPTH || (c->dims == 3 && c->temporal_depth != 1))
+    return fail(CCL_E_INVALID, "malformed config");
+  for (int d = 0; d < c->dims; ++d)
+    if (c->shape[d] < 1) return fail(CCL_E_INVALID, "empty extent");
+  if (c->nchunks > c->shape[0]) return fail(CCL_E_RANGE, "more chunks than rows");
+  if (c->tile_rows > 0) {
+    *rows = c->tile_rows;
+    return CCL_OK;
+  }
+  *rows = c->dims == 2
+              ? wave2d_plan_rows(c->shape[0], c->shape[1], c->nchunks, c->temporal_depth)
+              : wave3d_plan_planes(c->shape[0], c->shape[1], c->shape[2], c->nchunks);
+  return CCL_OK;
 }
 
 extern "C" ccl_status ccl_costmodel_features(int32_t n, const ccl_tune_config *cfgs,
@@ -194,7 +224,10 @@ extern "C" ccl_status ccl_costmodel_features(int32_t n, const ccl_tune_config *c
     const double cells = n0 * n1 * n2;
     const double T = c.temporal_depth;
     const double K = c.nchunks;
-    const double rows = c.tile_rows > 0 ? c.tile_rows : 64.0;
+    int32_t planned = 0;
+    if (c.tile_rows == 0 && ccl_wave_plan_rows(&c, &planned) != CCL_OK)
+      return fail(CCL_E_INVALID, "config %d: %s", i, ccl_last_error());
+    const double rows = c.tile_rows > 0 ? c.tile_rows : planned;
     // halo bytes per step: 2 directions x (K-1) boundaries x (2T-1) rows/planes
     // of u^n and u^{n-1}, read and written, per T steps
     const double row_bytes = 4.0 * n1 * n2;

@@ -96,6 +96,44 @@ struct WaveChunkPlan {  // host-side plan of one chunk for one block of steps
   Box load_prev, load_cur;  // loadable index boxes (region of the buffer ∩ domain)
 };
 
+// Rows (2D) or planes (3D) per tile when the caller leaves it to the
+// library: every wave streams (rows + 2*halo) rows and the launch runs in
+// ceil(waves / slots) rounds of concurrently resident waves, so the rows are
+// chosen to minimise rounds * (rows + 2*halo).  `waves_of(rows)` is the
+// launch's wave count for a given rows value (non-increasing in rows).
+template <class F>
+int32_t plan_tile_rows(int64_t slots, int32_t halo, int32_t min_rows, int32_t max_rows,
+                       F waves_of) {
+  if (slots < 1) slots = 1;
+  if (max_rows < min_rows) max_rows = min_rows;
+  int32_t best = max_rows;
+  double best_cost = 1e300;
+  for (int64_t m = 1; m <= 64; ++m) {
+    // smallest rows whose wave count fits in m rounds
+    int32_t lo = min_rows, hi = max_rows;
+    if (waves_of(hi) > m * slots) continue;
+    while (lo < hi) {
+      const int32_t mid = lo + (hi - lo) / 2;
+      if (waves_of(mid) <= m * slots)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    const int64_t w = waves_of(lo);
+    const double rounds = static_cast<double>((w + slots - 1) / slots);
+    const double cost = rounds * (lo + 2.0 * halo);
+    if (cost < best_cost - 1e-9) {
+      best_cost = cost;
+      best = lo;
+    }
+    if (lo == min_rows) break;
+  }
+  return best;
+}
+
+int32_t wave2d_plan_rows(int64_t ny, int64_t nx, int32_t K, int32_t T);
+int32_t wave3d_plan_planes(int64_t nz, int64_t ny, int64_t nx, int32_t K);
+
 ccl_status launch_wave2d(int32_t depth, bool in_place, float r2, int32_t tile_rows,
                          const WaveChunkPlan *plans, int32_t nplans, hipStream_t stream);
 ccl_status launch_wave3d(int32_t depth, bool in_place, float r2, int32_t tile_rows,

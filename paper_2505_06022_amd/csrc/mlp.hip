@@ -28,10 +28,12 @@ __device__ __forceinline__ void load_params(float *sp, const float *p) {
   for (int i = threadIdx.x; i < kParams; i += blockDim.x) sp[i] = p[i];
 }
 
-// Partial gradient of L = 1/(2n) sum (y - t)^2 over this block's samples.
+// Partial gradient of L = 1/(2n) sum w (y - t)^2 over this block's samples
+// (w = 1 where no weights are given).
 __global__ __launch_bounds__(kThreads) void mlp_grad_kernel(const float *__restrict__ params,
                                                             const float *__restrict__ x,
-                                                            const float *__restrict__ t, int n,
+                                                            const float *__restrict__ t,
+                                                            const float *__restrict__ w, int n,
                                                             float *__restrict__ partials,
                                                             float *__restrict__ loss_partials) {
   __shared__ float P[kParams];
@@ -39,6 +41,7 @@ __global__ __launch_bounds__(kThreads) void mlp_grad_kernel(const float *__restr
   __shared__ float H1[kS][kHid];
   __shared__ float H2[kS][kHid];
   __shared__ float DY[kS][kOut];
+  __shared__ float WR[kS][kOut];
   // H2 and H1 are overwritten in place by the back-propagated D2 and D1
   // once every reader of the activations is done (56 KB of LDS in all).
   float(*D2)[kHid] = H2;
@@ -72,14 +75,17 @@ __global__ __launch_bounds__(kThreads) void mlp_grad_kernel(const float *__restr
     const int s = tid / kOut, o = tid - s * kOut;
     float acc = P[ob3 + o];
     for (int k = 0; k < kHid; ++k) acc = fmaf(P[oW3 + o * kHid + k], H2[s][k], acc);
-    const float r = s < ns ? acc - t[static_cast<int64_t>(s0 + s) * kOut + o] : 0.0f;
-    DY[s][o] = r;  // residual; scaled by 1/n below
+    const int64_t q = static_cast<int64_t>(s0 + s) * kOut + o;
+    const float r = s < ns ? acc - t[q] : 0.0f;
+    const float wt = (s < ns && w) ? w[q] : 1.0f;
+    DY[s][o] = r * wt;        // w * residual; scaled by 1/n below
+    WR[s][o] = r;
   }
   __syncthreads();
   if (tid == 0) {
     float l = 0.0f;
     for (int s = 0; s < ns; ++s)
-      for (int o = 0; o < kOut; ++o) l = fmaf(DY[s][o], DY[s][o], l);
+      for (int o = 0; o < kOut; ++o) l = fmaf(DY[s][o], WR[s][o], l);
     loss_partials[blockIdx.x] = l;
   }
   __syncthreads();
@@ -345,21 +351,26 @@ extern "C" ccl_status ccl_mlp_forward(ccl_mlp *M, int32_t n, const float *x, flo
   return hip_check(hipGetLastError(), "mlp_forward_kernel launch");
 }
 
-extern "C" ccl_status ccl_mlp_grad(ccl_mlp *M, int32_t n, const float *x, const float *t,
-                                   void *hip_stream) {
+extern "C" ccl_status ccl_mlp_grad_weighted(ccl_mlp *M, int32_t n, const float *x,
+                                            const float *t, const float *w, void *hip_stream) {
   clear_error();
   if (!M || n < 1 || !x || !t) return fail(CCL_E_INVALID, "bad argument");
   ccl_status st = mlp_reserve(M, n);
   if (st != CCL_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const int blocks = (n + kS - 1) / kS;
-  hipLaunchKernelGGL(mlp_grad_kernel, dim3(blocks), dim3(kThreads), 0, s, M->params, x, t, n,
+  hipLaunchKernelGGL(mlp_grad_kernel, dim3(blocks), dim3(kThreads), 0, s, M->params, x, t, w, n,
                      M->partials, M->loss_partials);
   st = hip_check(hipGetLastError(), "mlp_grad_kernel launch");
   if (st != CCL_OK) return st;
   hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kParams + 255) / 256), dim3(256), 0, s,
                      M->partials, M->loss_partials, blocks, n, M->grads, M->loss);
   return hip_check(hipGetLastError(), "mlp_reduce_kernel launch");
+}
+
+extern "C" ccl_status ccl_mlp_grad(ccl_mlp *M, int32_t n, const float *x, const float *t,
+                                   void *hip_stream) {
+  return ccl_mlp_grad_weighted(M, n, x, t, nullptr, hip_stream);
 }
 
 extern "C" ccl_status ccl_mlp_adam(ccl_mlp *M, float lr, float b1, float b2, float eps,
@@ -378,11 +389,12 @@ extern "C" ccl_status ccl_mlp_adam(ccl_mlp *M, float lr, float b1, float b2, flo
 }
 
 extern "C" ccl_status ccl_mlp_train(ccl_mlp *M, int32_t n, const float *x, const float *t,
-                                    int32_t epochs, float lr, void *hip_stream) {
+                                    const float *w, int32_t epochs, float lr,
+                                    void *hip_stream) {
   clear_error();
   if (!M || epochs < 0) return fail(CCL_E_INVALID, "bad argument");
   for (int e = 0; e < epochs; ++e) {
-    ccl_status st = ccl_mlp_grad(M, n, x, t, hip_stream);
+    ccl_status st = ccl_mlp_grad_weighted(M, n, x, t, w, hip_stream);
     if (st != CCL_OK) return st;
     st = ccl_mlp_adam(M, lr, 0.9f, 0.999f, 1e-8f, hip_stream);
     if (st != CCL_OK) return st;

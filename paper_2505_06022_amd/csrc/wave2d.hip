@@ -68,17 +68,51 @@ bool fits_i32(int64_t v) { return v >= INT32_MIN && v <= INT32_MAX; }
 
 }  // namespace
 
-int32_t wave2d_auto_rows(int32_t depth, int64_t rows, int64_t cols, int32_t nchunks) {
-  // Aim at ~8 waves per SIMD (256 CUs x 4 SIMDs) while keeping the 2T-row
-  // re-read per segment below ~1/8 of the segment.
-  const int64_t strips = (cols + w2::strip_width(depth) - 1) / w2::strip_width(depth);
-  const int64_t target_waves = 8192;
-  int64_t r = (rows * strips + target_waves - 1) / target_waves;
-  r = std::max<int64_t>(r, 16 * depth);
-  r = std::max<int64_t>(r, 16);
-  r = (r + 7) / 8 * 8;
-  (void)nchunks;
-  return static_cast<int32_t>(std::min<int64_t>(r, 1 << 20));
+// Concurrent waves the device holds for the depth-T kernel (cached).
+static int64_t wave_slots(int T, bool in_place) {
+  static int64_t cache[2][CCL_MAX_DEPTH + 1] = {};
+  int64_t &c = cache[in_place ? 1 : 0][T];
+  if (c > 0) return c;
+  const void *fn = nullptr;
+  switch (in_place ? 0 : T) {
+    case 0: fn = reinterpret_cast<const void *>(&wave2d_kernel<1, true>); break;
+    case 1: fn = reinterpret_cast<const void *>(&wave2d_kernel<1, false>); break;
+    case 2: fn = reinterpret_cast<const void *>(&wave2d_kernel<2, false>); break;
+    case 3: fn = reinterpret_cast<const void *>(&wave2d_kernel<3, false>); break;
+    case 4: fn = reinterpret_cast<const void *>(&wave2d_kernel<4, false>); break;
+    case 5: fn = reinterpret_cast<const void *>(&wave2d_kernel<5, false>); break;
+    case 6: fn = reinterpret_cast<const void *>(&wave2d_kernel<6, false>); break;
+    case 7: fn = reinterpret_cast<const void *>(&wave2d_kernel<7, false>); break;
+    default: fn = reinterpret_cast<const void *>(&wave2d_kernel<8, false>); break;
+  }
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, 0) != hipSuccess ||
+      per_cu < 1) {
+    return 1024;  // planning only; any positive value gives a valid launch
+  }
+  c = static_cast<int64_t>(cus) * per_cu * kWavesPerBlock;
+  return c;
+}
+
+// The rows the launcher would pick for a domain split into K row chunks
+// (buffers starting at the domain's first column).
+int32_t wave2d_plan_rows(int64_t ny, int64_t nx, int32_t K, int32_t T) {
+  const int SW = w2::strip_width(T);
+  const int64_t nstrips = (nx + SW - 1) / SW;
+  int64_t rows_max = 0;
+  for (int k = 0; k < K; ++k) rows_max = std::max<int64_t>(rows_max, (k + 1) * ny / K - k * ny / K);
+  auto waves_of = [&](int32_t r) {
+    int64_t w = 0;
+    for (int k = 0; k < K; ++k) {
+      const int64_t rows = (k + 1) * ny / K - k * ny / K;
+      w += ((rows + r - 1) / r) * nstrips;
+    }
+    return w;
+  };
+  return plan_tile_rows(wave_slots(T, T == 1), T, std::max(8, T),
+                        static_cast<int32_t>(std::max<int64_t>(rows_max, 8)), waves_of);
 }
 
 ccl_status launch_wave2d(int32_t depth, bool in_place, float r2, int32_t tile_rows,
@@ -99,15 +133,11 @@ ccl_status launch_wave2d(int32_t depth, bool in_place, float r2, int32_t tile_ro
     a.dom.gy1 = static_cast<int32_t>(dom.hi[0]);
     a.dom.gx0 = static_cast<int32_t>(dom.lo[1]);
     a.dom.gx1 = static_cast<int32_t>(dom.hi[1]);
-    int64_t rows_max = 0, cols_max = 0;
+    int64_t rows_max = 0;
     for (int k = 0; k < n; ++k) {
       const Box &cb = plans[first + k].chunk;
       rows_max = std::max<int64_t>(rows_max, cb.hi[0] - cb.lo[0]);
-      cols_max = std::max<int64_t>(cols_max, cb.hi[1] - cb.lo[1]);
     }
-    a.tile_rows = tile_rows > 0 ? tile_rows
-                                : wave2d_auto_rows(depth, rows_max * n, cols_max, n);
-    int64_t tiles = 0;
     for (int k = 0; k < n; ++k) {
       const WaveChunkPlan &P = plans[first + k];
       w2::Chunk &C = a.ch[k];
@@ -153,7 +183,22 @@ ccl_status launch_wave2d(int32_t depth, bool in_place, float r2, int32_t tile_ro
                       "chunk %d: buffers must be 16-byte aligned, with pitch a multiple of 4 and "
                       "the same region column offset modulo 4", first + k);
       }
-      const int64_t segs = (P.chunk.hi[0] - P.chunk.lo[0] + a.tile_rows - 1) / a.tile_rows;
+    }
+    auto waves_of = [&](int32_t r) {
+      int64_t w = 0;
+      for (int k = 0; k < n; ++k)
+        w += ((a.ch[k].cy1 - a.ch[k].cy0 + r - 1) / r) * static_cast<int64_t>(a.ch[k].nstrips);
+      return w;
+    };
+    a.tile_rows = tile_rows > 0
+                      ? tile_rows
+                      : plan_tile_rows(wave_slots(depth, in_place), depth, std::max(8, depth),
+                                       static_cast<int32_t>(std::max<int64_t>(rows_max, 8)),
+                                       waves_of);
+    int64_t tiles = 0;
+    for (int k = 0; k < n; ++k) {
+      w2::Chunk &C = a.ch[k];
+      const int64_t segs = (C.cy1 - C.cy0 + a.tile_rows - 1) / a.tile_rows;
       if (!fits_i32(tiles)) return fail(CCL_E_RANGE, "too many tiles");
       C.tile_begin = static_cast<int32_t>(tiles);
       tiles += segs * C.nstrips;

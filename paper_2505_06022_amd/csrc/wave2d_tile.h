@@ -27,7 +27,10 @@
 namespace ccl {
 namespace w2 {
 
-constexpr int kPrefetch = 3;
+#ifndef CCL_W2_PREFETCH
+#define CCL_W2_PREFETCH 3
+#endif
+constexpr int kPrefetch = CCL_W2_PREFETCH;  // rows loaded ahead of use
 
 // Overlap columns per side and output columns per strip for depth T.
 __host__ __device__ constexpr int overlap(int T) { return 4 * ((T + 3) / 4); }

@@ -243,7 +243,38 @@ __global__ __launch_bounds__(kThreads) void wave3d_kernel(const W3Args a) {
 
 bool fits_i32(int64_t v) { return v >= INT32_MIN && v <= INT32_MAX; }
 
+int64_t wave_slots3d() {
+  static int64_t cached = 0;
+  if (cached > 0) return cached;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void *>(&wave3d_kernel), kThreads, 0) != hipSuccess ||
+      per_cu < 1)
+    return 1024;
+  cached = static_cast<int64_t>(cus) * per_cu * kWavesPerBlock;
+  return cached;
+}
+
 }  // namespace
+
+// The planes per tile the launcher would pick for a domain split into K
+// plane chunks.
+int32_t wave3d_plan_planes(int64_t nz, int64_t ny, int64_t nx, int32_t K) {
+  int64_t zmax = 0;
+  for (int k = 0; k < K; ++k) zmax = std::max<int64_t>(zmax, (k + 1) * nz / K - k * nz / K);
+  auto waves_of = [&](int32_t p) {
+    int64_t w = 0;
+    for (int k = 0; k < K; ++k) {
+      const int64_t z = (k + 1) * nz / K - k * nz / K;
+      w += ((z + p - 1) / p) * ((nx + 255) / 256) * ((ny + kRows - 1) / kRows);
+    }
+    return w;
+  };
+  return plan_tile_rows(wave_slots3d(), 1, 4, static_cast<int32_t>(std::max<int64_t>(zmax, 4)),
+                        waves_of);
+}
 
 ccl_status launch_wave3d(int32_t depth, bool in_place, float r2, int32_t tile_planes,
                          const WaveChunkPlan *plans, int32_t nplans, hipStream_t stream) {
@@ -255,12 +286,23 @@ ccl_status launch_wave3d(int32_t depth, bool in_place, float r2, int32_t tile_pl
     memset(&a, 0, sizeof(a));
     a.nchunks = n;
     a.r2 = r2;
-    a.tile_planes = tile_planes > 0 ? tile_planes : 0;
-    if (a.tile_planes == 0) {
+    if (tile_planes > 0) {
+      a.tile_planes = tile_planes;
+    } else {
       int64_t zmax = 0;
       for (int k = 0; k < n; ++k)
         zmax = std::max<int64_t>(zmax, plans[first + k].chunk.hi[0] - plans[first + k].chunk.lo[0]);
-      a.tile_planes = static_cast<int32_t>(std::min<int64_t>(zmax, 128));
+      auto waves_of = [&](int32_t p) {
+        int64_t w = 0;
+        for (int k = 0; k < n; ++k) {
+          const Box &cb = plans[first + k].chunk;
+          w += ((cb.hi[0] - cb.lo[0] + p - 1) / p) * ((cb.hi[2] - cb.lo[2] + 255) / 256) *
+               ((cb.hi[1] - cb.lo[1] + kRows - 1) / kRows);
+        }
+        return w;
+      };
+      a.tile_planes = plan_tile_rows(wave_slots3d(), 1, 4,
+                                     static_cast<int32_t>(std::max<int64_t>(zmax, 4)), waves_of);
     }
     int64_t tiles = 0;
     for (int k = 0; k < n; ++k) {

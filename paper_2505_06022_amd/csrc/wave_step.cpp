@@ -14,8 +14,6 @@
 
 namespace ccl {
 
-int32_t wave2d_auto_rows(int32_t depth, int64_t rows, int64_t cols, int32_t nchunks);
-
 namespace {
 
 WaveField field_of(const ccl_chunk_buffer &b) {

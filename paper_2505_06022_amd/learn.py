@@ -75,10 +75,11 @@ def train(data_path, model_path, epochs=4000, lr=3e-3, seed=0):
     with open(data_path) as f:
         doc = json.load(f)
     X = np.array(doc["features"], dtype=np.float64)
-    Y = tune.targets_of(doc["samples"])
-    m = tune.CostModel.fit(X, Y, epochs=epochs, lr=lr, seed=seed)
+    Y, W = tune.targets_of(doc["samples"])
+    m = tune.CostModel.fit(X, Y, W, epochs=epochs, lr=lr, seed=seed)
     pred = m.predict(X)
-    rmse = np.sqrt(np.mean((pred - Y) ** 2, axis=0))
+    rmse = np.array([np.sqrt(np.sum(W[:, k] * (pred[:, k] - Y[:, k]) ** 2) / max(W[:, k].sum(), 1))
+                     for k in range(2)])
     m.meta["train_rmse_log"] = rmse.tolist()
     m.save(model_path)
     _log(f"trained on {len(X)} samples in {m.meta['train_seconds']:.2f} s, "

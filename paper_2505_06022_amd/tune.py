@@ -2,7 +2,7 @@
 
 * ``candidates(shape)`` — the discrete config space of one shape: chunk
   counts K in {1, 2, 4, 8, 16} (K <= rows), rows per tile in
-  {16, 32, 64, 128}, temporal depth T in 1..8 (2D) or 1 (3D).
+  {auto, 16, 32, 64, 128}, temporal depth T in 1..8 (2D) or 1 (3D).
 * ``measure(cfgs)`` — time (and device energy) per step of each config,
   measured by the library's autotuner on the GPU (ccl_autotune_measure).
 * ``CostModel`` — the 12-64-64-2 MLP, trained on the GPU by the library's
@@ -30,7 +30,7 @@ from . import (CCL_MLP_NPARAMS, CCL_MLP_PARAMS, CCL_MLP_LOSS, ccl_autotune_measu
                ccl_mlp_pick, ccl_mlp_train, make_tune_config)
 
 K_SET = (1, 2, 4, 8, 16)
-ROWS_SET = (16, 32, 64, 128)
+ROWS_SET = (0, 16, 32, 64, 128)  # 0: the library's occupancy-aware choice
 T_SET_2D = tuple(range(1, 9))
 
 OBJECTIVES = {"time": (1.0, 0.0), "energy": (0.0, 1.0), "edp": (1.0, 1.0)}
@@ -82,11 +82,18 @@ def sweep(shape, r2=0.25, reps=3, energy_window_s=0.0):
 
 
 def targets_of(samples):
-    t = np.array([[math.log(s["s_per_cell_step"]),
-                   math.log(s["j_per_cell_step"]) if np.isfinite(s["j_per_cell_step"]) and
-                   s["j_per_cell_step"] > 0 else math.log(s["s_per_cell_step"])]
-                  for s in samples], dtype=np.float64)
-    return t
+    """Targets [log s/cell-step, log J/cell-step] and weights (energy weight 0
+    where no energy was measured; its target slot then holds 0)."""
+    t = np.zeros((len(samples), 2))
+    w = np.ones((len(samples), 2))
+    for i, s in enumerate(samples):
+        t[i, 0] = math.log(s["s_per_cell_step"])
+        e = s.get("j_per_cell_step")
+        if e is not None and np.isfinite(e) and e > 0:
+            t[i, 1] = math.log(e)
+        else:
+            w[i, 1] = 0.0
+    return t, w
 
 
 @dataclass
@@ -117,16 +124,24 @@ class CostModel:
         return pack(ws, bs)
 
     @classmethod
-    def fit(cls, X, Y, epochs=3000, lr=3e-3, seed=0, stream=None):
+    def fit(cls, X, Y, W=None, epochs=3000, lr=3e-3, seed=0, stream=None):
+        """W (n x 2, optional): 1 where a target was measured, 0 where not."""
         import torch
+        W = np.ones_like(Y) if W is None else np.asarray(W, np.float64)
         xs = Standardiser(X.mean(0), np.where(X.std(0) > 1e-9, X.std(0), 1.0))
-        ys = Standardiser(Y.mean(0), np.where(Y.std(0) > 1e-9, Y.std(0), 1.0))
+        ym = np.array([np.sum(W[:, k] * Y[:, k]) / max(W[:, k].sum(), 1) for k in range(2)])
+        yv = np.array([np.sum(W[:, k] * (Y[:, k] - ym[k]) ** 2) / max(W[:, k].sum(), 1)
+                       for k in range(2)])
+        ys = Standardiser(ym, np.where(yv > 1e-18, np.sqrt(yv), 1.0))
         m = cls(cls.init_params(seed), xs, ys, meta=dict(epochs=epochs, lr=lr, seed=seed,
-                                                         n=int(len(X))))
+                                                         n=int(len(X)),
+                                                         n_energy=int(W[:, 1].sum())))
         xd = torch.from_numpy(xs.apply(X)).cuda()
-        yd = torch.from_numpy(ys.apply(Y)).cuda()
+        yd = torch.from_numpy(np.where(W > 0, ys.apply(Y), 0.0).astype(np.float32)).cuda()
+        wd = torch.from_numpy(W.astype(np.float32)).cuda()
         t0 = time.perf_counter()
-        ccl_mlp_train(m.handle, len(X), xd.data_ptr(), yd.data_ptr(), epochs, lr, stream)
+        ccl_mlp_train(m.handle, len(X), xd.data_ptr(), yd.data_ptr(), epochs, lr, stream,
+                      w_ptr=wd.data_ptr())
         torch.cuda.synchronize()
         m.meta["train_seconds"] = time.perf_counter() - t0
         m.meta["final_loss"] = float(ccl_mlp_get(m.handle, CCL_MLP_LOSS)[0])

@@ -73,6 +73,32 @@ def test_forward_grad_loss_vs_oracle(n):
     ccl.ccl_mlp_destroy(h)
 
 
+def test_weighted_grad_vs_oracle():
+    """Per-output weights (a mask over the second output) against the oracle."""
+    import paper_2505_06022_amd as ccl
+    from paper_2505_06022_amd.tune import unpack
+    n = 333
+    ws, bs, x, t, p = make(11, n)
+    w = np.ones((n, 2))
+    w[::3, 1] = 0.0
+    w[5::7, 0] = 0.5
+    h = ccl.ccl_mlp_create(p)
+    xd = torch.from_numpy(x.astype(np.float32)).cuda()
+    td = torch.from_numpy(t.astype(np.float32)).cuda()
+    wd = torch.from_numpy(w.astype(np.float32)).cuda()
+    ccl.ccl_mlp_grad_weighted(h, n, xd.data_ptr(), td.data_ptr(), wd.data_ptr())
+    torch.cuda.synchronize()
+    acts = omlp.forward(ws, bs, x)
+    gw, gb = omlp.backward(ws, bs, acts, t, w)
+    uw, ub = unpack(ccl.ccl_mlp_get(h, ccl.CCL_MLP_GRADS))
+    for li in range(3):
+        assert rel_l2(uw[li], gw[li]) <= 1e-4 and rel_l2(ub[li], gb[li]) <= 1e-4
+    loss = ccl.ccl_mlp_get(h, ccl.CCL_MLP_LOSS)[0]
+    want = omlp.loss(acts[-1], t, w)
+    assert abs(loss - want) <= 1e-5 * max(1.0, want)
+    ccl.ccl_mlp_destroy(h)
+
+
 def test_adam_steps_vs_oracle():
     import paper_2505_06022_amd as ccl
     from paper_2505_06022_amd.tune import pack, unpack

@@ -153,6 +153,29 @@ def test_mlp_gradcheck():
                 assert abs(fd - gflat[idx]) <= 1e-7 * max(1.0, abs(fd)) + 1e-9
 
 
+def test_mlp_weighted_gradcheck():
+    """Weighted loss: finite differences again, with a mask on output 2."""
+    ws, bs = synth.mlp_params(SIZES, seed=12)
+    x, t = synth.mlp_batch(10, 12, 2, seed=13)
+    w = np.ones((10, 2))
+    w[::2, 1] = 0.0
+    w[3, 0] = 0.25
+    acts = mlp.forward(ws, bs, x)
+    dws, _ = mlp.backward(ws, bs, acts, t, w)
+    h = 1e-6
+    for li in range(3):
+        flat = ws[li].reshape(-1)
+        for idx in (0, flat.size // 2, flat.size - 1):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp = mlp.loss(mlp.forward(ws, bs, x)[-1], t, w)
+            flat[idx] = old - h
+            lm = mlp.loss(mlp.forward(ws, bs, x)[-1], t, w)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - dws[li].reshape(-1)[idx]) <= 1e-7 * max(1.0, abs(fd)) + 1e-9
+
+
 def test_mlp_forward_linear_region():
     """With every pre-activation positive, the net is the affine map
     W3 W2 W1 x + (W3 W2 b1 + W3 b2 + b3)."""

@@ -7,11 +7,11 @@ from paper_2505_06022_amd import tune
 
 def test_candidate_space():
     c2 = tune.candidates((1024, 4096))
-    assert len(c2) == 5 * 4 * 8
+    assert len(c2) == 5 * 5 * 8
     assert {c.temporal_depth for c in c2} == set(range(1, 9))
-    assert len(tune.candidates((8, 4096))) == 4 * 4 * 8  # K = 16 > 8 rows dropped
+    assert len(tune.candidates((8, 4096))) == 4 * 5 * 8  # K = 16 > 8 rows dropped
     c3 = tune.candidates((96, 768, 768))
-    assert {c.temporal_depth for c in c3} == {1} and len(c3) == 5 * 4
+    assert {c.temporal_depth for c in c3} == {1} and len(c3) == 5 * 5
 
 
 def test_sample_space_seeded():
@@ -35,11 +35,12 @@ def test_pack_unpack_roundtrip():
         assert np.array_equal(a.astype(np.float32), b)
 
 
-def test_targets_fall_back_to_time_without_energy():
+def test_targets_mask_missing_energy():
     s = [dict(s_per_cell_step=1e-12, j_per_cell_step=float("nan")),
          dict(s_per_cell_step=2e-12, j_per_cell_step=3e-10)]
-    t = tune.targets_of(s)
-    assert t[0, 1] == t[0, 0] and np.isclose(t[1, 1], np.log(3e-10))
+    t, w = tune.targets_of(s)
+    assert w[0, 1] == 0 and w[1, 1] == 1 and np.all(w[:, 0] == 1)
+    assert np.isclose(t[1, 1], np.log(3e-10)) and np.isclose(t[0, 0], np.log(1e-12))
 
 
 def test_steps_for():
