@@ -1,12 +1,15 @@
 """Learned launch-config selection: collect, train, evaluate.
 
     python -m paper_2505_06022_amd.learn collect  --out DIR [--shapes 250 --per-shape 16]
+    python -m paper_2505_06022_amd.learn energy   --out DIR [--count 120 --window 1.0]
     python -m paper_2505_06022_amd.learn train    --data DIR/samples.json --model MODEL.json
     python -m paper_2505_06022_amd.learn evaluate --model MODEL.json --out DIR [--shapes 200]
 
-collect  : seeded training shapes (2D, sides log-uniform on 256..16384), a
-           seeded subset of each shape's candidates, each measured by the
-           library's autotuner (time; device energy on an energy subset);
+collect  : seeded training shapes (2D sides log-uniform on 256..16384, 3D
+           sides 64..768), a seeded subset of each shape's candidates, each
+           timed by the library's autotuner;
+energy   : device energy for a seeded subset of those samples (each needs a
+           window spanning two updates of the ~1 Hz energy counter);
 train    : the 12-64-64-2 MLP fitted on the GPU by the library's kernels;
 evaluate : seeded held-out shapes never seen in training, each swept
            exhaustively (every candidate measured); the model's pick is
@@ -34,8 +37,8 @@ def _log(msg):
     print(f"[learn] {msg}", flush=True)
 
 
-def collect(out_dir, n_shapes=250, per_shape=16, energy_configs=0, energy_window_s=2.5,
-            n_shapes_3d=40):
+def collect(out_dir, n_shapes=250, per_shape=16, n_shapes_3d=40):
+    """Time samples of the seeded training configs, saved to samples.json."""
     from . import ccl_costmodel_features, tune
     os.makedirs(out_dir, exist_ok=True)
     shapes, cfgs = tune.sample_space(n_shapes, TRAIN_SHAPE_SEED, per_shape, SAMPLE_SEED,
@@ -43,31 +46,61 @@ def collect(out_dir, n_shapes=250, per_shape=16, energy_configs=0, energy_window
     _log(f"{len(cfgs)} configs over {len(shapes)} shapes")
     t0 = time.perf_counter()
     samples = []
-    # measure shape by shape so progress is visible
     by_shape = {}
     for c in cfgs:
         by_shape.setdefault(tuple(c.shape[:c.dims]), []).append(c)
+    order = []
     for i, (sh, cs) in enumerate(by_shape.items()):
         samples.extend(tune.measure(cs))
-        if (i + 1) % 25 == 0:
+        order.extend(cs)
+        if (i + 1) % 10 == 0:
             _log(f"  {i + 1}/{len(by_shape)} shapes, {time.perf_counter() - t0:.0f} s")
-    if energy_configs:
-        rs = np.random.default_rng(SAMPLE_SEED + 1)
-        pick = sorted(rs.choice(len(cfgs), size=min(energy_configs, len(cfgs)), replace=False))
-        _log(f"energy windows for {len(pick)} configs")
-        for j in pick:
-            r = tune.measure([cfgs[j]], energy_window_s=energy_window_s)[0]
-            samples[j]["j_per_step"] = r["j_per_step"]
-            samples[j]["j_per_cell_step"] = r["j_per_cell_step"]
-            samples[j]["window_s"] = r["window_s"]
-    X = ccl_costmodel_features(cfgs)
+    X = ccl_costmodel_features(order)
     doc = dict(samples=samples, features=X.tolist(),
-               meta=dict(shapes=len(shapes), configs=len(cfgs),
+               meta=dict(shapes=len(shapes), configs=len(order),
                          seconds=time.perf_counter() - t0))
-    with open(os.path.join(out_dir, "samples.json"), "w") as f:
-        json.dump(doc, f)
-    _log(f"collected in {time.perf_counter() - t0:.0f} s")
+    _save(out_dir, doc)
+    _log(f"collected {len(samples)} time samples in {time.perf_counter() - t0:.0f} s")
     return doc
+
+
+def _save(out_dir, doc):
+    tmp = os.path.join(out_dir, "samples.json.tmp")
+    with open(tmp, "w") as f:
+        json.dump(doc, f)
+    os.replace(tmp, os.path.join(out_dir, "samples.json"))
+
+
+def energy(out_dir, count=120, window_s=1.0, budget_s=600.0):
+    """Adds device-energy labels to a seeded subset of the collected samples
+    (resumable: samples that already have one are skipped)."""
+    from . import make_tune_config, tune
+    path = os.path.join(out_dir, "samples.json")
+    with open(path) as f:
+        doc = json.load(f)
+    samples = doc["samples"]
+    rs = np.random.default_rng(SAMPLE_SEED + 1)
+    pick = sorted(rs.choice(len(samples), size=min(count, len(samples)), replace=False))
+    t0 = time.perf_counter()
+    done = 0
+    for n, j in enumerate(pick):
+        s = samples[j]
+        if s.get("j_per_cell_step") is not None and np.isfinite(s["j_per_cell_step"]):
+            done += 1
+            continue
+        shape, K, T, rows = s["key"]
+        c = make_tune_config(shape, K, T, rows)
+        r = tune.measure([c], energy_window_s=window_s)[0]
+        s["j_per_step"], s["j_per_cell_step"] = r["j_per_step"], r["j_per_cell_step"]
+        s["window_s"] = r["window_s"]
+        done += 1
+        if done % 5 == 0:
+            _log(f"  energy {done}/{len(pick)}, {time.perf_counter() - t0:.0f} s")
+            _save(out_dir, doc)
+        if time.perf_counter() - t0 > budget_s:
+            break
+    _save(out_dir, doc)
+    _log(f"energy labels: {done}/{len(pick)} in {time.perf_counter() - t0:.0f} s")
 
 
 def train(data_path, model_path, epochs=4000, lr=3e-3, seed=0):
@@ -87,66 +120,104 @@ def train(data_path, model_path, epochs=4000, lr=3e-3, seed=0):
     return m
 
 
-def evaluate(model_path, out_dir, n_shapes=200, energy_shapes=0, energy_window_s=2.5):
-    """Exhaustive sweep of every held-out shape, and the ratio of the
-    model's pick to the measured best (time; energy on a subset)."""
+def evaluate(model_path, out_dir, n_shapes=200, start=0, count=None, budget_s=1e9,
+             reps=2, target_cell_steps=1.5e9):
+    """Exhaustive time sweep of held-out shapes [start, start+count): every
+    candidate measured; rows written to evaluation_part_<start>.json."""
     from . import tune
     os.makedirs(out_dir, exist_ok=True)
     import synth
     shapes = synth.cost_model_shapes(n_shapes, HELD_OUT_SEED)
+    count = len(shapes) - start if count is None else count
     model = tune.CostModel.load(model_path)
     untrained = tune.CostModel(tune.CostModel.init_params(1), model.xs, model.ys)
     rows = []
     t0 = time.perf_counter()
-    for i, sh in enumerate(shapes):
-        cfgs, res = tune.sweep(sh)
+    path = os.path.join(out_dir, f"evaluation_part_{start:04d}.json")
+    for i, sh in enumerate(shapes[start:start + count]):
+        cfgs = tune.candidates(sh)
+        res = tune.measure(cfgs, reps=reps,
+                           steps=tune.steps_for(sh, target_cell_steps=target_cell_steps))
         t = np.array([r["s_per_step"] for r in res])
         best = int(np.argmin(t))
-        pick_cfg, pick = model.pick(sh, "time")
-        ucfg, upick = untrained.pick(sh, "time")
-        default = next(j for j, c in enumerate(cfgs)
-                       if c.nchunks == 1 and c.temporal_depth == 1 and c.tile_rows == 64)
-        rows.append(dict(shape=list(sh), best=tune.cfg_key(cfgs[best]),
-                         pick=tune.cfg_key(cfgs[pick]), t_best=t[best], t_pick=t[pick],
-                         t_default=t[default], t_untrained=t[upick],
-                         ratio=t[pick] / t[best], ratio_default=t[default] / t[best],
+        keys = [tune.cfg_key(c) for c in cfgs]
+        pick_cfg, _ = model.pick(sh, "time")
+        ucfg, _ = untrained.pick(sh, "time")
+        pick = keys.index(tune.cfg_key(pick_cfg))
+        upick = keys.index(tune.cfg_key(ucfg))
+        default = keys.index((tuple(sh), 1, 1, 0))
+        rows.append(dict(index=start + i, shape=list(sh), best=keys[best], pick=keys[pick],
+                         t_best=t[best], t_pick=t[pick], t_default=t[default],
+                         t_untrained=t[upick], ratio=t[pick] / t[best],
+                         ratio_default=t[default] / t[best],
                          ratio_untrained=t[upick] / t[best]))
-        if (i + 1) % 20 == 0:
-            _log(f"  {i + 1}/{len(shapes)} shapes swept, {time.perf_counter() - t0:.0f} s")
+        _log(f"  shape {start + i} {sh}: pick/best {t[pick] / t[best]:.3f}, "
+             f"default/best {t[default] / t[best]:.2f} ({time.perf_counter() - t0:.0f} s)")
+        with open(path, "w") as f:
+            json.dump(rows, f)
+        if time.perf_counter() - t0 > budget_s:
+            break
+    model.close()
+    untrained.close()
+    return rows
+
+
+def energy_check(model_path, out_dir, n_shapes=200, count=4, window_s=1.0, top=3):
+    """For the first held-out shapes: device energy of the model's energy
+    pick and of the `top` fastest configs of the time sweep (the energy
+    judge is restricted to those, since a full energy sweep would need ~2 s
+    of counter time per candidate)."""
+    from . import tune
+    import synth
+    shapes = synth.cost_model_shapes(n_shapes, HELD_OUT_SEED)[:count]
+    model = tune.CostModel.load(model_path)
+    out = []
+    for sh in shapes:
+        cfgs = tune.candidates(sh)
+        res = tune.measure(cfgs, reps=2, steps=tune.steps_for(sh, target_cell_steps=1.5e9))
+        keys = [tune.cfg_key(c) for c in cfgs]
+        order = list(np.argsort([r["s_per_step"] for r in res])[:top])
+        pick_cfg, _ = model.pick(sh, "energy")
+        pick = keys.index(tune.cfg_key(pick_cfg))
+        idx = sorted(set(int(j) for j in order) | {pick})
+        meas = tune.measure([cfgs[j] for j in idx], energy_window_s=window_s)
+        e = {j: m["j_per_step"] for j, m in zip(idx, meas)}
+        best = min(e, key=e.get)
+        out.append(dict(shape=list(sh), pick=keys[pick], best=keys[best], e_pick=e[pick],
+                        e_best=e[best], ratio=e[pick] / e[best]))
+        _log(f"  energy {sh}: pick/best {e[pick] / e[best]:.3f}")
+    with open(os.path.join(out_dir, "energy_check.json"), "w") as f:
+        json.dump(out, f)
+    model.close()
+    return out
+
+
+def summarise(out_dir):
+    """Merges evaluation parts into evaluation.json with the summary."""
+    import glob
+    rows = []
+    for p in sorted(glob.glob(os.path.join(out_dir, "evaluation_part_*.json"))):
+        with open(p) as f:
+            rows.extend(json.load(f))
+    seen = {}
+    for r in rows:
+        seen[r["index"]] = r
+    rows = [seen[k] for k in sorted(seen)]
     ratios = np.array([r["ratio"] for r in rows])
-    summary = dict(
-        shapes=len(rows),
-        geomean_pick_over_best=float(np.exp(np.mean(np.log(ratios)))),
-        frac_within_5pct=float(np.mean(ratios <= 1.05)),
-        worst=float(ratios.max()),
-        geomean_default_over_best=float(np.exp(np.mean(np.log([r["ratio_default"] for r in rows])))),
-        geomean_untrained_over_best=float(np.exp(np.mean(np.log([r["ratio_untrained"] for r in rows])))),
-        sweep_seconds=time.perf_counter() - t0,
-    )
-    if energy_shapes:
-        erows = []
-        for sh in shapes[:energy_shapes]:
-            # energy of the measured-best-time config, the model's energy
-            # pick and the energy-best among the top time candidates
-            cfgs, res = tune.sweep(sh)
-            t = np.array([r["s_per_step"] for r in res])
-            order = np.argsort(t)[:4]
-            pick_cfg, pick = model.pick(sh, "energy")
-            idx = sorted(set(order.tolist()) | {pick})
-            meas = tune.measure([cfgs[j] for j in idx], energy_window_s=energy_window_s)
-            e = {j: m["j_per_step"] for j, m in zip(idx, meas)}
-            best_e = min(e.values())
-            erows.append(dict(shape=list(sh), e_pick=e[pick], e_best=best_e,
-                              ratio=e[pick] / best_e))
-        er = np.array([r["ratio"] for r in erows])
-        summary["energy"] = dict(shapes=len(erows),
-                                 geomean_pick_over_best=float(np.exp(np.mean(np.log(er)))),
-                                 frac_within_5pct=float(np.mean(er <= 1.05)), rows=erows)
+    gm = lambda a: float(np.exp(np.mean(np.log(a))))
+    summary = dict(shapes=len(rows), geomean_pick_over_best=gm(ratios),
+                   frac_within_5pct=float(np.mean(ratios <= 1.05)), worst=float(ratios.max()),
+                   geomean_default_over_best=gm([r["ratio_default"] for r in rows]),
+                   geomean_untrained_over_best=gm([r["ratio_untrained"] for r in rows]))
+    ep = os.path.join(out_dir, "energy_check.json")
+    if os.path.exists(ep):
+        with open(ep) as f:
+            er = json.load(f)
+        summary["energy"] = dict(shapes=len(er), geomean_pick_over_best=gm([r["ratio"] for r in er]),
+                                 frac_within_5pct=float(np.mean([r["ratio"] <= 1.05 for r in er])))
     with open(os.path.join(out_dir, "evaluation.json"), "w") as f:
         json.dump(dict(summary=summary, rows=rows), f)
     _log(json.dumps(summary))
-    model.close()
-    untrained.close()
     return summary
 
 
@@ -157,8 +228,13 @@ def main(argv=None):
     c = sub.add_parser("collect")
     c.add_argument("--out", required=True)
     c.add_argument("--shapes", type=int, default=250)
+    c.add_argument("--shapes-3d", type=int, default=40)
     c.add_argument("--per-shape", type=int, default=16)
-    c.add_argument("--energy-configs", type=int, default=0)
+    en = sub.add_parser("energy")
+    en.add_argument("--out", required=True)
+    en.add_argument("--count", type=int, default=120)
+    en.add_argument("--window", type=float, default=1.0)
+    en.add_argument("--budget", type=float, default=600.0)
     t = sub.add_parser("train")
     t.add_argument("--data", required=True)
     t.add_argument("--model", required=True)
@@ -168,16 +244,31 @@ def main(argv=None):
     e.add_argument("--model", required=True)
     e.add_argument("--out", required=True)
     e.add_argument("--shapes", type=int, default=200)
-    e.add_argument("--energy-shapes", type=int, default=0)
+    e.add_argument("--start", type=int, default=0)
+    e.add_argument("--count", type=int, default=None)
+    e.add_argument("--budget", type=float, default=1e9)
+    ec = sub.add_parser("energy-check")
+    ec.add_argument("--model", required=True)
+    ec.add_argument("--out", required=True)
+    ec.add_argument("--count", type=int, default=4)
+    sm = sub.add_parser("summarise")
+    sm.add_argument("--out", required=True)
     a = ap.parse_args(argv)
-    import torch
-    torch.cuda.set_device(0)
+    if a.cmd != "summarise":
+        import torch
+        torch.cuda.set_device(0)
     if a.cmd == "collect":
-        collect(a.out, a.shapes, a.per_shape, a.energy_configs)
+        collect(a.out, a.shapes, a.per_shape, a.shapes_3d)
+    elif a.cmd == "energy":
+        energy(a.out, a.count, a.window, a.budget)
     elif a.cmd == "train":
         train(a.data, a.model, a.epochs, a.lr)
+    elif a.cmd == "evaluate":
+        evaluate(a.model, a.out, a.shapes, a.start, a.count, a.budget)
+    elif a.cmd == "energy-check":
+        energy_check(a.model, a.out, count=a.count)
     else:
-        evaluate(a.model, a.out, a.shapes, a.energy_shapes)
+        summarise(a.out)
     return 0
 
 

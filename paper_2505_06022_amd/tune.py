@@ -59,14 +59,14 @@ def steps_for(shape, target_cell_steps=3e9):
     return int(min(960, max(24, s)))
 
 
-def measure(cfgs, r2=0.25, reps=3, energy_window_s=0.0, steps=None):
+def measure(cfgs, r2=0.25, reps=3, energy_window_s=0.0, steps=None, target_cell_steps=3e9):
     """Measures configs grouped by shape; returns one dict per config."""
     by_shape = {}
     for i, c in enumerate(cfgs):
         by_shape.setdefault(tuple(c.shape[:c.dims]), []).append(i)
     out = [None] * len(cfgs)
     for shape, idx in by_shape.items():
-        st = steps or steps_for(shape)
+        st = steps or steps_for(shape, target_cell_steps)
         res = ccl_autotune_measure([cfgs[i] for i in idx], r2, st, reps, energy_window_s)
         cells = float(np.prod(shape))
         for i, r in zip(idx, res):
