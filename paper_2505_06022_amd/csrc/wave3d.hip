@@ -91,6 +91,7 @@ __device__ __forceinline__ float4 ld4(const float *base, int64_t pz, int64_t py,
   if (c.any)
     v = *reinterpret_cast<const float4 *>(base + static_cast<int64_t>(z - z0) * pz +
                                           static_cast<int64_t>(y - y0) * py + (xl - x0));
+  if (c.m0 && c.m1 && c.m2 && c.m3) return v;  // folds away when all are known true
   v.x = c.m0 ? v.x : 0.0f;
   v.y = c.m1 ? v.y : 0.0f;
   v.z = c.m2 ? v.z : 0.0f;
@@ -104,6 +105,10 @@ __device__ __forceinline__ int xcd_block(int bid, int nblocks) {
   return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + idx;
 }
 
+// XIN: the strip's 256 columns lie inside the loadable and the output
+// column ranges (every strip of a domain whose width is a multiple of 256),
+// so loads and stores need no per-element column masks.
+template <bool XIN>
 __global__ __launch_bounds__(kThreads) void wave3d_kernel(const W3Args a) {
   const int lane = threadIdx.x & 63;
   const int tile = __builtin_amdgcn_readfirstlane(
@@ -129,8 +134,8 @@ __global__ __launch_bounds__(kThreads) void wave3d_kernel(const W3Args a) {
 
   // u^{n-1} is read (and written) only inside this tile's own output cells
   const int oy1 = min(C.cy1, yb + kRows);
-  const Cols out = cols_of(xl, C.cx0, C.cx1);
-  const Cols lc = cols_of(xl, C.lc_x0, C.lc_x1);
+  const Cols out = XIN ? Cols{true, true, true, true, true} : cols_of(xl, C.cx0, C.cx1);
+  const Cols lc = XIN ? Cols{true, true, true, true, true} : cols_of(xl, C.lc_x0, C.lc_x1);
   const int edge_x = lane == 0 ? xs - 1 : xs + 256;
   const bool edge_lane = lane == 0 || lane == 63;
 
@@ -250,7 +255,8 @@ int64_t wave_slots3d() {
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void *>(&wave3d_kernel), kThreads, 0) != hipSuccess ||
+          &per_cu, reinterpret_cast<const void *>(&wave3d_kernel<false>), kThreads, 0) !=
+              hipSuccess ||
       per_cu < 1)
     return 1024;
   cached = static_cast<int64_t>(cus) * per_cu * kWavesPerBlock;
@@ -364,10 +370,18 @@ ccl_status launch_wave3d(int32_t depth, bool in_place, float r2, int32_t tile_pl
     a.total_tiles = static_cast<int32_t>(tiles);
     const int blocks = static_cast<int>((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
     if (blocks == 0) continue;
+    bool xin = true;  // every strip of every chunk fully interior in x
+    for (int k = 0; k < n; ++k) {
+      const W3Chunk &C = a.ch[k];
+      xin = xin && (C.cx1 - C.cx0) % 256 == 0 && C.cx0 >= C.lc_x0 && C.cx1 <= C.lc_x1;
+    }
     ccl_status st;
     {
       TimedLaunch tl(CCL_KERNEL_STENCIL, stream);
-      hipLaunchKernelGGL(wave3d_kernel, dim3(blocks), dim3(kThreads), 0, stream, a);
+      if (xin)
+        hipLaunchKernelGGL(wave3d_kernel<true>, dim3(blocks), dim3(kThreads), 0, stream, a);
+      else
+        hipLaunchKernelGGL(wave3d_kernel<false>, dim3(blocks), dim3(kThreads), 0, stream, a);
     }
     st = hip_check(hipGetLastError(), "wave3d_kernel launch");
     if (st != CCL_OK) return st;

@@ -33,7 +33,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def run(depth: int, rows: int, blocks: int = 6):
+def run(depth: int, rows: int, blocks: int = 6, dims: int = 2):
     sys.path.insert(0, ROOT)
     import torch
 
@@ -41,10 +41,11 @@ def run(depth: int, rows: int, blocks: int = 6):
     import synth
     from paper_2505_06022_amd.fields import ChunkedWave
     torch.cuda.set_device(0)
-    w = synth.WORKLOADS["wave2d_8192_share_k4"]
+    name = "wave2d_8192_share_k4" if dims == 2 else "wave3d_768_k8"
+    w = synth.WORKLOADS[name]
     u0 = synth.gaussian_field(w["shape"], w["sigma"], w["seed"])
     cw = ChunkedWave(w["share_offset"], w["shape"], w["chunks"], w["r2"], depth=depth,
-                     tile_rows=rows, buffer_range=w["global_shape"])
+                     tile_rows=rows, buffer_range=w.get("global_shape"))
     cw.scatter(u0, u0)
     cw.step(depth * blocks)
     torch.cuda.synchronize()
@@ -53,7 +54,8 @@ def run(depth: int, rows: int, blocks: int = 6):
     z = torch.empty(SAXPY_N, device="cuda")
     ccl.ccl_saxpy(SAXPY_N, 2.0, x.data_ptr(), y.data_ptr(), z.data_ptr())
     torch.cuda.synchronize()
-    print(f"profile_run: {blocks} blocks of T={depth}, rows={rows}; saxpy n={SAXPY_N}", flush=True)
+    print(f"profile_run: {name}, {blocks} blocks of T={depth}, rows={rows}; saxpy n={SAXPY_N}",
+          flush=True)
 
 
 def _per_kernel(path, counter):
@@ -66,6 +68,7 @@ def _per_kernel(path, counter):
             name = row.get("Kernel_Name", "")
             val = float(row.get("Counter_Value", "nan"))
             key = ("wave2d" if "wave2d_kernel" in name else
+                   "wave3d" if "wave3d_kernel" in name else
                    "saxpy" if "saxpy_kernel" in name else
                    "halo" if "copy_boxes_kernel" in name else None)
             if key:
@@ -73,21 +76,23 @@ def _per_kernel(path, counter):
     return out
 
 
-def summarise(fetch_csv, write_csv, depth, rows, md_path):
+def summarise(fetch_csv, write_csv, depth, rows, md_path, dims=2):
     fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
     write = _per_kernel(write_csv, "WRITE_SIZE")
+    kern = "wave2d" if dims == 2 else "wave3d"
     sx_read = 8.0 * SAXPY_N / 1024.0   # KiB, algorithmic
     sx_write = 4.0 * SAXPY_N / 1024.0
     f_scale = sx_read / (sum(fetch["saxpy"]) / len(fetch["saxpy"]))
     w_scale = sx_write / (sum(write["saxpy"]) / len(write["saxpy"]))
     # skip the first stencil dispatch (cold caches after the host scatter)
-    fw = fetch["wave2d"][1:] or fetch["wave2d"]
-    ww = write["wave2d"][1:] or write["wave2d"]
+    fw = fetch[kern][1:] or fetch[kern]
+    ww = write[kern][1:] or write[kern]
     f_kib = sum(fw) / len(fw) * f_scale
     w_kib = sum(ww) / len(ww) * w_scale
-    cells = 8192 * 8192
+    cells = 8192 * 8192 if dims == 2 else 768 ** 3
     alg = (12 if depth == 1 else 16) * cells
-    doc = dict(kernel="wave2d_kernel", workload="8192x8192 share, 4 chunks", depth=depth,
+    wl = "8192x8192 share, 4 chunks" if dims == 2 else "768^3, 8 chunks"
+    doc = dict(kernel=f"{kern}_kernel", workload=wl, depth=depth,
                tile_rows=rows, kernel_hash=kernel_source_hash(),
                fetch_kib_per_dispatch_raw=sum(fw) / len(fw),
                write_kib_per_dispatch_raw=sum(ww) / len(ww),
@@ -95,12 +100,13 @@ def summarise(fetch_csv, write_csv, depth, rows, md_path):
                bytes_per_launch=int(round((f_kib + w_kib) * 1024.0)),
                algorithmic_bytes_per_launch=alg, dispatches=len(fw))
     lines = [
-        f"# HBM traffic of the 2D stencil launch — 8192x8192 share, 4 chunks, T={depth}, "
-        f"{rows} rows per tile",
+        f"# HBM traffic of the {kern} stencil launch — {wl}, T={depth}, "
+        f"{rows if rows else 'automatic'} rows per tile",
         "",
         "Counters from two rocprofv3 runs (`--pmc FETCH_SIZE`, then `--pmc WRITE_SIZE`) of "
-        "`python3 -m paper_2505_06022_amd.profile_run run --depth "
-        f"{depth} --rows {rows}`, scaled by what the same counters read for a SAXPY of "
+        "`python3 -m paper_2505_06022_amd.profile_run run --dims "
+        f"{dims} --depth {depth} --rows {rows}`, scaled by what the same counters read for a "
+        "SAXPY of "
         f"{SAXPY_N} floats (8 B read, 4 B written per element).",
         "",
         "| quantity | value |",
@@ -127,17 +133,19 @@ def main(argv=None):
     r.add_argument("--depth", type=int, required=True)
     r.add_argument("--rows", type=int, required=True)
     r.add_argument("--blocks", type=int, default=6)
+    r.add_argument("--dims", type=int, default=2)
     s = sub.add_parser("summarise")
     s.add_argument("--fetch", required=True)
     s.add_argument("--write", required=True)
     s.add_argument("--depth", type=int, required=True)
     s.add_argument("--rows", type=int, required=True)
     s.add_argument("--md", required=True)
+    s.add_argument("--dims", type=int, default=2)
     a = ap.parse_args(argv)
     if a.cmd == "run":
-        run(a.depth, a.rows, a.blocks)
+        run(a.depth, a.rows, a.blocks, a.dims)
     else:
-        summarise(a.fetch, a.write, a.depth, a.rows, a.md)
+        summarise(a.fetch, a.write, a.depth, a.rows, a.md, a.dims)
     return 0
 
 
