@@ -217,6 +217,51 @@ def batched_forms(log_energy=False):
             "configs": "cost model" if model is not None else "T=4, 64 rows"}
 
 
+def wave3d_forms(with_energy=False):
+    """768^3, r2 = 0.1, 8 z-slab chunks, 200 steps: the swept best tile-plane
+    count vs the cost model's pick (both among 8-chunk configs), timed with
+    the workload's own data through ccl_wave_step, with J/step."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2505_06022_amd import ccl_wave_plan_rows, tune
+    from paper_2505_06022_amd.fields import ChunkedWave
+    w = synth.WORKLOADS["wave3d_768_k8"]
+    shape = w["shape"]
+    cands = [c for c in tune.candidates(shape) if c.nchunks == w["chunks"]]
+    res = tune.measure(cands, w["r2"], reps=3, steps=20)
+    swept = cands[int(np.argmin([r["s_per_step"] for r in res]))]
+    learned = None
+    if os.path.exists(MODEL_PATH):
+        m = tune.CostModel.load(MODEL_PATH)
+        learned, _ = m.pick(shape, "time", nchunks=w["chunks"])
+        m.close()
+    u0 = synth.gaussian_field(shape, w["sigma"], w["seed"])
+    out = {"workload": "3D leapfrog 768^3, r2=0.1, 200 steps, 8 z-slab chunks",
+           "candidates": len(cands)}
+    cells = float(np.prod(shape))
+    for name, cfg in (("swept", swept), ("learned", learned)):
+        if cfg is None:
+            continue
+        cw = ChunkedWave((0, 0, 0), shape, w["chunks"], w["r2"], depth=1,
+                         tile_rows=cfg.tile_rows)
+        cw.scatter(u0, u0)
+        cw.step(w["steps"])
+        t = time_runs(cw, w["steps"], 2) / 2
+        entry = {"tile_planes": cfg.tile_rows,
+                 "planned_planes": ccl_wave_plan_rows(cfg),
+                 "mcells": round(cells * w["steps"] / t / 1e6, 1),
+                 "ms_per_run": round(t * 1e3, 3)}
+        if with_energy:
+            p = average_power(lambda: cw.step(w["steps"]))
+            entry["j_per_step"] = round(p * t / w["steps"], 5)
+        out[name] = entry
+        del cw
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -326,6 +371,8 @@ def main():
         out["saxpy_gbs"] = round(saxpy_calibration(), 1)
         log("batched workload")
         out["batched"] = batched_forms(log_energy=out.get("j_per_step") is not None)
+        log("3D workload")
+        out["wave3d"] = wave3d_forms(with_energy=out.get("j_per_step") is not None)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(w)

@@ -126,6 +126,25 @@ def summarise(fetch_csv, write_csv, depth, rows, md_path, dims=2):
     print("\n".join(lines))
 
 
+def trace_summary(db_path, md_path, title, command):
+    """Per-kernel call counts and durations from a rocprofv3 kernel-trace
+    database (its `top_kernels` view), as a markdown table."""
+    import sqlite3
+    db = sqlite3.connect(db_path)
+    rows = db.execute("select name, total_calls, total_duration, average, percentage "
+                      "from top_kernels order by total_duration desc").fetchall()
+    lines = [f"# {title}", "", "Command:", "", "```", command, "```", "",
+             "| kernel | calls | total (us) | average (us) | % |", "|---|---|---|---|---|"]
+    for name, calls, total, avg, pct in rows[:12]:
+        short = name.replace("ccl::(anonymous namespace)::", "").replace("void ", "")
+        short = short.split("(")[0][:90]
+        lines.append(f"| `{short}` | {calls} | {total:.1f} | {avg:.3f} | {pct:.2f} |")
+    lines.append("")
+    with open(md_path, "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -141,7 +160,15 @@ def main(argv=None):
     s.add_argument("--rows", type=int, required=True)
     s.add_argument("--md", required=True)
     s.add_argument("--dims", type=int, default=2)
+    t = sub.add_parser("trace-summary")
+    t.add_argument("--db", required=True)
+    t.add_argument("--md", required=True)
+    t.add_argument("--title", required=True)
+    t.add_argument("--command", required=True)
     a = ap.parse_args(argv)
+    if a.cmd == "trace-summary":
+        trace_summary(a.db, a.md, a.title, a.command)
+        return 0
     if a.cmd == "run":
         run(a.depth, a.rows, a.blocks, a.dims)
     else:

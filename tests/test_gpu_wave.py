@@ -299,3 +299,25 @@ def test_energy_read():
     e1, t1 = ccl.ccl_energy_read(0, torch.cuda.current_stream())
     assert e1 >= e0
     print("energy backend", ccl.ccl_energy_backend(0), "delta J", e1 - e0)
+
+
+@pytest.mark.parametrize("shape,K,T", [((1, 300), 1, 1), ((1, 300), 1, 4), ((57, 1), 3, 2),
+                                       ((40, 3), 40, 4), ((12, 700), 12, 8), ((5, 5), 5, 6),
+                                       ((2, 2), 2, 8)])
+def test_degenerate_shapes(shape, K, T):
+    """Single-row/column grids, one-row chunks whose halo reaches several
+    chunks away, domains narrower than one strip, depth beyond the grid."""
+    u_prev = synth.gaussian_field(shape, 3.0, seed=20)
+    u_cur = synth.gaussian_field(shape, 2.0, seed=21)
+    _, ref = oracle.wave(u_prev, u_cur, 0.25, 13)
+    _, gc = gpu_run(u_prev, u_cur, 0.25, 13, K, T)
+    assert_bitwise(gc, ref, f"{shape} K={K} T={T}")
+
+
+@pytest.mark.parametrize("shape,K", [((1, 1, 1), 1), ((3, 1, 5), 3), ((7, 9, 1), 2),
+                                     ((2, 300, 260), 2)])
+def test_degenerate_shapes_3d(shape, K):
+    u0 = synth.gaussian_field(shape, 2.0, seed=22)
+    _, ref = oracle.wave(u0.copy(), u0, 0.1, 9)
+    _, gc = gpu_run(u0, u0, 0.1, 9, K, 1)
+    assert_bitwise(gc, ref, f"3D {shape} K={K}")
