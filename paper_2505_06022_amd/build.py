@@ -32,31 +32,35 @@ def sources():
     return sorted(list(CSRC.glob("*.hip")) + list(CSRC.glob("*.cpp")))
 
 
-def _compile(src: Path) -> Path:
-    out = OBJ / (src.name + ".o")
+def _compile(src: Path, obj_dir: Path = OBJ, extra=()) -> Path:
+    out = obj_dir / (src.name + ".o")
     lang = ["-x", "hip"] if src.suffix == ".hip" else []
-    cmd = [HIPCC, *COMMON, *lang, "-c", str(src), "-o", str(out)]
+    cmd = [HIPCC, *COMMON, *extra, *lang, "-c", str(src), "-o", str(out)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return out
 
 
-def build(verbose: bool = False) -> Path:
-    OBJ.mkdir(exist_ok=True)
+def build(verbose: bool = False, out: Path = LIB, extra=()) -> Path:
+    """Compiles every source and links `out` (default: the in-tree library);
+    `extra` adds compiler flags (e.g. -D overrides of tuning constants)."""
+    obj_dir = OBJ if out == LIB else Path(out).parent / "_obj"
+    obj_dir.mkdir(parents=True, exist_ok=True)
     srcs = sources()
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB.with_suffix(".so.tmp")
+        objs = list(ex.map(lambda s: _compile(s, obj_dir, tuple(extra)), srcs))
+    LIBOUT = Path(out)
+    tmp = LIBOUT.with_suffix(".so.tmp")
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *map(str, objs), "-o", str(tmp),
            "-ldl", "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, LIBOUT)
     if verbose:
-        print(f"built {LIB}", flush=True)
-    return LIB
+        print(f"built {LIBOUT}", flush=True)
+    return LIBOUT
 
 
 if __name__ == "__main__":

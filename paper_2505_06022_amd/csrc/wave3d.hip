@@ -20,7 +20,10 @@ namespace {
 constexpr int kWavesPerBlock = 4;
 constexpr int kThreads = 64 * kWavesPerBlock;
 constexpr int kMaxChunksPerLaunch = 16;
-constexpr int kRows = 4;  // rows per wave tile
+#ifndef CCL_W3_ROWS
+#define CCL_W3_ROWS 4
+#endif
+constexpr int kRows = CCL_W3_ROWS;  // rows per wave tile
 
 struct W3Chunk {
   const float *in_cur;
