@@ -218,8 +218,8 @@ def batched_forms(log_energy=False):
 
 
 def wave3d_forms(with_energy=False):
-    """768^3, r2 = 0.1, 8 z-slab chunks, 200 steps: the swept best tile-plane
-    count vs the cost model's pick (both among 8-chunk configs), timed with
+    """768^3, r2 = 0.1, 8 z-slab chunks, 200 steps: the swept best (depth,
+    tile planes) vs the cost model's pick (both among 8-chunk configs), timed with
     the workload's own data through ccl_wave_step, with J/step."""
     import numpy as np
     import torch
@@ -244,12 +244,12 @@ def wave3d_forms(with_energy=False):
     for name, cfg in (("swept", swept), ("learned", learned)):
         if cfg is None:
             continue
-        cw = ChunkedWave((0, 0, 0), shape, w["chunks"], w["r2"], depth=1,
+        cw = ChunkedWave((0, 0, 0), shape, w["chunks"], w["r2"], depth=cfg.temporal_depth,
                          tile_rows=cfg.tile_rows)
         cw.scatter(u0, u0)
         cw.step(w["steps"])
         t = time_runs(cw, w["steps"], 2) / 2
-        entry = {"tile_planes": cfg.tile_rows,
+        entry = {"depth": cfg.temporal_depth, "tile_planes": cfg.tile_rows,
                  "planned_planes": ccl_wave_plan_rows(cfg),
                  "mcells": round(cells * w["steps"] / t / 1e6, 1),
                  "ms_per_run": round(t * 1e3, 3)}

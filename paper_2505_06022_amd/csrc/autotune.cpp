@@ -35,7 +35,6 @@ ccl_status plan_of(const ccl_tune_config &c, Plan *P) {
   if (dims != 2 && dims != 3) return fail(CCL_E_INVALID, "dims=%d must be 2 or 3", dims);
   if (c.temporal_depth < 1 || c.temporal_depth > CCL_MAX_DEPTH)
     return fail(CCL_E_INVALID, "temporal depth %d", c.temporal_depth);
-  if (dims == 3 && c.temporal_depth != 1) return fail(CCL_E_UNSUPPORTED, "3D needs T == 1");
   ccl_subrange r;
   memset(&r, 0, sizeof(r));
   r.dims = dims;
@@ -192,7 +191,7 @@ extern "C" ccl_status ccl_wave_plan_rows(const ccl_tune_config *c, int32_t *rows
   clear_error();
   if (!c || !rows) return fail(CCL_E_INVALID, "NULL argument");
   if ((c->dims != 2 && c->dims != 3) || c->nchunks < 1 || c->temporal_depth < 1 ||
-      c->temporal_depth > CCL_MAX_DEPTH || (c->dims == 3 && c->temporal_depth != 1))
+      c->temporal_depth > CCL_MAX_DEPTH)
     return fail(CCL_E_INVALID, "malformed config");
   for (int d = 0; d < c->dims; ++d)
     if (c->shape[d] < 1) return fail(CCL_E_INVALID, "empty extent");
@@ -203,7 +202,8 @@ extern "C" ccl_status ccl_wave_plan_rows(const ccl_tune_config *c, int32_t *rows
   }
   *rows = c->dims == 2
               ? wave2d_plan_rows(c->shape[0], c->shape[1], c->nchunks, c->temporal_depth)
-              : wave3d_plan_planes(c->shape[0], c->shape[1], c->shape[2], c->nchunks);
+              : wave3d_plan_planes(c->shape[0], c->shape[1], c->shape[2], c->nchunks,
+                                   c->temporal_depth);
   return CCL_OK;
 }
 
@@ -233,9 +233,17 @@ extern "C" ccl_status ccl_costmodel_features(int32_t n, const ccl_tune_config *c
     const double row_bytes = 4.0 * n1 * n2;
     const double halo = 2.0 * (K - 1.0) * (2.0 * T - 1.0) * row_bytes * 2.0 / T;
     const double model_bytes = c.temporal_depth == 1 ? 12.0 : 16.0 / T;
-    const double strip = c.dims == 2 ? 256.0 - 2.0 * 4.0 * std::ceil(T / 4.0) : 256.0;
-    const double waves = K * std::ceil(n0 / K / rows) * std::ceil((c.dims == 2 ? n1 : n2) / strip) *
-                         (c.dims == 3 ? std::ceil(n1 / 4.0) : 1.0);
+    double waves;
+    if (c.dims == 2) {
+      const double strip = 256.0 - 2.0 * 4.0 * std::ceil(T / 4.0);
+      waves = K * std::ceil(n0 / K / rows) * std::ceil(n1 / strip);
+    } else if (c.temporal_depth == 1) {
+      waves = K * std::ceil(n0 / K / rows) * std::ceil(n2 / 256.0) * std::ceil(n1 / 4.0);
+    } else {
+      int32_t oc = 1, orows = 1, wpb = 1;
+      wave3d_tb_geometry(c.temporal_depth, &oc, &orows, &wpb);
+      waves = wpb * K * std::ceil(n0 / K / rows) * std::ceil(n2 / oc) * std::ceil(n1 / orows);
+    }
     float *x = x_host + static_cast<size_t>(i) * CCL_MLP_IN;
     x[0] = static_cast<float>(std::log2(n0));
     x[1] = static_cast<float>(std::log2(n1));

@@ -132,11 +132,18 @@ int32_t plan_tile_rows(int64_t slots, int32_t halo, int32_t min_rows, int32_t ma
 }
 
 int32_t wave2d_plan_rows(int64_t ny, int64_t nx, int32_t K, int32_t T);
-int32_t wave3d_plan_planes(int64_t nz, int64_t ny, int64_t nx, int32_t K);
+int32_t wave3d_plan_planes(int64_t nz, int64_t ny, int64_t nx, int32_t K, int32_t T);
+int32_t wave3d_tb_plan_planes(int64_t nz, int64_t ny, int64_t nx, int32_t K, int32_t T);
+// Output columns and rows of one block's patch, and waves per block, of the
+// depth-T (2..8) 3D kernel.
+void wave3d_tb_geometry(int32_t T, int32_t *out_cols, int32_t *out_rows, int32_t *waves);
 
 ccl_status launch_wave2d(int32_t depth, bool in_place, float r2, int32_t tile_rows,
                          const WaveChunkPlan *plans, int32_t nplans, hipStream_t stream);
 ccl_status launch_wave3d(int32_t depth, bool in_place, float r2, int32_t tile_rows,
                          const WaveChunkPlan *plans, int32_t nplans, hipStream_t stream);
+// Depth T in 2..8, out of place (u^{n+T-1}, u^{n+T} to out_prev, out_cur).
+ccl_status launch_wave3d_tb(int32_t T, float r2, int32_t tile_planes, const WaveChunkPlan *plans,
+                            int32_t nplans, hipStream_t stream);
 
 }  // namespace ccl

@@ -13,6 +13,7 @@
 #include <cstring>
 
 #include "ccl_internal.h"
+#include "wave3d_cell.h"
 
 namespace ccl {
 namespace {
@@ -51,16 +52,6 @@ __device__ __forceinline__ float dpp_from_left(float v) {
 }
 __device__ __forceinline__ float dpp_from_right(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
-}
-
-// s = ((Z- + Z+) + (Y- + Y+)) + (X- + X+); lap = s - 6C; u+ = fma(r2, lap, 2C - P).
-// 6C is rounded (6 needs two significant bits), so it stays a separate
-// multiply; 2C is exact, so fma(2, C, -P) equals the rounded 2C - P.
-__device__ __forceinline__ float cell3(float zm, float zp, float ym, float yp, float xm, float xp,
-                                       float c, float p, float r2) {
-  const float sum = ((zm + zp) + (ym + yp)) + (xm + xp);
-  const float lap = sum - 6.0f * c;
-  return fmaf(r2, lap, fmaf(2.0f, c, -p));
 }
 
 __device__ __forceinline__ float4 zero4() { return make_float4(0.f, 0.f, 0.f, 0.f); }
@@ -269,8 +260,9 @@ int64_t wave_slots3d() {
 }  // namespace
 
 // The planes per tile the launcher would pick for a domain split into K
-// plane chunks.
-int32_t wave3d_plan_planes(int64_t nz, int64_t ny, int64_t nx, int32_t K) {
+// plane chunks, at temporal depth T.
+int32_t wave3d_plan_planes(int64_t nz, int64_t ny, int64_t nx, int32_t K, int32_t T) {
+  if (T > 1) return wave3d_tb_plan_planes(nz, ny, nx, K, T);
   int64_t zmax = 0;
   for (int k = 0; k < K; ++k) zmax = std::max<int64_t>(zmax, (k + 1) * nz / K - k * nz / K);
   auto waves_of = [&](int32_t p) {
@@ -287,8 +279,11 @@ int32_t wave3d_plan_planes(int64_t nz, int64_t ny, int64_t nx, int32_t K) {
 
 ccl_status launch_wave3d(int32_t depth, bool in_place, float r2, int32_t tile_planes,
                          const WaveChunkPlan *plans, int32_t nplans, hipStream_t stream) {
-  if (depth != 1 || !in_place)
-    return fail(CCL_E_UNSUPPORTED, "3D stencil supports temporal depth 1 (in place) only");
+  if (depth > 1) {
+    if (in_place) return fail(CCL_E_INVALID, "in-place update needs T == 1");
+    return launch_wave3d_tb(depth, r2, tile_planes, plans, nplans, stream);
+  }
+  if (!in_place) return fail(CCL_E_INVALID, "the one-step 3D kernel updates in place");
   for (int first = 0; first < nplans; first += kMaxChunksPerLaunch) {
     const int n = std::min(kMaxChunksPerLaunch, nplans - first);
     W3Args a;

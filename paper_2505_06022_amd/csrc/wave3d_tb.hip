@@ -1,0 +1,457 @@
+// 3D seven-point leapfrog stencil, T = 2..8 steps per pass over HBM.
+//
+// Work unit: one 256-thread block owns a patch of 64 columns by 16*P rows
+// and streams along z through a segment of planes.  Thread (ly, lx) holds
+// four consecutive columns (one 16-byte group) of P consecutive rows; the
+// 16 threads of a patch row are one DPP row, so x-neighbours come from DPP
+// row shifts.  For every level l < T the thread keeps the last three planes
+// of u^{n+l} over its cells in registers (a rotating three-slot ring), so
+// z-neighbours are register reads.  y-neighbours inside a thread's P rows
+// are its own registers; the first and last of its rows take their outer
+// neighbour from the adjacent thread row, published in LDS once per plane
+// (two 16-byte words per thread and level, one barrier per plane).
+//
+// At iteration i the block loads plane i of u^n (level 0) and, level by
+// level, computes plane i-l of u^{n+l}; level T gives u^{n+T} at plane i-T,
+// stored with u^{n+T-1} of the same plane.  A level-l value is valid only
+// where its whole dependency cone was loaded, so patches overlap their
+// neighbours by A = 4*ceil(T/4) columns and T rows on each side and
+// segments re-read T planes above and below; only the valid interior is
+// stored.  Every cell is produced by the same float32 expression as the
+// one-step kernel, so results are bitwise independent of T and tiling.
+#include <algorithm>
+#include <cstring>
+#include <type_traits>
+
+#include "ccl_internal.h"
+#include "wave2d_tile.h"
+#include "wave3d_cell.h"
+
+namespace ccl {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kPatchCols = 64;
+constexpr int kMaxChunksPerLaunch = 8;
+
+// Rows per thread, overlap, output extent and LDS buffering for depth T.
+#ifndef CCL_W3T_ROWS
+__host__ __device__ constexpr int tb_rows(int T) { return T <= 4 ? 4 : (T <= 6 ? 3 : 2); }
+#else
+__host__ __device__ constexpr int tb_rows(int) { return CCL_W3T_ROWS; }
+#endif
+__host__ __device__ constexpr int tb_overlap(int T) { return 4 * ((T + 3) / 4); }
+__host__ __device__ constexpr int tb_out_cols(int T) { return kPatchCols - 2 * tb_overlap(T); }
+__host__ __device__ constexpr int tb_out_rows(int T) { return 16 * tb_rows(T) - 2 * T; }
+__host__ __device__ constexpr int tb_lds_buffers(int T) { return T <= 4 ? 2 : 1; }
+
+struct Field3 {  // a chunk buffer: global index of its first element, strides
+  int32_t z0, y0, x0;
+  int32_t pz, py;
+};
+
+struct W3TChunk {
+  const float *in_prev;
+  const float *in_cur;
+  float *out_prev;
+  float *out_cur;
+  Field3 ip, ic, op, oc;
+  int32_t lp[6];  // loadable box of in_prev: z0, z1, y0, y1, x0, x1
+  int32_t lc[6];  // loadable box of in_cur
+  int32_t cz0, cz1, cy0, cy1, cx0, cx1;  // chunk (output) box
+  int32_t nstrips, nrowblk;
+  int32_t tile_begin;
+};
+
+struct W3TArgs {
+  int32_t nchunks;
+  int32_t total_tiles;
+  int32_t tile_planes;
+  float r2;
+  int32_t gz0, gz1, gy0, gy1, gx0, gx1;  // domain: zero outside
+  W3TChunk ch[kMaxChunksPerLaunch];
+};
+
+__device__ __forceinline__ float row_from_left(float v) {
+  // lane l receives lane l-1's value within its 16-lane row (row_shr:1)
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float row_from_right(float v) {
+  // lane l receives lane l+1's value within its 16-lane row (row_shl:1)
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ int64_t at(const Field3 &f, int z, int y, int x) {
+  return static_cast<int64_t>(z - f.z0) * f.pz + static_cast<int64_t>(y - f.y0) * f.py + (x - f.x0);
+}
+
+// The thread's P rows of plane z (zero outside the loadable box `lb`).
+// STREAM marks data read once (u^{n-1}).
+template <bool STREAM, int P>
+__device__ __forceinline__ void load_rows(float4 (&v)[P], const float *base, const Field3 &f,
+                                          const int32_t *lb, const w2::Cols &cx, int z, int yl,
+                                          int xl) {
+  const bool zin = z >= lb[0] && z < lb[1];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int y = yl + j;
+    float4 r = w2::zero4();
+    if (zin && y >= lb[2] && y < lb[3] && cx.any) {
+      const w2::f4v *p = reinterpret_cast<const w2::f4v *>(base + at(f, z, y, xl));
+      const w2::f4v q = STREAM ? __builtin_nontemporal_load(p) : *p;
+      r = make_float4(q.x, q.y, q.z, q.w);
+    }
+    r.x = cx.m0 ? r.x : 0.0f;
+    r.y = cx.m1 ? r.y : 0.0f;
+    r.z = cx.m2 ? r.z : 0.0f;
+    r.w = cx.m3 ? r.w : 0.0f;
+    v[j] = r;
+  }
+}
+
+// Stores a group where the output mask allows.  Partial groups occur only
+// at a chunk's x edges; their other columns are halo cells of this chunk's
+// own output buffer that nothing writes during the launch, so they are read
+// and written back unchanged (one 16-byte store).
+__device__ __forceinline__ void store_group(float *base, const Field3 &f, int z, int y, int xl,
+                                            const w2::Cols &c, const float4 &v) {
+  w2::f4v *p = reinterpret_cast<w2::f4v *>(base + at(f, z, y, xl));
+  w2::f4v w = {v.x, v.y, v.z, v.w};
+  if (!(c.m0 && c.m1 && c.m2 && c.m3)) {
+    const w2::f4v o = *p;
+    w.x = c.m0 ? v.x : o.x;
+    w.y = c.m1 ? v.y : o.y;
+    w.z = c.m2 ? v.z : o.z;
+    w.w = c.m3 ? v.w : o.w;
+  }
+  __builtin_nontemporal_store(w, p);
+}
+
+template <int T>
+__global__ __launch_bounds__(kThreads) void wave3d_tb_kernel(const W3TArgs a) {
+  constexpr int P = tb_rows(T);
+  constexpr int A = tb_overlap(T);
+  constexpr int OW = tb_out_cols(T);
+  constexpr int OH = tb_out_rows(T);
+  constexpr int NB = tb_lds_buffers(T);
+  // [buffer][level][first row / last row][thread]
+  __shared__ float4 xch[NB][T][2][kThreads];
+
+  const int blk = w2::xcd_block(blockIdx.x, gridDim.x);
+  if (blk >= a.total_tiles) return;  // the whole block leaves together
+  int c = 0;
+  while (c + 1 < a.nchunks && blk >= a.ch[c + 1].tile_begin) ++c;
+  const W3TChunk &C = a.ch[c];
+
+  // tile order: strip fastest, then row block, then z segment
+  int local = blk - C.tile_begin;
+  const int per_seg = C.nstrips * C.nrowblk;
+  const int seg = local / per_seg;
+  local -= seg * per_seg;
+  const int rb = local / C.nstrips;
+  const int strip = local - rb * C.nstrips;
+
+  const int tid = threadIdx.x;
+  const int lx = tid & 15, ly = tid >> 4;
+  const int zo0 = C.cz0 + seg * a.tile_planes;
+  const int zo1 = min(C.cz1, zo0 + a.tile_planes);
+  const int px = C.cx0 - A + strip * OW;  // patch origin
+  const int py = C.cy0 - T + rb * OH;
+  const int xl = px + 4 * lx;
+  const int yl = py + ly * P;
+  const int oy0 = max(C.cy0, py + T), oy1 = min(C.cy1, py + T + OH);
+  const float r2 = a.r2;
+
+  const w2::Cols dom = w2::cols_of(xl, a.gx0, a.gx1);
+  const w2::Cols out = w2::cols_of(xl, max(C.cx0, px + A), min(C.cx1, px + A + OW));
+  const w2::Cols lcx = w2::cols_of(xl, C.lc[4], C.lc[5]);
+  const w2::Cols lpx = w2::cols_of(xl, C.lp[4], C.lp[5]);
+  // a patch whose rows and columns all lie in the domain needs no masks
+  // except at planes outside it
+  const bool xy_in =
+      px >= a.gx0 && px + kPatchCols <= a.gx1 && py >= a.gy0 && py + 16 * P <= a.gy1;
+
+  float4 ring[T][3][P];  // level l: planes i-l-2, i-l-1, i-l in rotating slots
+#pragma unroll
+  for (int l = 0; l < T; ++l)
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+      for (int j = 0; j < P; ++j) ring[l][s][j] = w2::zero4();
+
+  const int i0 = zo0 - T;
+  const int n_iter = (zo1 - zo0) + 2 * T;
+  float4 qn[P], pn[P];  // next plane of u^n, of u^{n-1}
+  load_rows<false>(qn, C.in_cur, C.ic, C.lc, lcx, i0, yl, xl);
+  load_rows<true>(pn, C.in_prev, C.ip, C.lp, lpx, i0 - 1, yl, xl);
+
+  // One iteration; PH = iteration count mod 3 names the ring slots: before
+  // it the newest plane of every level sits in slot (PH+2)%3, after it in
+  // slot PH, with the middle in (PH+2)%3 and the oldest in (PH+1)%3.
+  auto iteration = [&](auto ph, int i) {
+    constexpr int PH = decltype(ph)::value;
+    constexpr int NEW = PH, MID = (PH + 2) % 3, OLD = (PH + 1) % 3;
+    const int b = NB == 2 ? (i & 1) : 0;
+    if (NB == 1) __syncthreads();  // every thread has read the last plane's words
+#pragma unroll
+    for (int l = 0; l < T; ++l) {
+      xch[b][l][0][tid] = ring[l][MID][0];  // MID is still the newest here
+      xch[b][l][1][tid] = ring[l][MID][P - 1];
+    }
+    __syncthreads();
+
+    // level 0: plane i of u^n arrives; u^{n-1} of plane i-1 for level 1
+#pragma unroll
+    for (int j = 0; j < P; ++j) ring[0][NEW][j] = qn[j];
+    float4 pc[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) pc[j] = pn[j];
+    load_rows<false>(qn, C.in_cur, C.ic, C.lc, lcx, i + 1, yl, xl);
+    load_rows<true>(pn, C.in_prev, C.ip, C.lp, lpx, i, yl, xl);
+
+#pragma unroll
+    for (int t = 1; t <= T; ++t) {
+      const int r = i - t;  // plane of u^{n+t} computed now
+      const bool z_in = r >= a.gz0 && r < a.gz1;  // block-uniform
+      // outer y-neighbours of this thread's rows in plane r of u^{n+t-1}
+      // (the top thread row reads the bottom one's words: patch-edge cells
+      // are never valid, so any finite or non-finite value is harmless)
+      const float4 up = xch[b][t - 1][1][(tid - 16) & (kThreads - 1)];
+      const float4 dn = xch[b][t - 1][0][(tid + 16) & (kThreads - 1)];
+      float4 o[P];
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const float4 cc = ring[t - 1][MID][j];
+        const float4 zm = ring[t - 1][OLD][j];
+        const float4 zp = ring[t - 1][NEW][j];
+        const float4 ym = j == 0 ? up : ring[t - 1][MID][j - 1];
+        const float4 yp = j == P - 1 ? dn : ring[t - 1][MID][j + 1];
+        const float4 pv = t == 1 ? pc[j] : ring[t >= 2 ? t - 2 : 0][OLD][j];
+        const float xm0 = row_from_left(cc.w);
+        const float xp3 = row_from_right(cc.x);
+        float4 v;
+        v.x = cell3(zm.x, zp.x, ym.x, yp.x, xm0, cc.y, cc.x, pv.x, r2);
+        v.y = cell3(zm.y, zp.y, ym.y, yp.y, cc.x, cc.z, cc.y, pv.y, r2);
+        v.z = cell3(zm.z, zp.z, ym.z, yp.z, cc.y, cc.w, cc.z, pv.z, r2);
+        v.w = cell3(zm.w, zp.w, ym.w, yp.w, cc.z, xp3, cc.w, pv.w, r2);
+        if (!(xy_in && z_in)) {
+          const int y = yl + j;
+          const bool in = z_in && y >= a.gy0 && y < a.gy1;
+          v.x = (in && dom.m0) ? v.x : 0.0f;
+          v.y = (in && dom.m1) ? v.y : 0.0f;
+          v.z = (in && dom.m2) ? v.z : 0.0f;
+          v.w = (in && dom.m3) ? v.w : 0.0f;
+        }
+        o[j] = v;
+      }
+      if (t < T) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) ring[t < T ? t : 0][NEW][j] = o[j];
+      } else if (r >= zo0 && r < zo1 && out.any) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          const int y = yl + j;
+          if (y < oy0 || y >= oy1) continue;
+          store_group(C.out_cur, C.oc, r, y, xl, out, o[j]);
+          store_group(C.out_prev, C.op, r, y, xl, out, ring[T - 1][MID][j]);
+        }
+      }
+    }
+  };
+
+  for (int n = 0; n < n_iter; n += 3) {
+    iteration(std::integral_constant<int, 0>(), i0 + n);
+    if (n + 1 < n_iter) iteration(std::integral_constant<int, 1>(), i0 + n + 1);
+    if (n + 2 < n_iter) iteration(std::integral_constant<int, 2>(), i0 + n + 2);
+  }
+}
+
+template <int T>
+const void *kernel_of() {
+  return reinterpret_cast<const void *>(&wave3d_tb_kernel<T>);
+}
+
+const void *kernel_for(int T) {
+  switch (T) {
+    case 2: return kernel_of<2>();
+    case 3: return kernel_of<3>();
+    case 4: return kernel_of<4>();
+    case 5: return kernel_of<5>();
+    case 6: return kernel_of<6>();
+    case 7: return kernel_of<7>();
+    case 8: return kernel_of<8>();
+    default: return nullptr;
+  }
+}
+
+// Concurrently resident blocks of the depth-T kernel on the device (cached).
+int64_t block_slots(int T) {
+  static int64_t cache[CCL_MAX_DEPTH + 1] = {};
+  if (T < 2 || T > CCL_MAX_DEPTH) return 256;
+  if (cache[T] > 0) return cache[T];
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_for(T), kThreads, 0) !=
+          hipSuccess ||
+      per_cu < 1)
+    return 256;
+  cache[T] = static_cast<int64_t>(cus) * per_cu;
+  return cache[T];
+}
+
+int64_t tiles_of(int64_t nz, int64_t ny, int64_t nx, int T, int32_t planes) {
+  return ((nz + planes - 1) / planes) * ((ny + tb_out_rows(T) - 1) / tb_out_rows(T)) *
+         ((nx + tb_out_cols(T) - 1) / tb_out_cols(T));
+}
+
+bool fits_i32(int64_t v) { return v >= INT32_MIN && v <= INT32_MAX; }
+
+ccl_status field3_of(const WaveField &w, Field3 *f) {
+  for (int d = 0; d < 3; ++d)
+    if (!fits_i32(w.off[d])) return fail(CCL_E_RANGE, "3D buffer origins must fit in int32");
+  if (!fits_i32(w.pitch[0]) || !fits_i32(w.pitch[1]))
+    return fail(CCL_E_RANGE, "3D buffer strides must fit in int32");
+  f->z0 = static_cast<int32_t>(w.off[0]);
+  f->y0 = static_cast<int32_t>(w.off[1]);
+  f->x0 = static_cast<int32_t>(w.off[2]);
+  f->pz = static_cast<int32_t>(w.pitch[0]);
+  f->py = static_cast<int32_t>(w.pitch[1]);
+  return CCL_OK;
+}
+
+void box6(const Box &b, int32_t *o) {
+  for (int d = 0; d < 3; ++d) {
+    o[2 * d] = static_cast<int32_t>(b.lo[d]);
+    o[2 * d + 1] = static_cast<int32_t>(b.hi[d]);
+  }
+}
+
+template <int T>
+ccl_status launch_t(const W3TArgs &a, int blocks, hipStream_t s) {
+  TimedLaunch tl(CCL_KERNEL_STENCIL, s);
+  hipLaunchKernelGGL(wave3d_tb_kernel<T>, dim3(blocks), dim3(kThreads), 0, s, a);
+  return hip_check(hipGetLastError(), "wave3d_tb_kernel launch");
+}
+
+}  // namespace
+
+void wave3d_tb_geometry(int32_t T, int32_t *out_cols, int32_t *out_rows, int32_t *waves) {
+  *out_cols = tb_out_cols(T);
+  *out_rows = tb_out_rows(T);
+  *waves = kThreads / 64;
+}
+
+// Planes per z segment the depth-T kernel would pick for a domain split
+// into K plane chunks (every block streams planes + 2T planes).
+int32_t wave3d_tb_plan_planes(int64_t nz, int64_t ny, int64_t nx, int32_t K, int32_t T) {
+  int64_t zmax = 0;
+  for (int k = 0; k < K; ++k) zmax = std::max<int64_t>(zmax, (k + 1) * nz / K - k * nz / K);
+  auto blocks_of = [&](int32_t p) {
+    int64_t w = 0;
+    for (int k = 0; k < K; ++k) w += tiles_of((k + 1) * nz / K - k * nz / K, ny, nx, T, p);
+    return w;
+  };
+  return plan_tile_rows(block_slots(T), T, 4, static_cast<int32_t>(std::max<int64_t>(zmax, 4)),
+                        blocks_of);
+}
+
+ccl_status launch_wave3d_tb(int32_t T, float r2, int32_t tile_planes, const WaveChunkPlan *plans,
+                            int32_t nplans, hipStream_t stream) {
+  if (T < 2 || T > CCL_MAX_DEPTH)
+    return fail(CCL_E_INVALID, "temporally blocked 3D stencil needs T in 2..%d", CCL_MAX_DEPTH);
+  if (nplans < 1) return CCL_OK;
+  const Box &D = plans[0].domain;
+  for (int k = 0; k < nplans; ++k)
+    for (int d = 0; d < 3; ++d)
+      if (plans[k].domain.lo[d] != D.lo[d] || plans[k].domain.hi[d] != D.hi[d])
+        return fail(CCL_E_INVALID, "chunks of one launch must share the domain");
+  for (int d = 0; d < 3; ++d)
+    if (!fits_i32(D.lo[d] - 64) || !fits_i32(D.hi[d] + 64))
+      return fail(CCL_E_RANGE, "3D indices must fit in int32");
+  for (int first = 0; first < nplans; first += kMaxChunksPerLaunch) {
+    const int n = std::min(kMaxChunksPerLaunch, nplans - first);
+    W3TArgs a;
+    memset(&a, 0, sizeof(a));
+    a.nchunks = n;
+    a.r2 = r2;
+    a.gz0 = static_cast<int32_t>(D.lo[0]);
+    a.gz1 = static_cast<int32_t>(D.hi[0]);
+    a.gy0 = static_cast<int32_t>(D.lo[1]);
+    a.gy1 = static_cast<int32_t>(D.hi[1]);
+    a.gx0 = static_cast<int32_t>(D.lo[2]);
+    a.gx1 = static_cast<int32_t>(D.hi[2]);
+    if (tile_planes > 0) {
+      a.tile_planes = tile_planes;
+    } else {
+      int64_t zmax = 0;
+      for (int k = 0; k < n; ++k)
+        zmax = std::max<int64_t>(zmax, plans[first + k].chunk.hi[0] - plans[first + k].chunk.lo[0]);
+      auto blocks_of = [&](int32_t p) {
+        int64_t w = 0;
+        for (int k = 0; k < n; ++k) {
+          const Box &cb = plans[first + k].chunk;
+          w += tiles_of(cb.hi[0] - cb.lo[0], cb.hi[1] - cb.lo[1], cb.hi[2] - cb.lo[2], T, p);
+        }
+        return w;
+      };
+      a.tile_planes = plan_tile_rows(block_slots(T), T, 4,
+                                     static_cast<int32_t>(std::max<int64_t>(zmax, 4)), blocks_of);
+    }
+    int64_t tiles = 0;
+    for (int k = 0; k < n; ++k) {
+      const WaveChunkPlan &P = plans[first + k];
+      W3TChunk &C = a.ch[k];
+      C.in_prev = P.in_prev.base;
+      C.in_cur = P.in_cur.base;
+      C.out_prev = P.out_prev.base;
+      C.out_cur = P.out_cur.base;
+      const WaveField *fs[4] = {&P.in_prev, &P.in_cur, &P.out_prev, &P.out_cur};
+      Field3 *gs[4] = {&C.ip, &C.ic, &C.op, &C.oc};
+      for (int b = 0; b < 4; ++b) {
+        ccl_status st = field3_of(*fs[b], gs[b]);
+        if (st != CCL_OK) return st;
+        // patches start A (a multiple of 4) columns left of the chunk: its
+        // first column must sit on a 16-byte boundary of every buffer
+        if ((P.chunk.lo[2] - fs[b]->off[2]) % 4 != 0 || fs[b]->pitch[0] % 4 != 0 ||
+            fs[b]->pitch[1] % 4 != 0 || (reinterpret_cast<uintptr_t>(fs[b]->base) & 15u) != 0)
+          return fail(CCL_E_INVALID,
+                      "chunk %d: 3D buffers must be 16-byte aligned with strides a multiple of 4 "
+                      "and the chunk's first column on a multiple of 4 of the region",
+                      first + k);
+      }
+      box6(P.load_prev, C.lp);
+      box6(P.load_cur, C.lc);
+      C.cz0 = static_cast<int32_t>(P.chunk.lo[0]);
+      C.cz1 = static_cast<int32_t>(P.chunk.hi[0]);
+      C.cy0 = static_cast<int32_t>(P.chunk.lo[1]);
+      C.cy1 = static_cast<int32_t>(P.chunk.hi[1]);
+      C.cx0 = static_cast<int32_t>(P.chunk.lo[2]);
+      C.cx1 = static_cast<int32_t>(P.chunk.hi[2]);
+      const int64_t nz = P.chunk.hi[0] - P.chunk.lo[0];
+      const int64_t ny = P.chunk.hi[1] - P.chunk.lo[1];
+      const int64_t nx = P.chunk.hi[2] - P.chunk.lo[2];
+      C.nstrips = static_cast<int32_t>((nx + tb_out_cols(T) - 1) / tb_out_cols(T));
+      C.nrowblk = static_cast<int32_t>((ny + tb_out_rows(T) - 1) / tb_out_rows(T));
+      C.tile_begin = static_cast<int32_t>(tiles);
+      tiles += tiles_of(nz, ny, nx, T, a.tile_planes);
+      if (tiles > INT32_MAX / 2) return fail(CCL_E_RANGE, "too many tiles");
+    }
+    a.total_tiles = static_cast<int32_t>(tiles);
+    if (tiles == 0) continue;
+    ccl_status st;
+    switch (T) {
+      case 2: st = launch_t<2>(a, static_cast<int>(tiles), stream); break;
+      case 3: st = launch_t<3>(a, static_cast<int>(tiles), stream); break;
+      case 4: st = launch_t<4>(a, static_cast<int>(tiles), stream); break;
+      case 5: st = launch_t<5>(a, static_cast<int>(tiles), stream); break;
+      case 6: st = launch_t<6>(a, static_cast<int>(tiles), stream); break;
+      case 7: st = launch_t<7>(a, static_cast<int>(tiles), stream); break;
+      default: st = launch_t<8>(a, static_cast<int>(tiles), stream); break;
+    }
+    if (st != CCL_OK) return st;
+  }
+  return CCL_OK;
+}
+
+}  // namespace ccl

@@ -52,7 +52,6 @@ extern "C" ccl_status ccl_wave_step(const ccl_wave_params *p, int32_t nchunks,
   if (p->tile_rows < 0) return fail(CCL_E_INVALID, "tile_rows < 0");
   if (p->flags != 0) return fail(CCL_E_INVALID, "flags must be 0");
   if (nsteps < 0) return fail(CCL_E_INVALID, "nsteps < 0");
-  if (dims == 3 && T != 1) return fail(CCL_E_UNSUPPORTED, "3D stencil supports T == 1 only");
   ccl_status st = check_chunks(nchunks, chunks, dims);
   if (st != CCL_OK) return st;
   const bool need_w = T > 1 && nsteps > 1;

@@ -1,6 +1,6 @@
 """Learned launch-config selection: collect, train, evaluate.
 
-    python -m paper_2505_06022_amd.learn collect  --out DIR [--shapes 250 --per-shape 16]
+    python -m paper_2505_06022_amd.learn collect  --out DIR [--shapes 250 --per-shape 16 --append]
     python -m paper_2505_06022_amd.learn energy   --out DIR [--count 120 --window 1.0]
     python -m paper_2505_06022_amd.learn train    --data DIR/samples.json --model MODEL.json
     python -m paper_2505_06022_amd.learn evaluate --model MODEL.json --out DIR [--shapes 200]
@@ -37,30 +37,43 @@ def _log(msg):
     print(f"[learn] {msg}", flush=True)
 
 
-def collect(out_dir, n_shapes=250, per_shape=16, n_shapes_3d=40):
-    """Time samples of the seeded training configs, saved to samples.json."""
+def _key(k):
+    return (tuple(k[0]), int(k[1]), int(k[2]), int(k[3]))
+
+
+def collect(out_dir, n_shapes=250, per_shape=16, n_shapes_3d=40, append=False, budget_s=1e9):
+    """Time samples of the seeded training configs, saved to samples.json.
+    With `append`, configs already in samples.json are skipped and the new
+    samples are added to it (saved every 10 shapes)."""
     from . import ccl_costmodel_features, tune
     os.makedirs(out_dir, exist_ok=True)
     shapes, cfgs = tune.sample_space(n_shapes, TRAIN_SHAPE_SEED, per_shape, SAMPLE_SEED,
                                      n_shapes_3d)
-    _log(f"{len(cfgs)} configs over {len(shapes)} shapes")
+    doc = dict(samples=[], features=[], meta={})
+    path = os.path.join(out_dir, "samples.json")
+    if append and os.path.exists(path):
+        with open(path) as f:
+            doc = json.load(f)
+        have = {_key(s["key"]) for s in doc["samples"]}
+        cfgs = [c for c in cfgs if _key(tune.cfg_key(c)) not in have]
+    _log(f"{len(cfgs)} configs to measure over {len(shapes)} shapes")
     t0 = time.perf_counter()
-    samples = []
     by_shape = {}
     for c in cfgs:
         by_shape.setdefault(tuple(c.shape[:c.dims]), []).append(c)
-    order = []
     for i, (sh, cs) in enumerate(by_shape.items()):
-        samples.extend(tune.measure(cs))
-        order.extend(cs)
+        doc["samples"].extend(tune.measure(cs))
+        doc["features"].extend(ccl_costmodel_features(cs).tolist())
         if (i + 1) % 10 == 0:
+            _save(out_dir, doc)
             _log(f"  {i + 1}/{len(by_shape)} shapes, {time.perf_counter() - t0:.0f} s")
-    X = ccl_costmodel_features(order)
-    doc = dict(samples=samples, features=X.tolist(),
-               meta=dict(shapes=len(shapes), configs=len(order),
-                         seconds=time.perf_counter() - t0))
+        if time.perf_counter() - t0 > budget_s:
+            _log("time budget reached")
+            break
+    doc["meta"] = dict(shapes=len(shapes), configs=len(doc["samples"]),
+                       seconds=doc.get("meta", {}).get("seconds", 0.0) + time.perf_counter() - t0)
     _save(out_dir, doc)
-    _log(f"collected {len(samples)} time samples in {time.perf_counter() - t0:.0f} s")
+    _log(f"{len(doc['samples'])} time samples after {time.perf_counter() - t0:.0f} s")
     return doc
 
 
@@ -230,6 +243,8 @@ def main(argv=None):
     c.add_argument("--shapes", type=int, default=250)
     c.add_argument("--shapes-3d", type=int, default=40)
     c.add_argument("--per-shape", type=int, default=16)
+    c.add_argument("--append", action="store_true")
+    c.add_argument("--budget", type=float, default=1e9)
     en = sub.add_parser("energy")
     en.add_argument("--out", required=True)
     en.add_argument("--count", type=int, default=120)
@@ -258,7 +273,7 @@ def main(argv=None):
         import torch
         torch.cuda.set_device(0)
     if a.cmd == "collect":
-        collect(a.out, a.shapes, a.per_shape, a.shapes_3d)
+        collect(a.out, a.shapes, a.per_shape, a.shapes_3d, a.append, a.budget)
     elif a.cmd == "energy":
         energy(a.out, a.count, a.window, a.budget)
     elif a.cmd == "train":

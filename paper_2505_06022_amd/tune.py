@@ -31,20 +31,18 @@ from . import (CCL_MLP_NPARAMS, CCL_MLP_PARAMS, CCL_MLP_LOSS, ccl_autotune_measu
 
 K_SET = (1, 2, 4, 8, 16)
 ROWS_SET = (0, 16, 32, 64, 128)  # 0: the library's occupancy-aware choice
-T_SET_2D = tuple(range(1, 9))
+T_SET = tuple(range(1, 9))
 
 OBJECTIVES = {"time": (1.0, 0.0), "energy": (0.0, 1.0), "edp": (1.0, 1.0)}
 
 
 def candidates(shape):
-    dims = len(shape)
-    ts = T_SET_2D if dims == 2 else (1,)
     out = []
     for K in K_SET:
         if K > shape[0]:
             continue
         for rows in ROWS_SET:
-            for T in ts:
+            for T in T_SET:
                 out.append(make_tune_config(shape, K, T, rows))
     return out
 

@@ -176,11 +176,12 @@ def test_wave_step_validation_no_launch():
     ov[1].range[0] += 1
     assert call(good, _fake_buffers(chunks, regs1), _fake_buffers(chunks, regs1),
                 chunks=ov) == ccl.CCL_E_RANGE
-    # 3D with T > 1 is not available
+    # 3D with T > 1 also needs the second buffer pair
     c3 = ccl.ccl_split_range((0, 0, 0), (8, 8, 8), 1)
     p3 = ccl.make_wave_params(3, 0.1, 2)
     r3 = [c3[0].box()]
-    assert call(p3, _fake_buffers(c3, r3), _fake_buffers(c3, r3), chunks=c3) == ccl.CCL_E_UNSUPPORTED
+    assert call(p3, _fake_buffers(c3, r3), _fake_buffers(c3, r3), chunks=c3) == ccl.CCL_E_INVALID
+    assert "w_prev" in ccl.ccl_last_error()
     # zero steps is a no-op that succeeds without touching memory
     assert call(good, _fake_buffers(chunks, regs1), _fake_buffers(chunks, regs1), n=0) == ccl.CCL_OK
 

@@ -245,6 +245,29 @@ def test_wave3d_ragged(K):
     assert_bitwise(gc, ref, f"3D K={K}")
 
 
+@pytest.mark.parametrize("T", [2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("K", [1, 3])
+def test_wave3d_depths(T, K):
+    """Temporally blocked 3D kernel: several patches in x (56 or 48 output
+    columns) and y, ragged tails, 25 steps = blocks of T plus a shorter one."""
+    shape = (21, 70, 150)
+    u_prev = synth.gaussian_field(shape, 6.0, seed=17)
+    u_cur = synth.gaussian_field(shape, 6.5, seed=18)
+    ref_prev, ref = oracle.wave(u_prev, u_cur, 0.1, 25)
+    gp, gc = gpu_run(u_prev, u_cur, 0.1, 25, K, T)
+    assert_bitwise(gc, ref, f"3D T={T} K={K}")
+    assert_bitwise(gp, ref_prev, f"3D T={T} K={K} (u^(n-1))")
+
+
+def test_wave3d_depth_tile_planes():
+    shape = (33, 20, 64)
+    u0 = synth.gaussian_field(shape, 5.0, seed=16)
+    _, ref = oracle.wave(u0.copy(), u0, 0.1, 12)
+    for tp in (1, 5, 64):
+        _, gc = gpu_run(u0, u0, 0.1, 12, 2, 4, tile_rows=tp)
+        assert_bitwise(gc, ref, f"3D T=4 tile_planes={tp}")
+
+
 def test_wave3d_tile_planes():
     shape = (33, 20, 64)
     u0 = synth.gaussian_field(shape, 5.0, seed=16)
@@ -266,6 +289,9 @@ def test_wave3d_768_full_size():
     _, a = gpu_run(u0, u0, w["r2"], w["steps"], w["chunks"], 1, fill=0.0)
     _, b = gpu_run(u0, u0, w["r2"], w["steps"], 1, 1, fill=0.0)
     assert np.all(np.isfinite(a)) and np.array_equal(a, b)
+    del b
+    _, c = gpu_run(u0, u0, w["r2"], w["steps"], w["chunks"], 4, fill=0.0)
+    assert np.array_equal(a, c), "768^3: T=4 differs from T=1"
 
 
 # ------------------------------------------------------------ measurement --
@@ -314,10 +340,12 @@ def test_degenerate_shapes(shape, K, T):
     assert_bitwise(gc, ref, f"{shape} K={K} T={T}")
 
 
-@pytest.mark.parametrize("shape,K", [((1, 1, 1), 1), ((3, 1, 5), 3), ((7, 9, 1), 2),
-                                     ((2, 300, 260), 2)])
-def test_degenerate_shapes_3d(shape, K):
+@pytest.mark.parametrize("shape,K,T", [((1, 1, 1), 1, 1), ((3, 1, 5), 3, 1), ((7, 9, 1), 2, 1),
+                                       ((2, 300, 260), 2, 1), ((1, 1, 1), 1, 2),
+                                       ((3, 1, 5), 3, 4), ((7, 9, 1), 2, 8),
+                                       ((2, 300, 260), 2, 3), ((9, 2, 70), 9, 6)])
+def test_degenerate_shapes_3d(shape, K, T):
     u0 = synth.gaussian_field(shape, 2.0, seed=22)
     _, ref = oracle.wave(u0.copy(), u0, 0.1, 9)
-    _, gc = gpu_run(u0, u0, 0.1, 9, K, 1)
-    assert_bitwise(gc, ref, f"3D {shape} K={K}")
+    _, gc = gpu_run(u0, u0, 0.1, 9, K, T)
+    assert_bitwise(gc, ref, f"3D {shape} K={K} T={T}")

@@ -11,7 +11,7 @@ def test_candidate_space():
     assert {c.temporal_depth for c in c2} == set(range(1, 9))
     assert len(tune.candidates((8, 4096))) == 4 * 5 * 8  # K = 16 > 8 rows dropped
     c3 = tune.candidates((96, 768, 768))
-    assert {c.temporal_depth for c in c3} == {1} and len(c3) == 5 * 5
+    assert {c.temporal_depth for c in c3} == set(range(1, 9)) and len(c3) == 5 * 5 * 8
 
 
 def test_sample_space_seeded():
