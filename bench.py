@@ -199,21 +199,36 @@ def batched_forms(log_energy=False):
     bw.close()
     del bw
     torch.cuda.empty_cache()
-    # per-grid loop of plain calls on the same grids
-    t_loop = 0.0
-    for d in grids:
+    # per-grid loop of plain (T=1) calls on the same grids, same data
+    cws = []
+    for g, d in enumerate(grids):
         cw = ChunkedWave((0, 0), (d["ny"], d["nx"]), 1, 0.25, depth=1)
-        cw.step(d["steps"])
-        t_loop += time_runs(cw, d["steps"], 1)
-        del cw
+        u0 = synth.gaussian_field((d["ny"], d["nx"]), d["sigma"], d["seed"])
+        cw.scatter(u0, u0)
+        cws.append(cw)
+
+    def loop_once():
+        for cw, d in zip(cws, grids):
+            cw.step(d["steps"])
+
+    loop_once()
+    torch.cuda.synchronize()
+    a.record()
+    loop_once()
+    b.record()
+    torch.cuda.synchronize()
+    t_loop = a.elapsed_time(b) * 1e-3
+    p_loop = average_power(loop_once) if log_energy else None
+    del cws
     torch.cuda.empty_cache()
+    nj = lambda p, t: None if p is None else round(p * t / cell_steps * 1e9, 4)
     return {"grids": len(grids), "cell_steps": cell_steps,
             "batched_mcells": round(cell_steps / t_batched / 1e6, 1),
             "batched_ms": round(t_batched * 1e3, 3),
             "per_grid_loop_mcells": round(cell_steps / t_loop / 1e6, 1),
             "per_grid_loop_ms": round(t_loop * 1e3, 3),
-            "batched_nj_per_cell_step": None if p_batched is None else
-            round(p_batched * t_batched / cell_steps * 1e9, 4),
+            "batched_nj_per_cell_step": nj(p_batched, t_batched),
+            "per_grid_loop_nj_per_cell_step": nj(p_loop, t_loop),
             "configs": "cost model" if model is not None else "T=4, 64 rows"}
 
 
@@ -365,6 +380,9 @@ def main():
         cp.step(w["steps"])
         t_plain = time_runs(cp, w["steps"], 2)
         out["plain_mcells"] = round(cells * w["steps"] * 2 / t_plain / 1e6, 1)
+        if out.get("j_per_step") is not None:
+            p_plain = average_power(lambda: cp.step(w["steps"]))
+            out["plain_j_per_step"] = round(p_plain * t_plain / (2 * w["steps"]), 6)
         del cp
         torch.cuda.empty_cache()
         log("SAXPY calibration")

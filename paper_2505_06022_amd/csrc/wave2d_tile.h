@@ -6,7 +6,7 @@
 // The wave streams down the rows: at iteration i it loads row i of u^n and
 // row i-1 of u^{n-1}, then computes level 2 at row i-1, level 3 at row i-2,
 // ..., level T+1 at row i-T, keeping the last three rows of every level in
-// registers.  North/south neighbours come from that register ring; west/east
+// registers (rotating slots, so no row is moved between iterations).  North/south neighbours come from that register ring; west/east
 // neighbours from the adjacent lane through DPP wave shifts (no LDS, no
 // barriers).  A level-(k+1) value is only valid where its whole dependency
 // cone was loaded, so strips overlap by 4*ceil(T/4) columns on each side and
@@ -27,10 +27,10 @@
 namespace ccl {
 namespace w2 {
 
-#ifndef CCL_W2_PREFETCH
-#define CCL_W2_PREFETCH 3
-#endif
-constexpr int kPrefetch = CCL_W2_PREFETCH;  // rows loaded ahead of use
+// Rows loaded ahead of use.  It equals the ring length, so the unrolled
+// body's copy u finds every level's newest row in ring slot u and nothing
+// is moved between iterations.
+constexpr int kPrefetch = 3;
 
 // Overlap columns per side and output columns per strip for depth T.
 __host__ __device__ constexpr int overlap(int T) { return 4 * ((T + 3) / 4); }
@@ -165,9 +165,14 @@ __device__ __forceinline__ float4 force_zero(float4 v, bool row_in, const Cols &
 // Advances one tile (segment `seg`, strip `strip` of chunk C) by T steps.
 // Strips are 256 columns wide and overlap their neighbours by A columns on
 // each side (A >= T, a multiple of 4); each writes SW = 256 - 2A columns.
+// The descriptors are copied into registers once: read through a reference
+// inside the loop, they would be reloaded after every store (the compiler
+// cannot rule out that a store aliases them).
 template <int T, bool IN_PLACE>
-__device__ __forceinline__ void tile(const Chunk &C, const Domain &D, float r2, int tile_rows,
-                                     int seg, int strip, int lane, int A) {
+__device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, float r2,
+                                     int tile_rows, int seg, int strip, int lane, int A) {
+  const Chunk C = Cref;
+  const Domain D = Dref;
   const int SW = 256 - 2 * A;
   const int y0 = C.cy0 + seg * tile_rows;
   const int y1 = min(C.cy1, y0 + tile_rows);
@@ -188,50 +193,48 @@ __device__ __forceinline__ void tile(const Chunk &C, const Domain &D, float r2, 
   // a strip whose 256 columns all lie in the domain needs no column mask
   const bool interior_cols = xs >= D.gx0 && xs + 256 <= D.gx1;
 
+  // ring[k][s]: the last three rows of level k in rotating slots; at the
+  // unrolled copy u the newest row goes to slot u, the middle one is in
+  // (u+2)%3 and the oldest in (u+1)%3
   float4 ring[T][3];
 #pragma unroll
   for (int k = 0; k < T; ++k) ring[k][0] = ring[k][1] = ring[k][2] = zero4();
 
-  const int i0 = y0 - T;
-  const int iend = y1 + T;  // exclusive
+  const int first = y0 - T;
+  const int nrows = (y1 - y0) + 2 * T;
   float4 q1[kPrefetch], q0[kPrefetch];
 #pragma unroll
   for (int u = 0; u < kPrefetch; ++u) {
-    q1[u] = load4<false>(C.in_cur, C.ic_y0, C.ic_x0, C.ic_pitch, i0 + u, xl, C.lc_y0, C.lc_y1,
+    q1[u] = load4<false>(C.in_cur, C.ic_y0, C.ic_x0, C.ic_pitch, first + u, xl, C.lc_y0, C.lc_y1,
                          lc);
-    q0[u] = load4<true>(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch, i0 + u - 1, xl, lpy0, lpy1,
+    q0[u] = load4<true>(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch, first + u - 1, xl, lpy0, lpy1,
                         lp);
   }
 
-  for (int base = i0; base < iend; base += kPrefetch) {
+  for (int jb = 0; jb < nrows; jb += kPrefetch) {
 #pragma unroll
     for (int u = 0; u < kPrefetch; ++u) {
-      const int i = base + u;
-      const float4 v1 = q1[u];
-      const float4 v0 = q0[u];
+      const int NEW = u, MID = (u + 2) % 3, OLD = (u + 1) % 3;
+      const int i = first + jb + u;  // row of level 0 arriving now
+      ring[0][NEW] = q1[u];
+      float4 pv = q0[u];
       q1[u] = load4<false>(C.in_cur, C.ic_y0, C.ic_x0, C.ic_pitch, i + kPrefetch, xl, C.lc_y0,
                            C.lc_y1, lc);
       q0[u] = load4<true>(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch, i + kPrefetch - 1, xl, lpy0,
                           lpy1, lp);
-      ring[0][0] = ring[0][1];
-      ring[0][1] = ring[0][2];
-      ring[0][2] = v1;
-      float4 pv = v0;
 #pragma unroll
       for (int k = 1; k <= T; ++k) {
-        const int r = i - k;  // row of level k+1 computed now
-        float4 nv = step4(ring[k - 1][0], ring[k - 1][1], ring[k - 1][2], pv, r2);
+        const int r = i - k;  // row of level k computed now
+        float4 nv = step4(ring[k - 1][OLD], ring[k - 1][MID], ring[k - 1][NEW], pv, r2);
         const bool row_in = r >= D.gy0 && r < D.gy1;  // wave-uniform
         if (!(row_in && interior_cols)) nv = force_zero(nv, row_in, dom);
         if (k < T) {
-          pv = ring[k - 1][0];
-          ring[k][0] = ring[k][1];
-          ring[k][1] = ring[k][2];
-          ring[k][2] = nv;
+          pv = ring[k - 1][OLD];
+          ring[k < T ? k : 0][NEW] = nv;
         } else if (r >= y0 && r < y1) {
           store4(C.out_cur, C.oc_y0, C.oc_x0, C.oc_pitch, r, xl, out, nv);
           if (!IN_PLACE)
-            store4(C.out_prev, C.op_y0, C.op_x0, C.op_pitch, r, xl, out, ring[T - 1][1]);
+            store4(C.out_prev, C.op_y0, C.op_x0, C.op_pitch, r, xl, out, ring[T - 1][MID]);
         }
       }
     }

@@ -110,7 +110,7 @@ __global__ __launch_bounds__(kThreads) void wave3d_kernel(const W3Args a) {
   if (tile >= a.total_tiles) return;
   int c = 0;
   while (c + 1 < a.nchunks && tile >= a.ch[c + 1].tile_begin) ++c;
-  const W3Chunk &C = a.ch[c];
+  const W3Chunk C = a.ch[c];  // in registers: not reloaded after stores
 
   // tile order: strip fastest, then row block, then z segment
   int local = tile - C.tile_begin;

@@ -34,16 +34,25 @@ constexpr int kThreads = 256;
 constexpr int kPatchCols = 64;
 constexpr int kMaxChunksPerLaunch = 8;
 
-// Rows per thread, overlap, output extent and LDS buffering for depth T.
+// Rows per thread, planes loaded ahead, overlap, output extent and LDS
+// buffering for depth T.
 #ifndef CCL_W3T_ROWS
-__host__ __device__ constexpr int tb_rows(int T) { return T <= 4 ? 4 : (T <= 6 ? 3 : 2); }
-#else
+#define CCL_W3T_ROWS 2
+#endif
 __host__ __device__ constexpr int tb_rows(int) { return CCL_W3T_ROWS; }
+#ifndef CCL_W3T_PF
+__host__ __device__ constexpr int tb_prefetch(int) { return 1; }
+#else
+__host__ __device__ constexpr int tb_prefetch(int) { return CCL_W3T_PF; }
 #endif
 __host__ __device__ constexpr int tb_overlap(int T) { return 4 * ((T + 3) / 4); }
 __host__ __device__ constexpr int tb_out_cols(int T) { return kPatchCols - 2 * tb_overlap(T); }
 __host__ __device__ constexpr int tb_out_rows(int T) { return 16 * tb_rows(T) - 2 * T; }
+#ifndef CCL_W3T_NB
 __host__ __device__ constexpr int tb_lds_buffers(int T) { return T <= 4 ? 2 : 1; }
+#else
+__host__ __device__ constexpr int tb_lds_buffers(int) { return CCL_W3T_NB; }
+#endif
 
 struct Field3 {  // a chunk buffer: global index of its first element, strides
   int32_t z0, y0, x0;
@@ -81,23 +90,49 @@ __device__ __forceinline__ float row_from_right(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xf, 0xf, false));
 }
 
-__device__ __forceinline__ int64_t at(const Field3 &f, int z, int y, int x) {
-  return static_cast<int64_t>(z - f.z0) * f.pz + static_cast<int64_t>(y - f.y0) * f.py + (x - f.x0);
+// One buffer as the streaming loop sees it: its base, the plane index of
+// its origin and the plane stride (block-uniform), and per thread the
+// element offset, within a plane, of each of the thread's rows (32 bits:
+// strides are checked to fit in int32 on the host).  A row that the
+// buffer does not hold has an offset that is never used.
+template <int P>
+struct Rows {
+  const float *base;
+  int32_t z0;
+  int32_t pz;
+  uint32_t off[P];
+};
+
+template <int P>
+__device__ __forceinline__ Rows<P> rows_of(const float *base, const Field3 &f, int yl, int xl) {
+  Rows<P> r;
+  r.base = base;
+  r.z0 = f.z0;
+  r.pz = f.pz;
+#pragma unroll
+  for (int j = 0; j < P; ++j)
+    r.off[j] = static_cast<uint32_t>((yl + j - f.y0) * f.py + (xl - f.x0));
+  return r;
 }
 
-// The thread's P rows of plane z (zero outside the loadable box `lb`).
-// STREAM marks data read once (u^{n-1}).
+template <int P>
+__device__ __forceinline__ const float *plane_of(const Rows<P> &b, int z) {
+  return b.base + static_cast<int64_t>(z - b.z0) * b.pz;
+}
+
+// The thread's P rows of plane z: zero outside the loadable box (planes
+// [lz0, lz1), rows where ok[j], columns in cx).  STREAM marks data read
+// once (u^{n-1}).
 template <bool STREAM, int P>
-__device__ __forceinline__ void load_rows(float4 (&v)[P], const float *base, const Field3 &f,
-                                          const int32_t *lb, const w2::Cols &cx, int z, int yl,
-                                          int xl) {
-  const bool zin = z >= lb[0] && z < lb[1];
+__device__ __forceinline__ void load_rows(float4 (&v)[P], const Rows<P> &b, int z, int lz0,
+                                          int lz1, const bool (&ok)[P], const w2::Cols &cx) {
+  const bool zin = z >= lz0 && z < lz1;  // block-uniform
+  const float *plane = plane_of(b, z);
 #pragma unroll
   for (int j = 0; j < P; ++j) {
-    const int y = yl + j;
     float4 r = w2::zero4();
-    if (zin && y >= lb[2] && y < lb[3] && cx.any) {
-      const w2::f4v *p = reinterpret_cast<const w2::f4v *>(base + at(f, z, y, xl));
+    if (zin && ok[j] && cx.any) {
+      const w2::f4v *p = reinterpret_cast<const w2::f4v *>(plane + b.off[j]);
       const w2::f4v q = STREAM ? __builtin_nontemporal_load(p) : *p;
       r = make_float4(q.x, q.y, q.z, q.w);
     }
@@ -113,9 +148,8 @@ __device__ __forceinline__ void load_rows(float4 (&v)[P], const float *base, con
 // at a chunk's x edges; their other columns are halo cells of this chunk's
 // own output buffer that nothing writes during the launch, so they are read
 // and written back unchanged (one 16-byte store).
-__device__ __forceinline__ void store_group(float *base, const Field3 &f, int z, int y, int xl,
-                                            const w2::Cols &c, const float4 &v) {
-  w2::f4v *p = reinterpret_cast<w2::f4v *>(base + at(f, z, y, xl));
+__device__ __forceinline__ void store_group(float *p_, const w2::Cols &c, const float4 &v) {
+  w2::f4v *p = reinterpret_cast<w2::f4v *>(p_);
   w2::f4v w = {v.x, v.y, v.z, v.w};
   if (!(c.m0 && c.m1 && c.m2 && c.m3)) {
     const w2::f4v o = *p;
@@ -127,49 +161,27 @@ __device__ __forceinline__ void store_group(float *base, const Field3 &f, int z,
   __builtin_nontemporal_store(w, p);
 }
 
+// What the streaming loop of one block needs, gathered once (in registers,
+// so nothing is reloaded from the kernel arguments after a store).
+template <int P>
+struct Patch {
+  Rows<P> ic, ip, oc, op;
+  int32_t lc_z0, lc_z1, lp_z0, lp_z1;  // loadable planes of u^n, u^{n-1}
+  int32_t gz0, gz1;                     // domain planes
+  int32_t zo0, zo1;                     // output planes of this segment
+  bool ok_c[P], ok_p[P], out_row[P], dom_row[P];
+  w2::Cols lcx, lpx, dom, out;
+  bool xy_in;                           // patch inside the domain in x and y
+};
+
+// xch: the block's LDS words, [buffer][level][first row / last row][thread].
 template <int T>
-__global__ __launch_bounds__(kThreads) void wave3d_tb_kernel(const W3TArgs a) {
+__device__ __forceinline__ void stream_patch(const Patch<tb_rows(T)> &S, float r2, int tid,
+                                             float4 (*xch)[T][2][kThreads]) {
   constexpr int P = tb_rows(T);
-  constexpr int A = tb_overlap(T);
-  constexpr int OW = tb_out_cols(T);
-  constexpr int OH = tb_out_rows(T);
   constexpr int NB = tb_lds_buffers(T);
-  // [buffer][level][first row / last row][thread]
-  __shared__ float4 xch[NB][T][2][kThreads];
-
-  const int blk = w2::xcd_block(blockIdx.x, gridDim.x);
-  if (blk >= a.total_tiles) return;  // the whole block leaves together
-  int c = 0;
-  while (c + 1 < a.nchunks && blk >= a.ch[c + 1].tile_begin) ++c;
-  const W3TChunk &C = a.ch[c];
-
-  // tile order: strip fastest, then row block, then z segment
-  int local = blk - C.tile_begin;
-  const int per_seg = C.nstrips * C.nrowblk;
-  const int seg = local / per_seg;
-  local -= seg * per_seg;
-  const int rb = local / C.nstrips;
-  const int strip = local - rb * C.nstrips;
-
-  const int tid = threadIdx.x;
-  const int lx = tid & 15, ly = tid >> 4;
-  const int zo0 = C.cz0 + seg * a.tile_planes;
-  const int zo1 = min(C.cz1, zo0 + a.tile_planes);
-  const int px = C.cx0 - A + strip * OW;  // patch origin
-  const int py = C.cy0 - T + rb * OH;
-  const int xl = px + 4 * lx;
-  const int yl = py + ly * P;
-  const int oy0 = max(C.cy0, py + T), oy1 = min(C.cy1, py + T + OH);
-  const float r2 = a.r2;
-
-  const w2::Cols dom = w2::cols_of(xl, a.gx0, a.gx1);
-  const w2::Cols out = w2::cols_of(xl, max(C.cx0, px + A), min(C.cx1, px + A + OW));
-  const w2::Cols lcx = w2::cols_of(xl, C.lc[4], C.lc[5]);
-  const w2::Cols lpx = w2::cols_of(xl, C.lp[4], C.lp[5]);
-  // a patch whose rows and columns all lie in the domain needs no masks
-  // except at planes outside it
-  const bool xy_in =
-      px >= a.gx0 && px + kPatchCols <= a.gx1 && py >= a.gy0 && py + 16 * P <= a.gy1;
+  constexpr int PF = tb_prefetch(T);
+  static_assert(PF == 1 || PF == 3, "prefetch depth is 1 or 3 planes");
 
   float4 ring[T][3][P];  // level l: planes i-l-2, i-l-1, i-l in rotating slots
 #pragma unroll
@@ -179,11 +191,17 @@ __global__ __launch_bounds__(kThreads) void wave3d_tb_kernel(const W3TArgs a) {
 #pragma unroll
       for (int j = 0; j < P; ++j) ring[l][s][j] = w2::zero4();
 
-  const int i0 = zo0 - T;
-  const int n_iter = (zo1 - zo0) + 2 * T;
-  float4 qn[P], pn[P];  // next plane of u^n, of u^{n-1}
-  load_rows<false>(qn, C.in_cur, C.ic, C.lc, lcx, i0, yl, xl);
-  load_rows<true>(pn, C.in_prev, C.ip, C.lp, lpx, i0 - 1, yl, xl);
+  const int i0 = S.zo0 - T;
+  const int n_iter = (S.zo1 - S.zo0) + 2 * T;
+  // planes loaded ahead: u^n of planes i..i+PF-1 and u^{n-1} of the plane
+  // before each; with PF = 3 plane i sits in slot i - i0 mod 3, the
+  // iteration's phase, so the slots rotate without moves
+  float4 qs[PF][P], ps[PF][P];
+#pragma unroll
+  for (int f = 0; f < PF; ++f) {
+    load_rows<false>(qs[f], S.ic, i0 + f, S.lc_z0, S.lc_z1, S.ok_c, S.lcx);
+    load_rows<true>(ps[f], S.ip, i0 + f - 1, S.lp_z0, S.lp_z1, S.ok_p, S.lpx);
+  }
 
   // One iteration; PH = iteration count mod 3 names the ring slots: before
   // it the newest plane of every level sits in slot (PH+2)%3, after it in
@@ -201,21 +219,22 @@ __global__ __launch_bounds__(kThreads) void wave3d_tb_kernel(const W3TArgs a) {
     __syncthreads();
 
     // level 0: plane i of u^n arrives; u^{n-1} of plane i-1 for level 1
+    constexpr int QS = PF == 3 ? PH : 0;
 #pragma unroll
-    for (int j = 0; j < P; ++j) ring[0][NEW][j] = qn[j];
+    for (int j = 0; j < P; ++j) ring[0][NEW][j] = qs[QS][j];
     float4 pc[P];
 #pragma unroll
-    for (int j = 0; j < P; ++j) pc[j] = pn[j];
-    load_rows<false>(qn, C.in_cur, C.ic, C.lc, lcx, i + 1, yl, xl);
-    load_rows<true>(pn, C.in_prev, C.ip, C.lp, lpx, i, yl, xl);
+    for (int j = 0; j < P; ++j) pc[j] = ps[QS][j];
+    load_rows<false>(qs[QS], S.ic, i + PF, S.lc_z0, S.lc_z1, S.ok_c, S.lcx);
+    load_rows<true>(ps[QS], S.ip, i + PF - 1, S.lp_z0, S.lp_z1, S.ok_p, S.lpx);
 
 #pragma unroll
     for (int t = 1; t <= T; ++t) {
       const int r = i - t;  // plane of u^{n+t} computed now
-      const bool z_in = r >= a.gz0 && r < a.gz1;  // block-uniform
+      const bool z_in = r >= S.gz0 && r < S.gz1;  // block-uniform
       // outer y-neighbours of this thread's rows in plane r of u^{n+t-1}
       // (the top thread row reads the bottom one's words: patch-edge cells
-      // are never valid, so any finite or non-finite value is harmless)
+      // are never valid, so any value there is harmless)
       const float4 up = xch[b][t - 1][1][(tid - 16) & (kThreads - 1)];
       const float4 dn = xch[b][t - 1][0][(tid + 16) & (kThreads - 1)];
       float4 o[P];
@@ -234,26 +253,26 @@ __global__ __launch_bounds__(kThreads) void wave3d_tb_kernel(const W3TArgs a) {
         v.y = cell3(zm.y, zp.y, ym.y, yp.y, cc.x, cc.z, cc.y, pv.y, r2);
         v.z = cell3(zm.z, zp.z, ym.z, yp.z, cc.y, cc.w, cc.z, pv.z, r2);
         v.w = cell3(zm.w, zp.w, ym.w, yp.w, cc.z, xp3, cc.w, pv.w, r2);
-        if (!(xy_in && z_in)) {
-          const int y = yl + j;
-          const bool in = z_in && y >= a.gy0 && y < a.gy1;
-          v.x = (in && dom.m0) ? v.x : 0.0f;
-          v.y = (in && dom.m1) ? v.y : 0.0f;
-          v.z = (in && dom.m2) ? v.z : 0.0f;
-          v.w = (in && dom.m3) ? v.w : 0.0f;
+        if (!(S.xy_in && z_in)) {
+          const bool in = z_in && S.dom_row[j];
+          v.x = (in && S.dom.m0) ? v.x : 0.0f;
+          v.y = (in && S.dom.m1) ? v.y : 0.0f;
+          v.z = (in && S.dom.m2) ? v.z : 0.0f;
+          v.w = (in && S.dom.m3) ? v.w : 0.0f;
         }
         o[j] = v;
       }
       if (t < T) {
 #pragma unroll
         for (int j = 0; j < P; ++j) ring[t < T ? t : 0][NEW][j] = o[j];
-      } else if (r >= zo0 && r < zo1 && out.any) {
+      } else if (r >= S.zo0 && r < S.zo1 && S.out.any) {
+        float *pcur = const_cast<float *>(plane_of(S.oc, r));
+        float *pprev = const_cast<float *>(plane_of(S.op, r));
 #pragma unroll
         for (int j = 0; j < P; ++j) {
-          const int y = yl + j;
-          if (y < oy0 || y >= oy1) continue;
-          store_group(C.out_cur, C.oc, r, y, xl, out, o[j]);
-          store_group(C.out_prev, C.op, r, y, xl, out, ring[T - 1][MID][j]);
+          if (!S.out_row[j]) continue;
+          store_group(pcur + S.oc.off[j], S.out, o[j]);
+          store_group(pprev + S.op.off[j], S.out, ring[T - 1][MID][j]);
         }
       }
     }
@@ -264,6 +283,65 @@ __global__ __launch_bounds__(kThreads) void wave3d_tb_kernel(const W3TArgs a) {
     if (n + 1 < n_iter) iteration(std::integral_constant<int, 1>(), i0 + n + 1);
     if (n + 2 < n_iter) iteration(std::integral_constant<int, 2>(), i0 + n + 2);
   }
+}
+
+template <int T>
+__global__ __launch_bounds__(kThreads) void wave3d_tb_kernel(const W3TArgs a) {
+  constexpr int P = tb_rows(T);
+  constexpr int A = tb_overlap(T);
+  constexpr int OW = tb_out_cols(T);
+  constexpr int OH = tb_out_rows(T);
+
+  const int blk = w2::xcd_block(blockIdx.x, gridDim.x);
+  if (blk >= a.total_tiles) return;  // the whole block leaves together
+  int c = 0;
+  while (c + 1 < a.nchunks && blk >= a.ch[c + 1].tile_begin) ++c;
+  const W3TChunk &C = a.ch[c];
+
+  // tile order: strip fastest, then row block, then z segment
+  int local = blk - C.tile_begin;
+  const int per_seg = C.nstrips * C.nrowblk;
+  const int seg = local / per_seg;
+  local -= seg * per_seg;
+  const int rb = local / C.nstrips;
+  const int strip = local - rb * C.nstrips;
+
+  const int tid = threadIdx.x;
+  const int lx = tid & 15, ly = tid >> 4;
+  const int px = C.cx0 - A + strip * OW;  // patch origin
+  const int py = C.cy0 - T + rb * OH;
+  const int xl = px + 4 * lx;
+  const int yl = py + ly * P;
+  const int oy0 = max(C.cy0, py + T), oy1 = min(C.cy1, py + T + OH);
+
+  Patch<P> S;
+  S.ic = rows_of<P>(C.in_cur, C.ic, yl, xl);
+  S.ip = rows_of<P>(C.in_prev, C.ip, yl, xl);
+  S.oc = rows_of<P>(C.out_cur, C.oc, yl, xl);
+  S.op = rows_of<P>(C.out_prev, C.op, yl, xl);
+  S.lc_z0 = C.lc[0];
+  S.lc_z1 = C.lc[1];
+  S.lp_z0 = C.lp[0];
+  S.lp_z1 = C.lp[1];
+  S.gz0 = a.gz0;
+  S.gz1 = a.gz1;
+  S.zo0 = C.cz0 + seg * a.tile_planes;
+  S.zo1 = min(C.cz1, S.zo0 + a.tile_planes);
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int y = yl + j;
+    S.ok_c[j] = y >= C.lc[2] && y < C.lc[3];
+    S.ok_p[j] = y >= C.lp[2] && y < C.lp[3];
+    S.out_row[j] = y >= oy0 && y < oy1;
+    S.dom_row[j] = y >= a.gy0 && y < a.gy1;
+  }
+  S.lcx = w2::cols_of(xl, C.lc[4], C.lc[5]);
+  S.lpx = w2::cols_of(xl, C.lp[4], C.lp[5]);
+  S.dom = w2::cols_of(xl, a.gx0, a.gx1);
+  S.out = w2::cols_of(xl, max(C.cx0, px + A), min(C.cx1, px + A + OW));
+  S.xy_in = px >= a.gx0 && px + kPatchCols <= a.gx1 && py >= a.gy0 && py + 16 * P <= a.gy1;
+  __shared__ float4 xch[tb_lds_buffers(T)][T][2][kThreads];
+  stream_patch<T>(S, a.r2, tid, xch);
 }
 
 template <int T>

@@ -25,9 +25,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SAXPY_N = 1 << 26
 
 
-def kernel_source_hash() -> str:
+SOURCES = {2: ("wave2d_tile.h", "wave2d.hip", "wave_step.cpp", "halo.hip"),
+           3: ("wave3d_cell.h", "wave3d.hip", "wave3d_tb.hip", "wave_step.cpp", "halo.hip")}
+
+
+def kernel_source_hash(dims: int = 2) -> str:
     h = hashlib.sha256()
-    for name in ("wave2d_tile.h", "wave2d.hip", "wave_step.cpp", "halo.hip"):
+    for name in SOURCES[dims]:
         with open(os.path.join(ROOT, "paper_2505_06022_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -44,7 +48,8 @@ def run(depth: int, rows: int, blocks: int = 6, dims: int = 2):
     name = "wave2d_8192_share_k4" if dims == 2 else "wave3d_768_k8"
     w = synth.WORKLOADS[name]
     u0 = synth.gaussian_field(w["shape"], w["sigma"], w["seed"])
-    cw = ChunkedWave(w["share_offset"], w["shape"], w["chunks"], w["r2"], depth=depth,
+    cw = ChunkedWave(w.get("share_offset", (0,) * len(w["shape"])), w["shape"], w["chunks"],
+                     w["r2"], depth=depth,
                      tile_rows=rows, buffer_range=w.get("global_shape"))
     cw.scatter(u0, u0)
     cw.step(depth * blocks)
@@ -68,7 +73,7 @@ def _per_kernel(path, counter):
             name = row.get("Kernel_Name", "")
             val = float(row.get("Counter_Value", "nan"))
             key = ("wave2d" if "wave2d_kernel" in name else
-                   "wave3d" if "wave3d_kernel" in name else
+                   "wave3d" if ("wave3d_kernel" in name or "wave3d_tb_kernel" in name) else
                    "saxpy" if "saxpy_kernel" in name else
                    "halo" if "copy_boxes_kernel" in name else None)
             if key:
@@ -93,7 +98,7 @@ def summarise(fetch_csv, write_csv, depth, rows, md_path, dims=2):
     alg = (12 if depth == 1 else 16) * cells
     wl = "8192x8192 share, 4 chunks" if dims == 2 else "768^3, 8 chunks"
     doc = dict(kernel=f"{kern}_kernel", workload=wl, depth=depth,
-               tile_rows=rows, kernel_hash=kernel_source_hash(),
+               tile_rows=rows, kernel_hash=kernel_source_hash(dims),
                fetch_kib_per_dispatch_raw=sum(fw) / len(fw),
                write_kib_per_dispatch_raw=sum(ww) / len(ww),
                fetch_scale=f_scale, write_scale=w_scale,
@@ -103,11 +108,22 @@ def summarise(fetch_csv, write_csv, depth, rows, md_path, dims=2):
         f"# HBM traffic of the {kern} stencil launch — {wl}, T={depth}, "
         f"{rows if rows else 'automatic'} rows per tile",
         "",
-        "Counters from two rocprofv3 runs (`--pmc FETCH_SIZE`, then `--pmc WRITE_SIZE`) of "
-        "`python3 -m paper_2505_06022_amd.profile_run run --dims "
-        f"{dims} --depth {depth} --rows {rows}`, scaled by what the same counters read for a "
-        "SAXPY of "
-        f"{SAXPY_N} floats (8 B read, 4 B written per element).",
+        "Counters from two rocprofv3 runs, one per counter, scaled by what the same counters "
+        f"read for a SAXPY of {SAXPY_N} floats (8 B read, 4 B written per element) launched "
+        "at the end of the same program:",
+        "",
+        "```",
+        f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/fetch -o p -- python3 -m "
+        f"paper_2505_06022_amd.profile_run run --dims {dims} --depth {depth} --rows {rows}",
+        f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/write -o p -- python3 -m "
+        f"paper_2505_06022_amd.profile_run run --dims {dims} --depth {depth} --rows {rows}",
+        f"python3 -m paper_2505_06022_amd.profile_run summarise --fetch OUT/fetch/.../"
+        f"p_counter_collection.csv --write OUT/write/.../p_counter_collection.csv --dims {dims} "
+        f"--depth {depth} --rows {rows} --md {os.path.relpath(md_path, ROOT)}",
+        "```",
+        "",
+        "The first stencil dispatch (cold caches after the host scatter) is left out of the "
+        f"average over the other {len(fw)}.",
         "",
         "| quantity | value |",
         "|---|---|",

@@ -1,0 +1,63 @@
+"""What the trained cost model gains over launching without it (GPU).
+
+The committed model (paper_2505_06022_amd/costmodel.json, trained by the
+library's own MLP kernels on samples the autotuner measured) picks a launch
+configuration for held-out shapes it never saw in training.  Each pick is
+timed next to (a) the configuration used without a model (one chunk, T = 1,
+automatic tile rows) and (b) the best of the exhaustive sweep of the same
+shape, all in one measurement call so that they share the device state.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+MODEL = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                     "paper_2505_06022_amd", "costmodel.json")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    if not os.path.exists(MODEL):
+        pytest.skip("no trained cost model committed")
+    torch.cuda.set_device(0)
+    import paper_2505_06022_amd as ccl
+    ccl.lib()
+    yield
+
+
+def held_out_shapes(n=2, max_cells=3.2e7):
+    from paper_2505_06022_amd.learn import HELD_OUT_SEED
+    shapes = synth.cost_model_shapes(200, HELD_OUT_SEED)
+    return [s for s in shapes if s[0] * s[1] <= max_cells][:n]
+
+
+@pytest.mark.parametrize("shape", held_out_shapes())
+def test_learned_pick_gains_over_no_model(shape):
+    from paper_2505_06022_amd import tune
+    cfgs = tune.candidates(shape)
+    keys = [tune.cfg_key(c) for c in cfgs]
+    res = tune.measure(cfgs, reps=3)
+    t = np.array([r["s_per_step"] for r in res])
+    m = tune.CostModel.load(MODEL)
+    try:
+        pick_cfg, _ = m.pick(shape, "time")
+    finally:
+        m.close()
+    pick = keys.index(tune.cfg_key(pick_cfg))
+    default = keys.index((tuple(shape), 1, 1, 0))
+    best = int(np.argmin(t))
+    gain = t[default] / t[pick]
+    ratio = t[pick] / t[best]
+    print(f"{shape}: pick {keys[pick][1:]} best {keys[best][1:]}; pick/best {ratio:.3f}, "
+          f"no-model/pick {gain:.2f}")
+    assert gain >= 1.3, f"the model's pick is only {gain:.2f}x faster than no model"
+    assert ratio <= 1.25, f"the model's pick is {ratio:.3f}x the swept best"
