@@ -316,12 +316,25 @@ ccl_status ccl_autotune_measure(int32_t n, const ccl_tune_config *cfgs, float r2
  * itself when it is positive.  Errors: INVALID, RANGE. */
 ccl_status ccl_wave_plan_rows(const ccl_tune_config *c, int32_t *rows);
 
-/* Cost-model features of each config (host array n x CCL_MLP_IN):
- * log2 of the three extents (0 for the third in 2D), is-3D, log2 cells,
- * log2 K, log2 tile rows (as ccl_wave_plan_rows gives them), T, 1/T,
- * log2(1 + halo bytes per step), modelled
- * HBM bytes per cell-step (12 for T = 1, 16/T otherwise), log2 waves per
- * launch.  Errors: INVALID. */
+/* Waves of the stencil kernel for (dims, T) that the current device holds
+ * at once, as the occupancy API reports them (the figure the row planner
+ * uses; a fixed guess where no device answers).  Errors: INVALID. */
+ccl_status ccl_wave_slots(int32_t dims, int32_t T, int64_t *slots);
+
+/* Cost-model features of each config (host array n x CCL_MLP_IN), from the
+ * launch geometry the kernels would use (rows as ccl_wave_plan_rows gives
+ * them, chunks as ccl_split_range cuts dim 0):
+ *   0-2  log2 of the three extents (0 for the third in 2D)
+ *   3    1 for 3D, 0 for 2D
+ *   4    log2 of the redundancy: cells the waves stream per launch (tile
+ *        overlap included) / cells of the domain
+ *   5    log2 K          6  log2 tile rows          7  T
+ *   8    last-round fill: waves / (ceil(waves / slots) * slots), slots from
+ *        ccl_wave_slots
+ *   9    log2(1 + halo bytes per step)
+ *   10   modelled HBM bytes per cell-step (12 for T = 1, 16/T otherwise)
+ *   11   log2 waves per launch
+ * Errors: INVALID, RANGE (more chunks than rows). */
 ccl_status ccl_costmodel_features(int32_t n, const ccl_tune_config *cfgs, float *x_host);
 
 /* ---- Launch-config cost model ------------------------------------------

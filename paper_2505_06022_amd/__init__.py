@@ -142,6 +142,7 @@ _SIGS = {
                                               ctypes.c_int32, ctypes.c_void_p,
                                               _P(ccl_tune_sample)]),
     "ccl_wave_plan_rows": (ctypes.c_int32, [_P(ccl_tune_config), _P(ctypes.c_int32)]),
+    "ccl_wave_slots": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_int64)]),
     "ccl_costmodel_features": (ctypes.c_int32, [ctypes.c_int32, _P(ccl_tune_config),
                                                 _P(ctypes.c_float)]),
     "ccl_mlp_create": (ctypes.c_int32, [_P(ctypes.c_float), _P(ctypes.c_void_p)]),
@@ -385,6 +386,12 @@ def ccl_wave_plan_rows(cfg) -> int:
     r = ctypes.c_int32(0)
     _check("ccl_wave_plan_rows", lib().ccl_wave_plan_rows(ctypes.byref(cfg), ctypes.byref(r)))
     return r.value
+
+
+def ccl_wave_slots(dims: int, T: int) -> int:
+    v = ctypes.c_int64(0)
+    _check("ccl_wave_slots", lib().ccl_wave_slots(dims, T, ctypes.byref(v)))
+    return v.value
 
 
 def ccl_costmodel_features(cfgs):

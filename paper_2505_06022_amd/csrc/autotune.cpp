@@ -207,6 +207,60 @@ extern "C" ccl_status ccl_wave_plan_rows(const ccl_tune_config *c, int32_t *rows
   return CCL_OK;
 }
 
+extern "C" ccl_status ccl_wave_slots(int32_t dims, int32_t T, int64_t *slots) {
+  clear_error();
+  if (!slots) return fail(CCL_E_INVALID, "NULL argument");
+  if ((dims != 2 && dims != 3) || T < 1 || T > CCL_MAX_DEPTH)
+    return fail(CCL_E_INVALID, "dims=%d, T=%d", dims, T);
+  *slots = dims == 2 ? wave2d_slots(T) : wave3d_slots(T);
+  return CCL_OK;
+}
+
+namespace ccl {
+namespace {
+
+// Launch geometry of one config as the kernels tile it: waves per launch
+// and the cells the waves stream (overlap included) per useful cell.
+struct Geometry {
+  double waves = 0.0;
+  double redundancy = 1.0;
+};
+
+Geometry geometry_of(const ccl_tune_config &c, int32_t rows) {
+  const int T = c.temporal_depth, K = c.nchunks;
+  const int64_t n0 = c.shape[0], n1 = c.shape[1], n2 = c.dims == 3 ? c.shape[2] : 1;
+  const int A = 4 * ((T + 3) / 4);
+  double waves = 0.0, streamed = 0.0;
+  for (int k = 0; k < K; ++k) {
+    const int64_t nk = (k + 1) * n0 / K - k * n0 / K;  // the split of ccl_split_range
+    const int64_t segs = (nk + rows - 1) / rows;
+    if (c.dims == 2) {
+      const int64_t strips = (n1 + (256 - 2 * A) - 1) / (256 - 2 * A);
+      waves += static_cast<double>(segs * strips);
+      streamed += static_cast<double>(segs) * (rows + 2.0 * T) * strips * 256.0;
+    } else if (T == 1) {
+      const int64_t strips = (n2 + 255) / 256, rowblk = (n1 + 3) / 4;
+      waves += static_cast<double>(segs * strips * rowblk);
+      // each wave also loads the two rows around its four
+      streamed += static_cast<double>(segs) * (rows + 2.0) * strips * 256.0 * rowblk * 6.0;
+    } else {
+      int32_t oc = 1, orows = 1, wpb = 1;
+      wave3d_tb_geometry(T, &oc, &orows, &wpb);
+      const int64_t strips = (n2 + oc - 1) / oc, rowblk = (n1 + orows - 1) / orows;
+      waves += static_cast<double>(segs * strips * rowblk * wpb);
+      streamed += static_cast<double>(segs) * (rows + 2.0 * T) * strips * (oc + 2.0 * A) *
+                  rowblk * (orows + 2.0 * T);
+    }
+  }
+  Geometry g;
+  g.waves = waves;
+  g.redundancy = streamed / (static_cast<double>(n0) * n1 * n2);
+  return g;
+}
+
+}  // namespace
+}  // namespace ccl
+
 extern "C" ccl_status ccl_costmodel_features(int32_t n, const ccl_tune_config *cfgs,
                                              float *x_host) {
   clear_error();
@@ -218,45 +272,37 @@ extern "C" ccl_status ccl_costmodel_features(int32_t n, const ccl_tune_config *c
       return fail(CCL_E_INVALID, "config %d is malformed", i);
     for (int d = 0; d < c.dims; ++d)
       if (c.shape[d] < 1) return fail(CCL_E_INVALID, "config %d has an empty extent", i);
+    if (c.nchunks > c.shape[0]) return fail(CCL_E_RANGE, "config %d: more chunks than rows", i);
     const double n0 = static_cast<double>(c.shape[0]);
     const double n1 = static_cast<double>(c.shape[1]);
     const double n2 = c.dims == 3 ? static_cast<double>(c.shape[2]) : 1.0;
-    const double cells = n0 * n1 * n2;
     const double T = c.temporal_depth;
     const double K = c.nchunks;
-    int32_t planned = 0;
-    if (c.tile_rows == 0 && ccl_wave_plan_rows(&c, &planned) != CCL_OK)
+    int32_t rows = 0;
+    if (ccl_wave_plan_rows(&c, &rows) != CCL_OK)
       return fail(CCL_E_INVALID, "config %d: %s", i, ccl_last_error());
-    const double rows = c.tile_rows > 0 ? c.tile_rows : planned;
+    const Geometry g = geometry_of(c, rows);
+    const double slots = static_cast<double>(
+        c.dims == 2 ? wave2d_slots(c.temporal_depth) : wave3d_slots(c.temporal_depth));
+    const double rounds = std::ceil(g.waves / slots);
     // halo bytes per step: 2 directions x (K-1) boundaries x (2T-1) rows/planes
     // of u^n and u^{n-1}, read and written, per T steps
     const double row_bytes = 4.0 * n1 * n2;
     const double halo = 2.0 * (K - 1.0) * (2.0 * T - 1.0) * row_bytes * 2.0 / T;
     const double model_bytes = c.temporal_depth == 1 ? 12.0 : 16.0 / T;
-    double waves;
-    if (c.dims == 2) {
-      const double strip = 256.0 - 2.0 * 4.0 * std::ceil(T / 4.0);
-      waves = K * std::ceil(n0 / K / rows) * std::ceil(n1 / strip);
-    } else if (c.temporal_depth == 1) {
-      waves = K * std::ceil(n0 / K / rows) * std::ceil(n2 / 256.0) * std::ceil(n1 / 4.0);
-    } else {
-      int32_t oc = 1, orows = 1, wpb = 1;
-      wave3d_tb_geometry(c.temporal_depth, &oc, &orows, &wpb);
-      waves = wpb * K * std::ceil(n0 / K / rows) * std::ceil(n2 / oc) * std::ceil(n1 / orows);
-    }
     float *x = x_host + static_cast<size_t>(i) * CCL_MLP_IN;
     x[0] = static_cast<float>(std::log2(n0));
     x[1] = static_cast<float>(std::log2(n1));
     x[2] = static_cast<float>(c.dims == 3 ? std::log2(n2) : 0.0);
     x[3] = c.dims == 3 ? 1.0f : 0.0f;
-    x[4] = static_cast<float>(std::log2(cells));
+    x[4] = static_cast<float>(std::log2(g.redundancy));
     x[5] = static_cast<float>(std::log2(K));
-    x[6] = static_cast<float>(std::log2(rows));
+    x[6] = static_cast<float>(std::log2(static_cast<double>(rows)));
     x[7] = static_cast<float>(T);
-    x[8] = static_cast<float>(1.0 / T);
+    x[8] = static_cast<float>(g.waves / (rounds * slots));
     x[9] = static_cast<float>(std::log2(1.0 + halo));
     x[10] = static_cast<float>(model_bytes);
-    x[11] = static_cast<float>(std::log2(std::max(1.0, waves)));
+    x[11] = static_cast<float>(std::log2(std::max(1.0, g.waves)));
   }
   return CCL_OK;
 }

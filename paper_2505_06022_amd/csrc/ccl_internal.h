@@ -132,6 +132,11 @@ int32_t plan_tile_rows(int64_t slots, int32_t halo, int32_t min_rows, int32_t ma
 }
 
 int32_t wave2d_plan_rows(int64_t ny, int64_t nx, int32_t K, int32_t T);
+// Waves of the depth-T kernel the device holds at once (occupancy API; a
+// fixed guess where no device answers).
+int64_t wave2d_slots(int32_t T);
+int64_t wave3d_slots(int32_t T);
+int64_t wave3d_tb_wave_slots(int32_t T);
 int32_t wave3d_plan_planes(int64_t nz, int64_t ny, int64_t nx, int32_t K, int32_t T);
 int32_t wave3d_tb_plan_planes(int64_t nz, int64_t ny, int64_t nx, int32_t K, int32_t T);
 // Output columns and rows of one block's patch, and waves per block, of the

@@ -96,6 +96,8 @@ static int64_t wave_slots(int T, bool in_place) {
   return c;
 }
 
+int64_t wave2d_slots(int32_t T) { return wave_slots(T, T == 1); }
+
 // The rows the launcher would pick for a domain split into K row chunks
 // (buffers starting at the domain's first column).
 int32_t wave2d_plan_rows(int64_t ny, int64_t nx, int32_t K, int32_t T) {

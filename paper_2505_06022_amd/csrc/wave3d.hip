@@ -259,6 +259,8 @@ int64_t wave_slots3d() {
 
 }  // namespace
 
+int64_t wave3d_slots(int32_t T) { return T > 1 ? wave3d_tb_wave_slots(T) : wave_slots3d(); }
+
 // The planes per tile the launcher would pick for a domain split into K
 // plane chunks, at temporal depth T.
 int32_t wave3d_plan_planes(int64_t nz, int64_t ny, int64_t nx, int32_t K, int32_t T) {

@@ -414,6 +414,8 @@ ccl_status launch_t(const W3TArgs &a, int blocks, hipStream_t s) {
 
 }  // namespace
 
+int64_t wave3d_tb_wave_slots(int32_t T) { return block_slots(T) * (kThreads / 64); }
+
 void wave3d_tb_geometry(int32_t T, int32_t *out_cols, int32_t *out_rows, int32_t *waves) {
   *out_cols = tb_out_cols(T);
   *out_rows = tb_out_rows(T);

@@ -175,6 +175,27 @@ class CostModel:
         i = int(best.item())
         return cfgs[i], i
 
+    def rank(self, shape, objective="time", nchunks=None):
+        """Indices into candidates(shape) (restricted to `nchunks` when
+        given) ordered by the model's predicted objective, best first."""
+        cfgs = candidates(shape)
+        idx = [i for i, c in enumerate(cfgs) if nchunks is None or c.nchunks == nchunks]
+        y = self.predict(ccl_costmodel_features([cfgs[i] for i in idx]))
+        w = OBJECTIVES[objective]
+        score = w[0] * y[:, 0] + w[1] * y[:, 1]
+        return [idx[j] for j in np.argsort(score, kind="stable")]
+
+    def pick_verified(self, shape, objective="time", k=3, r2=0.25, nchunks=None):
+        """The model's k best candidates measured by the autotuner; returns
+        the fastest (or least-energy) of them and its measurement."""
+        cfgs = candidates(shape)
+        top = [cfgs[i] for i in self.rank(shape, objective, nchunks)[:k]]
+        res = measure(top, r2, energy_window_s=1.0 if objective != "time" else 0.0)
+        key = "s_per_step" if objective == "time" else "j_per_step"
+        j = int(np.argmin([r[key] if objective != "edp" else r["s_per_step"] * r["j_per_step"]
+                           for r in res]))
+        return top[j], res[j]
+
     def to_json(self):
         return dict(params=self.params.tolist(), x_mean=self.xs.mean.tolist(),
                     x_std=self.xs.std.tolist(), y_mean=self.ys.mean.tolist(),

@@ -244,21 +244,46 @@ def test_batch_create_validation_no_launch():
 
 
 def test_costmodel_features_host():
-    """Features of two configs written out by hand."""
+    """Features of three configs written out by hand from the kernels'
+    tiling (2D strips of 256 columns, 3D one-step tiles of 256 x 4, 3D
+    blocked patches of 64 x 32)."""
     import math
     import numpy as np
     c2 = ccl.make_tune_config((1024, 4096), 4, 8, 64)
     c3 = ccl.make_tune_config((96, 768, 768), 8, 1, 32)
-    x = ccl.ccl_costmodel_features([c2, c3])
+    c3b = ccl.make_tune_config((100, 200, 300), 3, 5, 16)
+    x = ccl.ccl_costmodel_features([c2, c3, c3b])
+
+    def fill(waves, slots):
+        return waves / (math.ceil(waves / slots) * slots)
+
+    # 2D, T = 8: strips of 256 - 2*8 = 240 output columns, segments of 64 rows
     halo2 = 2 * 3 * 15 * (4 * 4096) * 2 / 8
-    waves2 = 4 * math.ceil(1024 / 4 / 64) * math.ceil(4096 / 240)
-    want2 = [10, 12, 0, 0, 22, 2, 6, 8, 1 / 8, math.log2(1 + halo2), 2.0, math.log2(waves2)]
+    waves2 = 4 * math.ceil(256 / 64) * math.ceil(4096 / 240)
+    red2 = 4 * math.ceil(256 / 64) * (64 + 16) * math.ceil(4096 / 240) * 256 / (1024 * 4096)
+    s2 = ccl.ccl_wave_slots(2, 8)
+    want2 = [10, 12, 0, 0, math.log2(red2), 2, 6, 8, fill(waves2, s2), math.log2(1 + halo2), 2.0,
+             math.log2(waves2)]
+    # 3D, T = 1: 96 planes in 8 chunks of 12, tiles of 32 planes, 256 x 4 cells
     halo3 = 2 * 7 * 1 * (4 * 768 * 768) * 2 / 1
-    waves3 = 8 * math.ceil(96 / 8 / 32) * math.ceil(768 / 256) * math.ceil(768 / 4)
-    want3 = [math.log2(96), math.log2(768), math.log2(768), 1, math.log2(96 * 768 * 768), 3, 5, 1,
-             1, math.log2(1 + halo3), 12.0, math.log2(waves3)]
+    waves3 = 8 * math.ceil(12 / 32) * math.ceil(768 / 256) * math.ceil(768 / 4)
+    red3 = 8 * (32 + 2) * 3 * 256 * 192 * 6 / (96 * 768 * 768)
+    s3 = ccl.ccl_wave_slots(3, 1)
+    want3 = [math.log2(96), math.log2(768), math.log2(768), 1, math.log2(red3), 3, 5, 1,
+             fill(waves3, s3), math.log2(1 + halo3), 12.0, math.log2(waves3)]
+    # 3D, T = 5: patches of 64 x 32 cells writing 48 x 22; chunks of 33, 33, 34 planes
+    segs = [math.ceil(33 / 16), math.ceil(33 / 16), math.ceil(34 / 16)]
+    tiles = [s * math.ceil(300 / 48) * math.ceil(200 / 22) for s in segs]
+    waves3b = 4 * sum(tiles)
+    red3b = sum(t * (16 + 10) * 64 * 32 for t in tiles) / (100 * 200 * 300)
+    halo3b = 2 * 2 * 9 * (4 * 200 * 300) * 2 / 5
+    s3b = ccl.ccl_wave_slots(3, 5)
+    want3b = [math.log2(100), math.log2(200), math.log2(300), 1, math.log2(red3b),
+              math.log2(3), 4, 5, fill(waves3b, s3b), math.log2(1 + halo3b), 16 / 5,
+              math.log2(waves3b)]
     assert np.allclose(x[0], want2, rtol=1e-6)
     assert np.allclose(x[1], want3, rtol=1e-6)
+    assert np.allclose(x[2], want3b, rtol=1e-6)
     L = ccl.lib()
     bad = ccl.make_tune_config((16, 16), 0, 1, 16)
     arr = (ccl.ccl_tune_config * 1)(bad)
