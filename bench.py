@@ -123,23 +123,9 @@ def pick_config(w, args):
     """(T, rows, how) for the headline share."""
     if args.depth and args.tile_rows:
         return args.depth, args.tile_rows, "given"
-    import numpy as np
-
-    import paper_2505_06022_amd as ccl
     from paper_2505_06022_amd import tune
-    shape = w["shape"]
-    if os.path.exists(MODEL_PATH) and not args.sweep:
-        m = tune.CostModel.load(MODEL_PATH)
-        cands = [c for c in tune.candidates(shape) if c.nchunks == w["chunks"]]
-        X = ccl.ccl_costmodel_features(cands)
-        y = m.predict(X)
-        i = int(np.argmin(y[:, 0]))
-        m.close()
-        return cands[i].temporal_depth, cands[i].tile_rows, "cost model"
-    cands = [c for c in tune.candidates(shape) if c.nchunks == w["chunks"]]
-    res = tune.measure(cands, w["r2"], reps=3, steps=48)
-    i = int(np.argmin([r["s_per_step"] for r in res]))
-    return cands[i].temporal_depth, cands[i].tile_rows, "autotuner sweep"
+    return tune.launch_config(w["shape"], w["chunks"], w["r2"],
+                              model_path=None if args.sweep else MODEL_PATH)
 
 
 def time_runs(cw, steps, runs):

@@ -264,3 +264,23 @@ def sample_space(n_shapes: int, seed: int, per_shape: int, rng_seed: int, n_shap
         pick = rs.choice(len(cands), size=min(per_shape, len(cands)), replace=False)
         cfgs.extend(cands[i] for i in sorted(pick))
     return shapes, cfgs
+
+
+MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "costmodel.json")
+
+
+def launch_config(shape, nchunks, r2=0.25, model_path=MODEL_PATH):
+    """(T, tile rows, how) for a shape split into `nchunks` chunks: the
+    trained cost model's pick among the candidates with that many chunks,
+    or, without a model, the fastest of a quick autotuner sweep of them."""
+    cands = [c for c in candidates(shape) if c.nchunks == nchunks]
+    if model_path and os.path.exists(model_path):
+        m = CostModel.load(model_path)
+        try:
+            c, _ = m.pick(shape, "time", nchunks=nchunks)
+        finally:
+            m.close()
+        return c.temporal_depth, c.tile_rows, "cost model"
+    res = measure(cands, r2, reps=3, steps=48)
+    i = int(np.argmin([r["s_per_step"] for r in res]))
+    return cands[i].temporal_depth, cands[i].tile_rows, "autotuner sweep"

@@ -215,12 +215,16 @@ def cone_sample(u_prev, u_cur, r2, steps, point):
 
 def test_headline_share_full_size():
     """8192 x 8192 share of 32768 x 8192 at offset 8192, 1000 steps, 4 chunks,
-    in the launch configuration the benchmark times (T = 4): bitwise equal to
-    the unchunked T = 1 run everywhere, and to the oracle at sampled cells
-    (corners, chunk boundaries, centre)."""
+    in the launch configuration the benchmark times (the committed cost
+    model's pick, as bench.py takes it): bitwise equal to the unchunked T = 1
+    run everywhere, and to the oracle at sampled cells (corners, chunk
+    boundaries, centre)."""
+    from paper_2505_06022_amd import tune
     w = synth.WORKLOADS["wave2d_8192_share_k4"]
+    T, rows, how = tune.launch_config(w["shape"], w["chunks"], w["r2"])
+    print(f"headline launch configuration: T={T}, tile rows={rows} ({how})")
     u0 = synth.gaussian_field(w["shape"], w["sigma"], w["seed"])
-    _, chunked = gpu_run(u0, u0, w["r2"], w["steps"], w["chunks"], 4,
+    _, chunked = gpu_run(u0, u0, w["r2"], w["steps"], w["chunks"], T, tile_rows=rows,
                          offset=w["share_offset"], buffer_range=w["global_shape"])
     _, plain = gpu_run(u0, u0, w["r2"], w["steps"], 1, 1, offset=w["share_offset"],
                        buffer_range=w["global_shape"])
@@ -279,7 +283,10 @@ def test_wave3d_tile_planes():
 
 def test_wave3d_768_full_size():
     """768^3, r2 = 0.1, 8 z-slab chunks: 200 steps bitwise equal to the
-    unchunked run, and 8 steps bitwise equal to the oracle everywhere."""
+    unchunked run, also in the launch configuration the benchmark times for
+    it (the cost model's pick), and 8 steps bitwise equal to the oracle
+    everywhere."""
+    from paper_2505_06022_amd import tune
     w = synth.WORKLOADS["wave3d_768_k8"]
     u0 = synth.gaussian_field(w["shape"], w["sigma"], w["seed"])
     _, ref = oracle.wave(u0.copy(), u0, w["r2"], 8, threads=oracle.max_threads())
@@ -290,8 +297,14 @@ def test_wave3d_768_full_size():
     _, b = gpu_run(u0, u0, w["r2"], w["steps"], 1, 1, fill=0.0)
     assert np.all(np.isfinite(a)) and np.array_equal(a, b)
     del b
-    _, c = gpu_run(u0, u0, w["r2"], w["steps"], w["chunks"], 4, fill=0.0)
-    assert np.array_equal(a, c), "768^3: T=4 differs from T=1"
+    T, planes, how = tune.launch_config(w["shape"], w["chunks"], w["r2"])
+    print(f"3D launch configuration: T={T}, tile planes={planes} ({how})")
+    _, c = gpu_run(u0, u0, w["r2"], w["steps"], w["chunks"], T, tile_rows=planes, fill=0.0)
+    assert np.array_equal(a, c), f"768^3: T={T}, planes={planes} differs from T=1"
+    if T != 4:
+        del c
+        _, c = gpu_run(u0, u0, w["r2"], w["steps"], w["chunks"], 4, fill=0.0)
+        assert np.array_equal(a, c), "768^3: T=4 differs from T=1"
 
 
 # ------------------------------------------------------------ measurement --
