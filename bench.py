@@ -97,26 +97,27 @@ def saxpy_calibration(n: int = 1 << 28, reps: int = 10):
 
 def average_power(run_once, min_span=2.0, limit=30.0):
     """Mean device power (W) over back-to-back runs, between two updates of
-    the device energy counter at least `min_span` s apart (the counter
-    advances in coarse steps, so the window is aligned to its updates)."""
+    the device energy counter at least `min_span` s apart by the counter's
+    own timestamps (the counter advances in coarse steps, so the window is
+    aligned to its updates; an update is a change of the energy value)."""
     import torch
 
     import paper_2505_06022_amd as ccl
-    _, ts0 = ccl.ccl_energy_read(0, None)
-    first = last = None
+    prev, _ = ccl.ccl_energy_read(0, None)
+    first = None
     t0 = time.perf_counter()
-    while last is None:
+    while True:
         run_once()
         torch.cuda.synchronize()
         e, ts = ccl.ccl_energy_read(0, None)
-        if first is None:
-            if ts != ts0:
-                first = (e, ts)
-        elif (ts - first[1]) * 1e-9 >= min_span:
-            last = (e, ts)
+        if e != prev:
+            if first is None or e < first[0] or ts <= first[1]:
+                first = (e, ts)  # first update seen (or the counter went back)
+            elif (ts - first[1]) * 1e-9 >= min_span:
+                return (e - first[0]) / ((ts - first[1]) * 1e-9)
+        prev = e
         if time.perf_counter() - t0 > limit:
             raise RuntimeError("energy counter did not advance")
-    return (last[0] - first[0]) / ((last[1] - first[1]) * 1e-9)
 
 
 def pick_config(w, args):

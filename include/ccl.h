@@ -339,8 +339,9 @@ ccl_status ccl_costmodel_features(int32_t n, const ccl_tune_config *cfgs, float 
 
 /* ---- Launch-config cost model ------------------------------------------
  * A 12-64-64-2 float32 MLP (ReLU hidden layers) that maps the features of a
- * launch config to predicted [log time, log energy] per cell-step
- * (standardised by the caller).  Trained on the GPU by the library's own
+ * launch config to two predicted targets (the library's tuner uses [log time
+ * per cell-step, log device power], standardised by the caller; the kernels
+ * do not depend on what the targets mean).  Trained on the GPU by the library's own
  * forward/backward kernels with L = 1/(2n) sum w |y - t|^2 and Adam; gradients
  * are summed in a fixed order, so training is deterministic.  Parameters are
  * packed W1 (64x12), b1 (64), W2 (64x64), b2 (64), W3 (2x64), b3 (2),

@@ -145,32 +145,37 @@ extern "C" ccl_status ccl_autotune_measure(int32_t n, const ccl_tune_config *cfg
     if (want_energy) {
       // The device counter advances in coarse steps (about once a second on
       // the MI355X boxes): run back to back and take the energy between two
-      // counter updates at least energy_window_s apart, by the counter's own
-      // timestamps; J/step = mean power x the timed seconds per step.
-      double j = 0.0, ja = 0.0;
-      uint64_t ts = 0, ts0 = 0, tsa = 0;
+      // counter updates (changes of its value) at least energy_window_s
+      // apart by the counter's own timestamps; J/step = mean power x the
+      // timed seconds per step.  A counter that goes back restarts the window.
+      double j = 0.0, prev = 0.0, ja = 0.0;
+      uint64_t ts = 0, tsa = 0;
       bool have_a = false, done = false;
       int runs = 0;
       const auto t0 = std::chrono::steady_clock::now();
-      if (ccl_energy_read(device, s, &j, &ts0) == CCL_OK) {
+      if (ccl_energy_read(device, s, &prev, &ts) == CCL_OK) {
         while (!done) {
           st = run();
           if (st != CCL_OK) break;
           ++runs;
           if (ccl_energy_read(device, s, &j, &ts) != CCL_OK) break;
-          if (!have_a) {
-            if (ts != ts0) {
+          if (j != prev) {
+            if (!have_a || j < ja || ts <= tsa) {
               have_a = true;
               ja = j;
               tsa = ts;
+              runs = 0;
+            } else if (static_cast<double>(ts - tsa) * 1e-9 >= energy_window_s) {
+              const double watts = (j - ja) / (static_cast<double>(ts - tsa) * 1e-9);
+              if (watts > 0.0 && std::isfinite(watts)) {
+                o.joules_per_step = watts * o.seconds_per_step;
+                o.window_seconds = static_cast<double>(ts - tsa) * 1e-9;
+                o.runs_in_window = runs;
+              }
+              done = true;
             }
-          } else if (static_cast<double>(ts - tsa) * 1e-9 >= energy_window_s) {
-            const double watts = (j - ja) / (static_cast<double>(ts - tsa) * 1e-9);
-            o.joules_per_step = watts * o.seconds_per_step;
-            o.window_seconds = static_cast<double>(ts - tsa) * 1e-9;
-            o.runs_in_window = runs;
-            done = true;
           }
+          prev = j;
           const double el =
               std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
           if (el > 10.0 * energy_window_s + 5.0) break;  // counter not advancing

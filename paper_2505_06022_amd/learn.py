@@ -93,12 +93,13 @@ def energy(out_dir, count=120, window_s=1.0, budget_s=600.0):
     with open(path) as f:
         doc = json.load(f)
     samples = doc["samples"]
+    # a seeded permutation: a larger count extends the same subset
     rs = np.random.default_rng(SAMPLE_SEED + 1)
-    pick = sorted(rs.choice(len(samples), size=min(count, len(samples)), replace=False))
+    pick = rs.permutation(len(samples))[:count]
     t0 = time.perf_counter()
     done = 0
     for n, j in enumerate(pick):
-        s = samples[j]
+        s = samples[int(j)]
         if s.get("j_per_cell_step") is not None and np.isfinite(s["j_per_cell_step"]):
             done += 1
             continue
@@ -135,7 +136,7 @@ def train(data_path, model_path, epochs=4000, lr=3e-3, seed=0):
     m.meta["train_rmse_log"] = rmse.tolist()
     m.save(model_path)
     _log(f"trained on {len(X)} samples in {m.meta['train_seconds']:.2f} s, "
-         f"final loss {m.meta['final_loss']:.4g}, rmse(log t, log E) = {rmse}")
+         f"final loss {m.meta['final_loss']:.4g}, rmse(log t, log W) = {rmse}")
     return m
 
 
@@ -205,11 +206,18 @@ def energy_check(model_path, out_dir, n_shapes=200, count=4, window_s=1.0, top=3
         pick = keys.index(tune.cfg_key(pick_cfg))
         idx = sorted(set(int(j) for j in order) | {pick})
         meas = tune.measure([cfgs[j] for j in idx], energy_window_s=window_s)
-        e = {j: m["j_per_step"] for j, m in zip(idx, meas)}
+        e = {j: m["j_per_step"] for j, m in zip(idx, meas)
+             if m["j_per_step"] is not None and np.isfinite(m["j_per_step"])
+             and m["j_per_step"] > 0}
+        if pick not in e:
+            _log(f"  energy {sh}: no valid energy window for the pick; shape skipped")
+            continue
         best = min(e, key=e.get)
         out.append(dict(shape=list(sh), pick=keys[pick], best=keys[best], e_pick=e[pick],
-                        e_best=e[best], ratio=e[pick] / e[best]))
-        _log(f"  energy {sh}: pick/best {e[pick] / e[best]:.3f}")
+                        e_best=e[best], ratio=e[pick] / e[best],
+                        time_pick_over_best=res[pick]["s_per_step"] / res[order[0]]["s_per_step"]))
+        _log(f"  energy {sh}: pick/best {e[pick] / e[best]:.3f} ({keys[pick][1:]} vs "
+             f"{keys[best][1:]})")
     with open(os.path.join(out_dir, "energy_check.json"), "w") as f:
         json.dump(out, f)
     model.close()

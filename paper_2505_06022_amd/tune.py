@@ -2,12 +2,12 @@
 
 * ``candidates(shape)`` — the discrete config space of one shape: chunk
   counts K in {1, 2, 4, 8, 16} (K <= rows), rows per tile in
-  {auto, 16, 32, 64, 128}, temporal depth T in 1..8 (2D) or 1 (3D).
+  {auto, 16, 32, 64, 128}, temporal depth T in 1..8 (2D and 3D).
 * ``measure(cfgs)`` — time (and device energy) per step of each config,
   measured by the library's autotuner on the GPU (ccl_autotune_measure).
 * ``CostModel`` — the 12-64-64-2 MLP, trained on the GPU by the library's
   kernels (ccl_mlp_*) on standardised features (ccl_costmodel_features) and
-  standardised targets [log s/cell-step, log J/cell-step]; ``pick`` scores
+  standardised targets [log s/cell-step, log W (device power)]; ``pick`` scores
   every candidate of a shape on the GPU (ccl_mlp_pick) and returns the best
   by time, energy or energy-delay product.
 * ``sweep`` — the exhaustive measurement of every candidate: the fallback
@@ -33,7 +33,9 @@ K_SET = (1, 2, 4, 8, 16)
 ROWS_SET = (0, 16, 32, 64, 128)  # 0: the library's occupancy-aware choice
 T_SET = tuple(range(1, 9))
 
-OBJECTIVES = {"time": (1.0, 0.0), "energy": (0.0, 1.0), "edp": (1.0, 1.0)}
+# weights on the model's outputs [log s/cell-step, log W]: log energy =
+# log time + log power, log (energy x delay) = 2 log time + log power
+OBJECTIVES = {"time": (1.0, 0.0), "energy": (1.0, 1.0), "edp": (2.0, 1.0)}
 
 
 def candidates(shape):
@@ -80,15 +82,19 @@ def sweep(shape, r2=0.25, reps=3, energy_window_s=0.0):
 
 
 def targets_of(samples):
-    """Targets [log s/cell-step, log J/cell-step] and weights (energy weight 0
-    where no energy was measured; its target slot then holds 0)."""
+    """Targets [log s/cell-step, log W] and weights.  The second output is
+    the mean device power while the config runs (J/step / s/step); energy
+    per cell-step is then the sum of the two logs.  Power varies far less
+    across configs than time does, so the few samples with an energy label
+    constrain it well.  Weight 0 where no energy was measured (the target
+    slot then holds 0)."""
     t = np.zeros((len(samples), 2))
     w = np.ones((len(samples), 2))
     for i, s in enumerate(samples):
         t[i, 0] = math.log(s["s_per_cell_step"])
         e = s.get("j_per_cell_step")
         if e is not None and np.isfinite(e) and e > 0:
-            t[i, 1] = math.log(e)
+            t[i, 1] = math.log(e / s["s_per_cell_step"])
         else:
             w[i, 1] = 0.0
     return t, w
@@ -147,7 +153,7 @@ class CostModel:
         return m
 
     def predict(self, X):
-        """Predicted [log s/cell-step, log J/cell-step] (host arrays)."""
+        """Predicted [log s/cell-step, log W] (host arrays)."""
         import torch
 
         from . import ccl_mlp_forward

@@ -40,7 +40,8 @@ def test_targets_mask_missing_energy():
          dict(s_per_cell_step=2e-12, j_per_cell_step=3e-10)]
     t, w = tune.targets_of(s)
     assert w[0, 1] == 0 and w[1, 1] == 1 and np.all(w[:, 0] == 1)
-    assert np.isclose(t[1, 1], np.log(3e-10)) and np.isclose(t[0, 0], np.log(1e-12))
+    # second target: log power = log(J per cell-step / s per cell-step)
+    assert np.isclose(t[1, 1], np.log(3e-10 / 2e-12)) and np.isclose(t[0, 0], np.log(1e-12))
 
 
 def test_steps_for():
