@@ -175,7 +175,8 @@ def evaluate(model_path, out_dir, n_shapes=200, start=0, count=None, budget_s=1e
                          t_untrained=t[upick], ratio=t[pick] / t[best],
                          ratio_default=t[default] / t[best],
                          ratio_untrained=t[upick] / t[best],
-                         **{f"ratio_top{k}": v / t[best] for k, v in topk.items()}))
+                         **{f"ratio_top{k}": v / t[best] for k, v in topk.items()},
+                         t_all=[float(v) for v in t]))
         _log(f"  shape {start + i} {sh}: pick/best {t[pick] / t[best]:.3f}, "
              f"default/best {t[default] / t[best]:.2f} ({time.perf_counter() - t0:.0f} s)")
         with open(path, "w") as f:
