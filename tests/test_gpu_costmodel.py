@@ -179,3 +179,22 @@ def test_autotune_measure():
     bad = [ccl.make_tune_config((512, 1024), 1, 9, 32)]
     with pytest.raises(ccl.CclError):
         ccl.ccl_autotune_measure(bad, 0.25, 24)
+
+
+def test_wave_slots_and_features_on_device():
+    """The occupancy the planner and the features use: positive, a whole
+    number of waves per CU, non-increasing with T for the 2D kernel (its
+    register ring grows with T); features finite, fill in (0, 1]."""
+    import paper_2505_06022_amd as ccl
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    s2 = [ccl.ccl_wave_slots(2, T) for T in range(1, 9)]
+    s3 = [ccl.ccl_wave_slots(3, T) for T in range(1, 9)]
+    for s in s2 + s3:
+        assert s > 0 and s % cus == 0
+    assert all(a >= b for a, b in zip(s2[1:], s2[2:]))
+    cfgs = [ccl.make_tune_config((8192, 8192), 4, T, 0) for T in range(1, 9)]
+    cfgs += [ccl.make_tune_config((768, 768, 768), 8, T, 0) for T in range(1, 9)]
+    x = ccl.ccl_costmodel_features(cfgs)
+    assert np.all(np.isfinite(x))
+    assert np.all(x[:, 8] > 0) and np.all(x[:, 8] <= 1)
+    assert np.all(x[:, 4] > 0)  # tiles always stream more cells than they write
