@@ -31,6 +31,11 @@ namespace w2 {
 // body's copy u finds every level's newest row in ring slot u and nothing
 // is moved between iterations.
 constexpr int kPrefetch = 3;
+#ifndef CCL_W2_UNROLL
+#define CCL_W2_UNROLL 3
+#endif
+constexpr int kUnroll = CCL_W2_UNROLL;
+static_assert(kUnroll % kPrefetch == 0, "the unrolled body must be whole ring turns");
 
 // Overlap columns per side and output columns per strip for depth T.
 __host__ __device__ constexpr int overlap(int T) { return 4 * ((T + 3) / 4); }
@@ -112,25 +117,37 @@ __device__ __forceinline__ Cols cols_of(int xl, int x0, int x1) {
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 
-// Loads the lane's group of `row` (zero outside the loadable box).  STREAM
-// marks data read once (u^{n-1}): a nontemporal load keeps it from
-// displacing the u^n rows that neighbouring tiles re-read from cache.
+// The first and the last aligned group of four columns (aligned relative to
+// the buffer's first column bx0) that meet [x0, x1), a non-empty range of
+// the buffer's columns; such groups lie inside the allocated row.
+__device__ __forceinline__ int clamp_group(int xl, int x0, int x1, int bx0) {
+  const int g0 = x0 - ((x0 - bx0) & 3);
+  const int g1 = (x1 - 1) - ((x1 - 1 - bx0) & 3);
+  return min(max(xl, g0), g1);
+}
+
+// Loads a group unconditionally: the caller passes a row and a group that
+// the buffer holds (clamped into the loadable box), so the load needs no
+// branch and stays in flight until its value is used; cells outside the box
+// are zeroed later by mask4, where the value is consumed.  STREAM marks
+// data read once (u^{n-1}): a nontemporal load keeps it from displacing the
+// u^n rows that neighbouring tiles re-read from cache.
 template <bool STREAM>
 __device__ __forceinline__ float4 load4(const float *base, int32_t by0, int32_t bx0,
-                                        int32_t pitch, int row, int xl, int ly0, int ly1,
-                                        const Cols &c) {
-  float4 v = zero4();
-  if (row < ly0 || row >= ly1) return v;  // wave-uniform
-  if (c.any) {
-    const f4v *p = reinterpret_cast<const f4v *>(base + static_cast<int64_t>(row - by0) * pitch +
-                                                 (xl - bx0));
-    const f4v r = STREAM ? __builtin_nontemporal_load(p) : *p;
-    v = make_float4(r.x, r.y, r.z, r.w);
-  }
-  v.x = c.m0 ? v.x : 0.0f;
-  v.y = c.m1 ? v.y : 0.0f;
-  v.z = c.m2 ? v.z : 0.0f;
-  v.w = c.m3 ? v.w : 0.0f;
+                                        int32_t pitch, int row, int xg) {
+  const f4v *p = reinterpret_cast<const f4v *>(base + static_cast<int64_t>(row - by0) * pitch +
+                                               (xg - bx0));
+  const f4v r = STREAM ? __builtin_nontemporal_load(p) : *p;
+  return make_float4(r.x, r.y, r.z, r.w);
+}
+
+// Zero outside the loadable box: the row (wave-uniform) and the lane's
+// columns.
+__device__ __forceinline__ float4 mask4(float4 v, bool row_ok, const Cols &c) {
+  v.x = (row_ok && c.m0) ? v.x : 0.0f;
+  v.y = (row_ok && c.m1) ? v.y : 0.0f;
+  v.z = (row_ok && c.m2) ? v.z : 0.0f;
+  v.w = (row_ok && c.m3) ? v.w : 0.0f;
   return v;
 }
 
@@ -202,26 +219,34 @@ __device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, floa
 
   const int first = y0 - T;
   const int nrows = (y1 - y0) + 2 * T;
+  // loads go to rows and groups clamped into the loadable box (never empty:
+  // it holds the chunk's rows and columns), masks apply on use
+  const int xgc = clamp_group(xl, C.lc_x0, C.lc_x1, C.ic_x0);
+  const int xgp = clamp_group(xl, IN_PLACE ? max(C.lp_x0, vx0) : C.lp_x0,
+                              IN_PLACE ? min(C.lp_x1, vx1) : C.lp_x1, C.ip_x0);
+  auto row_c = [&](int r) { return min(max(r, C.lc_y0), C.lc_y1 - 1); };
+  auto row_p = [&](int r) { return min(max(r, lpy0), lpy1 - 1); };
   float4 q1[kPrefetch], q0[kPrefetch];
 #pragma unroll
   for (int u = 0; u < kPrefetch; ++u) {
-    q1[u] = load4<false>(C.in_cur, C.ic_y0, C.ic_x0, C.ic_pitch, first + u, xl, C.lc_y0, C.lc_y1,
-                         lc);
-    q0[u] = load4<true>(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch, first + u - 1, xl, lpy0, lpy1,
-                        lp);
+    q1[u] = load4<false>(C.in_cur, C.ic_y0, C.ic_x0, C.ic_pitch, row_c(first + u), xgc);
+    q0[u] = load4<true>(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch, row_p(first + u - 1), xgp);
   }
 
-  for (int jb = 0; jb < nrows; jb += kPrefetch) {
+  // kUnroll rows per loop iteration (a multiple of the ring length): the
+  // compiler waits for all outstanding loads once per iteration, at the
+  // loop head, so a longer body exposes that latency less often
+  for (int jb = 0; jb < nrows; jb += kUnroll) {
 #pragma unroll
-    for (int u = 0; u < kPrefetch; ++u) {
+    for (int uu = 0; uu < kUnroll; ++uu) {
+      const int u = uu % kPrefetch;
       const int NEW = u, MID = (u + 2) % 3, OLD = (u + 1) % 3;
-      const int i = first + jb + u;  // row of level 0 arriving now
-      ring[0][NEW] = q1[u];
-      float4 pv = q0[u];
-      q1[u] = load4<false>(C.in_cur, C.ic_y0, C.ic_x0, C.ic_pitch, i + kPrefetch, xl, C.lc_y0,
-                           C.lc_y1, lc);
-      q0[u] = load4<true>(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch, i + kPrefetch - 1, xl, lpy0,
-                          lpy1, lp);
+      const int i = first + jb + uu;  // row of level 0 arriving now
+      ring[0][NEW] = mask4(q1[u], i >= C.lc_y0 && i < C.lc_y1, lc);
+      float4 pv = mask4(q0[u], i - 1 >= lpy0 && i - 1 < lpy1, lp);
+      q1[u] = load4<false>(C.in_cur, C.ic_y0, C.ic_x0, C.ic_pitch, row_c(i + kPrefetch), xgc);
+      q0[u] = load4<true>(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch, row_p(i + kPrefetch - 1),
+                          xgp);
 #pragma unroll
       for (int k = 1; k <= T; ++k) {
         const int r = i - k;  // row of level k computed now
