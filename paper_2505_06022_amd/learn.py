@@ -118,24 +118,64 @@ def energy(out_dir, count=120, window_s=1.0, budget_s=600.0):
     _log(f"energy labels: {done}/{len(pick)} in {time.perf_counter() - t0:.0f} s")
 
 
-def train(data_path, model_path, epochs=4000, lr=3e-3, seed=0):
+def _pick_quality(model, X, Y, groups):
+    """Geometric mean over groups (the sampled configs of one shape) of the
+    measured time of the model's pick among them over the group's measured
+    best: how well the model ranks configs it was not trained on."""
+    pred = model.predict(X)
+    r = []
+    for idx in groups:
+        if len(idx) < 2:
+            continue
+        p = idx[int(np.argmin(pred[idx, 0]))]
+        b = idx[int(np.argmin(Y[idx, 0]))]
+        r.append(Y[p, 0] - Y[b, 0])
+    return float(np.exp(np.mean(r))) if r else float("nan")
+
+
+def train(data_path, model_path, epochs=4000, lr=3e-3, seed=0, seeds=1, val_frac=0.2):
     """Fits the model to the samples; features are recomputed from each
     sample's config, so they always follow the library's current
-    definition (and this device's occupancy)."""
+    definition (and this device's occupancy).  With seeds > 1 the
+    initialisation seed is chosen first: for each of `seeds` seeds a model is
+    fitted without a seeded `val_frac` of the training shapes and judged on
+    how well it ranks those shapes' sampled configs; the chosen seed is then
+    fitted on all samples."""
     from . import ccl_costmodel_features, make_tune_config, tune
     with open(data_path) as f:
         doc = json.load(f)
-    cfgs = [make_tune_config(tuple(k[0]), int(k[1]), int(k[2]), int(k[3]))
-            for k in (s["key"] for s in doc["samples"])]
+    keys = [s["key"] for s in doc["samples"]]
+    cfgs = [make_tune_config(tuple(k[0]), int(k[1]), int(k[2]), int(k[3])) for k in keys]
     X = ccl_costmodel_features(cfgs).astype(np.float64)
     Y, W = tune.targets_of(doc["samples"])
+    selection = None
+    if seeds > 1:
+        by_shape = {}
+        for i, k in enumerate(keys):
+            by_shape.setdefault(tuple(k[0]), []).append(i)
+        shapes = sorted(by_shape)
+        rs = np.random.default_rng(SAMPLE_SEED + 2)
+        val = set(tuple(shapes[j]) for j in rs.permutation(len(shapes))[:int(val_frac * len(shapes))])
+        tr = np.array([i for i, k in enumerate(keys) if tuple(k[0]) not in val])
+        groups = [np.array(by_shape[sh]) for sh in shapes if sh in val]
+        scores = {}
+        for sd in range(seed, seed + seeds):
+            m = tune.CostModel.fit(X[tr], Y[tr], W[tr], epochs=epochs, lr=lr, seed=sd)
+            scores[sd] = _pick_quality(m, X, Y, groups)
+            m.close()
+            _log(f"  seed {sd}: validation pick/best {scores[sd]:.4f}")
+        seed = min(scores, key=scores.get)
+        selection = dict(val_shapes=len(groups), scores={str(k): v for k, v in scores.items()},
+                         chosen=seed)
     m = tune.CostModel.fit(X, Y, W, epochs=epochs, lr=lr, seed=seed)
     pred = m.predict(X)
     rmse = np.array([np.sqrt(np.sum(W[:, k] * (pred[:, k] - Y[:, k]) ** 2) / max(W[:, k].sum(), 1))
                      for k in range(2)])
     m.meta["train_rmse_log"] = rmse.tolist()
+    if selection:
+        m.meta["seed_selection"] = selection
     m.save(model_path)
-    _log(f"trained on {len(X)} samples in {m.meta['train_seconds']:.2f} s, "
+    _log(f"trained on {len(X)} samples in {m.meta['train_seconds']:.2f} s (seed {seed}), "
          f"final loss {m.meta['final_loss']:.4g}, rmse(log t, log W) = {rmse}")
     return m
 
@@ -288,6 +328,7 @@ def main(argv=None):
     t.add_argument("--model", required=True)
     t.add_argument("--epochs", type=int, default=4000)
     t.add_argument("--lr", type=float, default=3e-3)
+    t.add_argument("--seeds", type=int, default=1)
     e = sub.add_parser("evaluate")
     e.add_argument("--model", required=True)
     e.add_argument("--out", required=True)
@@ -311,7 +352,7 @@ def main(argv=None):
     elif a.cmd == "energy":
         energy(a.out, a.count, a.window, a.budget)
     elif a.cmd == "train":
-        train(a.data, a.model, a.epochs, a.lr)
+        train(a.data, a.model, a.epochs, a.lr, seeds=a.seeds)
     elif a.cmd == "evaluate":
         evaluate(a.model, a.out, a.shapes, a.start, a.count, a.budget)
     elif a.cmd == "energy-check":

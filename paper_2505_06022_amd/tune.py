@@ -163,22 +163,32 @@ class CostModel:
         torch.cuda.synchronize()
         return self.ys.invert(yd.cpu().numpy().astype(np.float64))
 
-    def pick(self, shape, objective="time", nchunks=None):
+    def pick(self, shape, objective="time", nchunks=None, shortlist=8):
         """Best candidate of `shape` by the model (only those with `nchunks`
-        chunks when given); returns (config, index into that list)."""
+        chunks when given); returns (config, index into that list).  The
+        argmin runs on the GPU (ccl_mlp_pick).  For energy and EDP the pick
+        is made among the `shortlist` candidates predicted fastest: power
+        varies by a few percent across configs and is labelled for few of
+        them, so a slow config is never chosen for a predicted power saving
+        the model cannot back."""
         import torch
         cfgs = candidates(shape)
         if nchunks is not None:
             cfgs = [c for c in cfgs if c.nchunks == nchunks]
         X = ccl_costmodel_features(cfgs)
+        base = list(range(len(cfgs)))
+        if objective != "time" and shortlist and len(cfgs) > shortlist:
+            t = self.predict(X)[:, 0]
+            base = sorted(np.argsort(t, kind="stable")[:shortlist].tolist())
+            X = X[base]
         w = OBJECTIVES[objective]
         # scores in standardised target units, weighted back to log units
         wt, we = w[0] * float(self.ys.std[0]), w[1] * float(self.ys.std[1])
         xd = torch.from_numpy(self.xs.apply(X)).cuda()
         best = torch.zeros(1, dtype=torch.int32, device="cuda")
-        ccl_mlp_pick(self.handle, len(cfgs), xd.data_ptr(), wt, we, 0, best.data_ptr())
+        ccl_mlp_pick(self.handle, len(X), xd.data_ptr(), wt, we, 0, best.data_ptr())
         torch.cuda.synchronize()
-        i = int(best.item())
+        i = base[int(best.item())]
         return cfgs[i], i
 
     def rank(self, shape, objective="time", nchunks=None):
