@@ -152,7 +152,7 @@ def time_runs(cw, steps, runs):
 
 def batched_forms(log_energy=False):
     """The 64-grid workload: one graph launch (per-grid depth picked by the
-    cost model or T=4) vs a loop of plain T=1 ccl_wave_step calls."""
+    cost model, else T=4) vs a loop of plain T=1 ccl_wave_step calls."""
     import numpy as np
     import torch
 
@@ -166,9 +166,10 @@ def batched_forms(log_energy=False):
         depth, rows = 4, 64
         if model is not None:
             c, _ = model.pick((d["ny"], d["nx"]), "time", nchunks=1)
-            # rows 0 = automatic, resolved by the batch itself (every candidate
-            # row count is at least 16 >= T otherwise)
-            depth, rows = c.temporal_depth, c.tile_rows
+            # the model's depth; tile rows are left to the batch, which sizes
+            # them for the grids it steps together (the model's row pick is
+            # for a grid launched alone)
+            depth, rows = c.temporal_depth, 0
         specs.append(dict(ny=d["ny"], nx=d["nx"], steps=d["steps"], r2=0.25, depth=depth,
                           tile_rows=rows))
     if model is not None:

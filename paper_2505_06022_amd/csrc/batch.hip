@@ -12,12 +12,16 @@
 // after its stores; waiters acquire it before reading.
 //
 // Work order: a single queue holds all (block, grid, tile) items sorted by
-// block, then grid, then tile.  Waves pop items with an atomic counter.  An
-// item of block b depends only on items of block b-1, all of which sit
-// earlier in the queue and were popped by waves that are running, so every
-// wait ends without any assumption about how many waves are resident.  A
-// wait also ends after a time limit (an error flag is raised and all waves
-// drain the queue without computing), so the launch always completes.
+// block, then depth class, then grid, then tile.  (Stepping small groups of grids whose
+// buffers fit in the 256 MB Infinity Cache block by block was measured 5x
+// slower: a block of two grids is too little work to hide the hand-off
+// between consecutive blocks.)  Waves pop items with an atomic counter.  An
+// item of block b depends only on items of the same grid at block b-1, all
+// of which sit earlier in the queue and were popped by waves that are
+// running, so every wait ends without any assumption about how many waves
+// are resident.  A wait also ends after a time limit (an error flag is
+// raised and all waves drain the queue without computing), so the launch
+// always completes.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -33,6 +37,7 @@ namespace {
 constexpr int kWavesPerBlock = 4;
 constexpr int kThreads = 64 * kWavesPerBlock;
 
+
 struct GridDev {
   float *buf[4];
   int32_t ny, nx, pitch;
@@ -42,16 +47,22 @@ struct GridDev {
   float r2;
 };
 
+// The queue is a list of segments, one per (block, depth class): the tiles
+// of the class's grids that have that block, grids [g0, gend) of the sorted
+// list (each class is sorted by block count, descending, so the grids still
+// active at a block are a prefix of the class).
 struct BatchTables {
-  const GridDev *grids;          // sorted by nblocks, descending
-  const int32_t *prefix_tiles;   // [ngrids + 1] over the sorted grids
-  const int32_t *level_start;    // [max_blocks + 1] queue index of block b's first item
-  const int32_t *active;         // [max_blocks] grids with nblocks > b (a prefix)
+  const GridDev *grids;          // by depth class, then nblocks descending
+  const int32_t *prefix_tiles;   // [ngrids + 1] tiles before each grid
+  const int32_t *seg_start;      // [nseg + 1] queue index of each segment's first item
+  const int32_t *seg_block;      // [nseg] the segment's block
+  const int32_t *seg_g0;         // [nseg] its first grid
+  const int32_t *seg_gend;       // [nseg] one past its last grid
   int32_t *counters;             // per tile: blocks completed
   int32_t *ctl;                  // [0] queue head, [1] error flag
   const int64_t *wait_ticks;     // wall-clock ticks a wait may last
   int32_t total;
-  int32_t max_blocks;
+  int32_t nseg;
   int32_t ncounters;
 };
 
@@ -62,9 +73,9 @@ __global__ __launch_bounds__(256) void batch_reset_kernel(int32_t *counters, int
   if (i < 2) ctl[i] = 0;
 }
 
-__device__ __forceinline__ int upper_index(const int32_t *a, int n, int32_t v) {
-  // largest i in [0, n) with a[i] <= v (a ascending, a[0] <= v)
-  int lo = 0, hi = n - 1;
+__device__ __forceinline__ int upper_index(const int32_t *a, int lo, int n, int32_t v) {
+  // largest i in [lo, n) with a[i] <= v (a ascending, a[lo] <= v)
+  int hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (a[mid] <= v)
@@ -116,9 +127,11 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(const BatchTables t) {
     if (lane == 0) q = __hip_atomic_fetch_add(&t.ctl[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     q = __builtin_amdgcn_readfirstlane(q);
     if (q >= t.total) break;
-    const int b = upper_index(t.level_start, t.max_blocks, q);
-    const int32_t local = q - t.level_start[b];
-    const int g = upper_index(t.prefix_tiles, t.active[b], local);
+    const int sg = upper_index(t.seg_start, 0, t.nseg, q);
+    const int b = t.seg_block[sg];
+    const int g0 = t.seg_g0[sg];
+    const int32_t local = q - t.seg_start[sg] + t.prefix_tiles[g0];
+    const int g = upper_index(t.prefix_tiles, g0, t.seg_gend[sg], local);
     const GridDev G = t.grids[g];
     const int tl = local - t.prefix_tiles[g];
     const int seg = tl / G.nstrips;
@@ -231,7 +244,6 @@ extern "C" ccl_status ccl_batch_create(int32_t ngrids, const ccl_batch_grid *gri
   std::vector<GridDev> gd(ngrids);
   std::vector<int32_t> nblk(ngrids);
   int tmax = 1;
-  int64_t counters = 0;
   for (int g = 0; g < ngrids; ++g) {
     const ccl_batch_grid &G = grids[g];
     if (G.ny < 1 || G.nx < 1 || G.ny > (1 << 30) || G.nx > (1 << 30))
@@ -254,43 +266,94 @@ extern "C" ccl_status ccl_batch_create(int32_t ngrids, const ccl_batch_grid *gri
     D.pitch = static_cast<int32_t>(G.pitch);
     D.T = G.temporal_depth;
     D.A = w2::overlap(D.T);
-    D.tile_rows = G.tile_rows > 0 ? G.tile_rows : std::max(32, 16 * D.T);
+    D.tile_rows = G.tile_rows;  // 0: planned below
     D.nstrips = static_cast<int32_t>((G.nx + w2::strip_width(D.T) - 1) / w2::strip_width(D.T));
-    D.nsegs = static_cast<int32_t>((G.ny + D.tile_rows - 1) / D.tile_rows);
     D.nblocks = (G.steps + D.T - 1) / D.T;
     D.last_T = G.steps - D.T * (D.nblocks > 0 ? D.nblocks - 1 : 0);
     D.r2 = G.r2;
-    D.counter_base = static_cast<int32_t>(counters);
-    counters += static_cast<int64_t>(D.nstrips) * D.nsegs;
-    if (counters > INT32_MAX / 4) return fail(CCL_E_RANGE, "too many tiles");
     nblk[g] = D.nblocks;
     tmax = std::max(tmax, D.T);
   }
   tmax = tmax <= 1 ? 1 : tmax <= 2 ? 2 : tmax <= 4 ? 4 : 8;
-  // sort by number of blocks, descending (stable): the grids active at any
-  // block are then a prefix of the sorted list
+
+  // persistent grid: as many blocks as fit on the device at once
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  e = e ? e : hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const void *kfn = tmax == 1   ? batch_kernel_ptr<1>()
+                    : tmax == 2 ? batch_kernel_ptr<2>()
+                    : tmax == 4 ? batch_kernel_ptr<4>()
+                                : batch_kernel_ptr<8>();
+  e = e ? e : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, kThreads, 0);
+  if (e != hipSuccess) return hip_check(e, "occupancy query");
+  const int blocks = std::max(1, cus * std::max(1, per_cu));
+  const int64_t slots = static_cast<int64_t>(blocks) * kWavesPerBlock;
+
+  // order: by depth class (T descending), then block count, descending
+  // (stable).  Within a block the queue then holds one depth class after
+  // another, so the waves running at any moment execute the same tile code
+  // (mixing depths cost ~15%: each depth is its own unrolled loop)
   std::vector<int> order(ngrids);
   std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return gd[a].nblocks > gd[b].nblocks; });
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return gd[a].T != gd[b].T ? gd[a].T > gd[b].T : gd[a].nblocks > gd[b].nblocks;
+  });
+  // automatic tile rows: the largest candidate that still gives every
+  // resident wave a tile of the first block; at least max(8, T)
+  {
+    static const int32_t kRowsCand[] = {256, 128, 64, 32, 16, 8};
+    int32_t chosen = 0;
+    for (int32_t r : kRowsCand) {
+      int64_t items = 0;
+      for (const GridDev &D : gd) {
+        const int32_t rr = D.tile_rows > 0 ? D.tile_rows : std::max(r, std::max(8, D.T));
+        items += static_cast<int64_t>((D.ny + rr - 1) / rr) * D.nstrips;
+      }
+      chosen = r;
+      if (items >= slots) break;
+    }
+    for (GridDev &D : gd)
+      if (D.tile_rows == 0) D.tile_rows = std::max(chosen, std::max(8, D.T));
+  }
+  int64_t counters = 0;
+  for (int g = 0; g < ngrids; ++g) {
+    GridDev &D = gd[g];
+    D.nsegs = static_cast<int32_t>((D.ny + D.tile_rows - 1) / D.tile_rows);
+    D.counter_base = static_cast<int32_t>(counters);
+    counters += static_cast<int64_t>(D.nstrips) * D.nsegs;
+    if (counters > INT32_MAX / 4) return fail(CCL_E_RANGE, "too many tiles");
+  }
   std::vector<GridDev> sorted(ngrids);
   std::vector<int32_t> prefix(ngrids + 1, 0);
   for (int i = 0; i < ngrids; ++i) {
     sorted[i] = gd[order[i]];
     prefix[i + 1] = prefix[i] + sorted[i].nstrips * sorted[i].nsegs;
   }
-  const int32_t max_blocks = sorted[0].nblocks;
-  std::vector<int32_t> active(std::max(1, max_blocks), 0), level(max_blocks + 1, 0);
+  // queue segments: (block, depth class) -> the class's grids still active
+  // (a prefix of the class, which is sorted by block count)
+  std::vector<int32_t> cls;  // first grid of each depth class, then ngrids
+  for (int i = 0; i < ngrids; ++i)
+    if (i == 0 || sorted[i].T != sorted[i - 1].T) cls.push_back(i);
+  cls.push_back(ngrids);
+  int32_t max_blocks = 0;
+  for (const GridDev &D : sorted) max_blocks = std::max(max_blocks, D.nblocks);
+  std::vector<int32_t> seg_start, seg_block, seg_g0, seg_gend;
   int64_t total = 0;
   for (int b = 0; b < max_blocks; ++b) {
-    int a = 0;
-    while (a < ngrids && sorted[a].nblocks > b) ++a;
-    active[b] = a;
-    level[b] = static_cast<int32_t>(total);
-    total += prefix[a];
-    if (total > INT32_MAX / 2) return fail(CCL_E_RANGE, "batch queue too long");
+    for (size_t c = 0; c + 1 < cls.size(); ++c) {
+      int a = cls[c];
+      while (a < cls[c + 1] && sorted[a].nblocks > b) ++a;
+      if (a == cls[c]) continue;
+      seg_start.push_back(static_cast<int32_t>(total));
+      seg_block.push_back(b);
+      seg_g0.push_back(cls[c]);
+      seg_gend.push_back(a);
+      total += prefix[a] - prefix[cls[c]];
+      if (total > INT32_MAX / 2) return fail(CCL_E_RANGE, "batch queue too long");
+    }
   }
-  level[max_blocks] = static_cast<int32_t>(total);
+  const int32_t nseg = static_cast<int32_t>(seg_block.size());
+  seg_start.push_back(static_cast<int32_t>(total));
 
   BatchImpl *B = new BatchImpl();
   B->ngrids = ngrids;
@@ -298,13 +361,16 @@ extern "C" ccl_status ccl_batch_create(int32_t ngrids, const ccl_batch_grid *gri
   B->flags = flags;
   B->grids.assign(grids, grids + ngrids);
   B->nblocks = nblk;
-  // device layout: grids | prefix | level | active | counters | ctl | wait_ticks
+  // device layout: grids | prefix | segment tables | counters | ctl | wait_ticks
   auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+  const size_t nsg = static_cast<size_t>(std::max(nseg, 1));
   const size_t o_grids = 0;
   const size_t o_prefix = al(o_grids + sizeof(GridDev) * ngrids);
-  const size_t o_level = al(o_prefix + sizeof(int32_t) * (ngrids + 1));
-  const size_t o_active = al(o_level + sizeof(int32_t) * (max_blocks + 1));
-  const size_t o_count = al(o_active + sizeof(int32_t) * active.size());
+  const size_t o_sstart = al(o_prefix + sizeof(int32_t) * (ngrids + 1));
+  const size_t o_sblock = al(o_sstart + sizeof(int32_t) * (nsg + 1));
+  const size_t o_sg0 = al(o_sblock + sizeof(int32_t) * nsg);
+  const size_t o_sgend = al(o_sg0 + sizeof(int32_t) * nsg);
+  const size_t o_count = al(o_sgend + sizeof(int32_t) * nsg);
   const size_t o_ctl = al(o_count + sizeof(int32_t) * std::max<int64_t>(counters, 1));
   const size_t o_wait = al(o_ctl + sizeof(int32_t) * 2);
   const size_t bytes = al(o_wait + sizeof(int64_t));
@@ -315,12 +381,17 @@ extern "C" ccl_status ccl_batch_create(int32_t ngrids, const ccl_batch_grid *gri
   }
   char *d = static_cast<char *>(B->dev);
   const int64_t wait_ticks = int64_t(100000000) * 10;  // 10 s of the 100 MHz wall clock
-  hipError_t e = hipSuccess;
-  e = e ? e : hipMemcpy(d + o_grids, sorted.data(), sizeof(GridDev) * ngrids, hipMemcpyHostToDevice);
-  e = e ? e : hipMemcpy(d + o_prefix, prefix.data(), sizeof(int32_t) * (ngrids + 1), hipMemcpyHostToDevice);
-  e = e ? e : hipMemcpy(d + o_level, level.data(), sizeof(int32_t) * (max_blocks + 1), hipMemcpyHostToDevice);
-  e = e ? e : hipMemcpy(d + o_active, active.data(), sizeof(int32_t) * active.size(), hipMemcpyHostToDevice);
-  e = e ? e : hipMemcpy(d + o_wait, &wait_ticks, sizeof(int64_t), hipMemcpyHostToDevice);
+  auto put = [&](size_t off, const void *src, size_t n) {
+    if (e == hipSuccess && n > 0) e = hipMemcpy(d + off, src, n, hipMemcpyHostToDevice);
+  };
+  e = hipSuccess;
+  put(o_grids, sorted.data(), sizeof(GridDev) * ngrids);
+  put(o_prefix, prefix.data(), sizeof(int32_t) * (ngrids + 1));
+  put(o_sstart, seg_start.data(), sizeof(int32_t) * seg_start.size());
+  put(o_sblock, seg_block.data(), sizeof(int32_t) * seg_block.size());
+  put(o_sg0, seg_g0.data(), sizeof(int32_t) * seg_g0.size());
+  put(o_sgend, seg_gend.data(), sizeof(int32_t) * seg_gend.size());
+  put(o_wait, &wait_ticks, sizeof(int64_t));
   if (e != hipSuccess) {
     release(B);
     return hip_check(e, "hipMemcpy(batch tables)");
@@ -328,32 +399,19 @@ extern "C" ccl_status ccl_batch_create(int32_t ngrids, const ccl_batch_grid *gri
   BatchTables &t = B->tables;
   t.grids = reinterpret_cast<const GridDev *>(d + o_grids);
   t.prefix_tiles = reinterpret_cast<const int32_t *>(d + o_prefix);
-  t.level_start = reinterpret_cast<const int32_t *>(d + o_level);
-  t.active = reinterpret_cast<const int32_t *>(d + o_active);
+  t.seg_start = reinterpret_cast<const int32_t *>(d + o_sstart);
+  t.seg_block = reinterpret_cast<const int32_t *>(d + o_sblock);
+  t.seg_g0 = reinterpret_cast<const int32_t *>(d + o_sg0);
+  t.seg_gend = reinterpret_cast<const int32_t *>(d + o_sgend);
   t.counters = reinterpret_cast<int32_t *>(d + o_count);
   t.ctl = reinterpret_cast<int32_t *>(d + o_ctl);
   t.wait_ticks = reinterpret_cast<const int64_t *>(d + o_wait);
   B->wait_ticks_dev = reinterpret_cast<int64_t *>(d + o_wait);
   t.total = static_cast<int32_t>(total);
-  t.max_blocks = max_blocks;
+  t.nseg = nseg;
   t.ncounters = static_cast<int32_t>(counters);
   B->counter_blocks = static_cast<int>((std::max<int64_t>(counters, 2) + 255) / 256);
-
-  // persistent grid: as many blocks as fit on the device at once
-  int dev = 0, cus = 0, per_cu = 0;
-  e = hipGetDevice(&dev);
-  e = e ? e : hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const void *kfn = tmax == 1   ? batch_kernel_ptr<1>()
-                    : tmax == 2 ? batch_kernel_ptr<2>()
-                    : tmax == 4 ? batch_kernel_ptr<4>()
-                                : batch_kernel_ptr<8>();
-  e = e ? e : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, kThreads, 0);
-  if (e != hipSuccess) {
-    release(B);
-    return hip_check(e, "occupancy query");
-  }
-  B->blocks = std::max(1, cus * std::max(1, per_cu));
-  if (total == 0) B->blocks = 1;
+  B->blocks = total == 0 ? 1 : blocks;
 
   if (!(flags & CCL_BATCH_NO_GRAPH)) {
     e = hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking);
