@@ -42,14 +42,15 @@ def _key(k):
     return (tuple(k[0]), int(k[1]), int(k[2]), int(k[3]))
 
 
-def collect(out_dir, n_shapes=250, per_shape=16, n_shapes_3d=40, append=False, budget_s=1e9):
+def collect(out_dir, n_shapes=250, per_shape=16, n_shapes_3d=40, append=False, budget_s=1e9,
+            n_shapes_3d_large=40):
     """Time samples of the seeded training configs, saved to samples.json.
     With `append`, configs already in samples.json are skipped and the new
     samples are added to it (saved every 10 shapes)."""
     from . import ccl_costmodel_features, tune
     os.makedirs(out_dir, exist_ok=True)
     shapes, cfgs = tune.sample_space(n_shapes, TRAIN_SHAPE_SEED, per_shape, SAMPLE_SEED,
-                                     n_shapes_3d)
+                                     n_shapes_3d, n_shapes_3d_large)
     doc = dict(samples=[], features=[], meta={})
     path = os.path.join(out_dir, "samples.json")
     if append and os.path.exists(path):
@@ -315,6 +316,7 @@ def main(argv=None):
     c.add_argument("--out", required=True)
     c.add_argument("--shapes", type=int, default=250)
     c.add_argument("--shapes-3d", type=int, default=40)
+    c.add_argument("--shapes-3d-large", type=int, default=40)
     c.add_argument("--per-shape", type=int, default=16)
     c.add_argument("--append", action="store_true")
     c.add_argument("--budget", type=float, default=1e9)
@@ -348,7 +350,8 @@ def main(argv=None):
         import torch
         torch.cuda.set_device(0)
     if a.cmd == "collect":
-        collect(a.out, a.shapes, a.per_shape, a.shapes_3d, a.append, a.budget)
+        collect(a.out, a.shapes, a.per_shape, a.shapes_3d, a.append, a.budget,
+                a.shapes_3d_large)
     elif a.cmd == "energy":
         energy(a.out, a.count, a.window, a.budget)
     elif a.cmd == "train":

@@ -265,14 +265,20 @@ def unpack(p, sizes=(12, 64, 64, 2)):
     return ws, bs
 
 
-def sample_space(n_shapes: int, seed: int, per_shape: int, rng_seed: int, n_shapes_3d: int = 0):
+def sample_space(n_shapes: int, seed: int, per_shape: int, rng_seed: int, n_shapes_3d: int = 0,
+                 n_shapes_3d_large: int = 0):
     """Training configs: `n_shapes` seeded 2D shapes (sides log-uniform on
-    256..16384) and `n_shapes_3d` 3D shapes (sides 64..768), `per_shape`
-    candidates each drawn without replacement."""
+    256..16384), `n_shapes_3d` 3D shapes (sides 64..768) and
+    `n_shapes_3d_large` 3D shapes with sides 384..768 (log-uniform sides
+    rarely give large volumes), `per_shape` candidates each drawn without
+    replacement.  Each set extends the previous ones: a shape's configs do
+    not change when later sets are added."""
     import synth
     shapes = synth.cost_model_shapes(n_shapes, seed)
     if n_shapes_3d:
         shapes = shapes + synth.cost_model_shapes_3d(n_shapes_3d, seed + 100)
+    if n_shapes_3d_large:
+        shapes = shapes + synth.cost_model_shapes_3d(n_shapes_3d_large, seed + 200, lo=384)
     rs = np.random.default_rng(rng_seed)
     cfgs = []
     for sh in shapes:
