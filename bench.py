@@ -151,51 +151,62 @@ def time_runs(cw, steps, runs):
 
 
 def batched_forms(log_energy=False):
-    """The 64-grid workload: one graph launch (per-grid depth picked by the
-    cost model, else T=4) vs a loop of plain T=1 ccl_wave_step calls."""
+    """The 64-grid workload, each form on the same data:
+    * batched: one graph launch of the persistent kernel (per-grid depth
+      picked by the cost model, else T=4; tile rows sized by the batch);
+    * batched_per_grid: one graph launch holding every grid's own
+      ccl_wave_step sequence (the cost model's depth and rows per grid);
+    * per_grid_loop: a loop of plain T=1 ccl_wave_step calls."""
     import numpy as np
     import torch
 
+    import paper_2505_06022_amd as ccl
     import synth
     from paper_2505_06022_amd import tune
     from paper_2505_06022_amd.fields import BatchedWaves, ChunkedWave
     grids = synth.batched_grids()
     model = tune.CostModel.load(MODEL_PATH) if os.path.exists(MODEL_PATH) else None
-    specs = []
+    specs, specs_pg = [], []
     for d in grids:
         depth, rows = 4, 64
         if model is not None:
             c, _ = model.pick((d["ny"], d["nx"]), "time", nchunks=1)
-            # the model's depth; tile rows are left to the batch, which sizes
-            # them for the grids it steps together (the model's row pick is
-            # for a grid launched alone)
-            depth, rows = c.temporal_depth, 0
-        specs.append(dict(ny=d["ny"], nx=d["nx"], steps=d["steps"], r2=0.25, depth=depth,
-                          tile_rows=rows))
+            depth, rows = c.temporal_depth, c.tile_rows
+        base = dict(ny=d["ny"], nx=d["nx"], steps=d["steps"], r2=0.25, depth=depth)
+        # the persistent kernel sizes tiles for all grids at once (the
+        # model's row pick is for a grid launched alone); the per-grid form
+        # launches each grid alone, so it takes the model's rows
+        specs.append(dict(base, tile_rows=0 if model is not None else rows))
+        specs_pg.append(dict(base, tile_rows=rows))
     if model is not None:
         model.close()
-    bw = BatchedWaves(specs)
-    for g, d in enumerate(grids):
-        u0 = synth.gaussian_field((d["ny"], d["nx"]), d["sigma"], d["seed"])
-        bw.scatter(g, u0, u0)
-    torch.cuda.synchronize()
-    import paper_2505_06022_amd as ccl
-    bw.run()
-    ccl.ccl_batch_check(bw.handle)
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    reps = 3
-    a.record()
-    for _ in range(reps):
-        bw.run()
-    b.record()
-    ccl.ccl_batch_check(bw.handle)
-    t_batched = a.elapsed_time(b) * 1e-3 / reps
     cell_steps = sum(d["ny"] * d["nx"] * d["steps"] for d in grids)
-    p_batched = average_power(bw.run) if log_energy else None
-    bw.close()
-    del bw
-    torch.cuda.empty_cache()
+
+    def run_batch(sp, flags):
+        bw = BatchedWaves(sp, flags=flags)
+        for g, d in enumerate(grids):
+            u0 = synth.gaussian_field((d["ny"], d["nx"]), d["sigma"], d["seed"])
+            bw.scatter(g, u0, u0)
+        torch.cuda.synchronize()
+        bw.run()
+        ccl.ccl_batch_check(bw.handle)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        reps = 3
+        a.record()
+        for _ in range(reps):
+            bw.run()
+        b.record()
+        ccl.ccl_batch_check(bw.handle)
+        t = a.elapsed_time(b) * 1e-3 / reps
+        p = average_power(bw.run) if log_energy else None
+        bw.close()
+        del bw
+        torch.cuda.empty_cache()
+        return t, p
+
+    t_batched, p_batched = run_batch(specs, 0)
+    t_pg, p_pg = run_batch(specs_pg, ccl.CCL_BATCH_PER_GRID)
     # per-grid loop of plain (T=1) calls on the same grids, same data
     cws = []
     for g, d in enumerate(grids):
@@ -210,6 +221,8 @@ def batched_forms(log_energy=False):
 
     loop_once()
     torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
     a.record()
     loop_once()
     b.record()
@@ -222,6 +235,9 @@ def batched_forms(log_energy=False):
     return {"grids": len(grids), "cell_steps": cell_steps,
             "batched_mcells": round(cell_steps / t_batched / 1e6, 1),
             "batched_ms": round(t_batched * 1e3, 3),
+            "batched_per_grid_mcells": round(cell_steps / t_pg / 1e6, 1),
+            "batched_per_grid_ms": round(t_pg * 1e3, 3),
+            "batched_per_grid_nj_per_cell_step": nj(p_pg, t_pg),
             "per_grid_loop_mcells": round(cell_steps / t_loop / 1e6, 1),
             "per_grid_loop_ms": round(t_loop * 1e3, 3),
             "batched_nj_per_cell_step": nj(p_batched, t_batched),

@@ -259,6 +259,11 @@ typedef struct {
 typedef struct ccl_batch ccl_batch;  /* opaque */
 
 #define CCL_BATCH_NO_GRAPH 1  /* ccl_batch_run launches kernels directly */
+#define CCL_BATCH_PER_GRID 2  /* step each grid by its own ccl_wave_step
+                                 sequence (one chunk, its own T and tile
+                                 rows), grid after grid, instead of the
+                                 persistent kernel: each grid's buffers stay
+                                 in the last-level cache across its blocks */
 
 /* Plans a batch: tile tables, progress counters and the captured graph
  * (library-owned device memory, released by ccl_batch_destroy).  The grid

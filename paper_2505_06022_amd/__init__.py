@@ -77,6 +77,7 @@ class ccl_batch_grid(ctypes.Structure):
 
 
 CCL_BATCH_NO_GRAPH = 1
+CCL_BATCH_PER_GRID = 2
 
 
 class ccl_tune_config(ctypes.Structure):

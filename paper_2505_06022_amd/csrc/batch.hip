@@ -1,5 +1,6 @@
 // Many independent 2D grids stepped by one persistent launch, captured in a
-// HIP graph.
+// HIP graph (or, with CCL_BATCH_PER_GRID, by each grid's own ccl_wave_step
+// sequence captured in the same way).
 //
 // Every grid is cut into the same 2D tiles as the chunked launch (a strip of
 // 256 columns by a segment of rows, processed by one wave with the code in
@@ -201,9 +202,45 @@ struct BatchImpl {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int64_t *wait_ticks_dev = nullptr;
+  std::vector<int32_t> final_prev, final_cur;  // CCL_BATCH_PER_GRID: buffer roles at the end
 };
 
+// CCL_BATCH_PER_GRID: every grid stepped by its own ccl_wave_step call (one
+// chunk, its own T and tile rows), one grid after another, so that each
+// grid's buffers stay cache-resident across its T-blocks.
+static ccl_status enqueue_per_grid(BatchImpl *B, hipStream_t s) {
+  for (int g = 0; g < B->ngrids; ++g) {
+    const ccl_batch_grid &G = B->grids[g];
+    if (G.steps == 0) continue;
+    ccl_chunk ch;
+    memset(&ch, 0, sizeof(ch));
+    ch.dims = 2;
+    ch.range[0] = ch.global_range[0] = G.ny;
+    ch.range[1] = ch.global_range[1] = G.nx;
+    ccl_chunk_buffer b[4];
+    for (int k = 0; k < 4; ++k) {
+      memset(&b[k], 0, sizeof(b[k]));
+      b[k].base = G.buf[k];
+      b[k].region.dims = 2;
+      b[k].region.range[0] = G.ny;
+      b[k].region.range[1] = G.nx;
+      b[k].pitch[0] = G.pitch;
+      b[k].pitch[1] = 1;
+    }
+    ccl_wave_params p;
+    memset(&p, 0, sizeof(p));
+    p.dims = 2;
+    p.r2 = G.r2;
+    p.temporal_depth = G.temporal_depth;
+    p.tile_rows = G.tile_rows;
+    ccl_status st = ccl_wave_step(&p, 1, &ch, &b[0], &b[1], &b[2], &b[3], G.steps, s);
+    if (st != CCL_OK) return st;
+  }
+  return CCL_OK;
+}
+
 static ccl_status enqueue_batch(BatchImpl *B, hipStream_t s) {
+  if (B->flags & CCL_BATCH_PER_GRID) return enqueue_per_grid(B, s);
   const BatchTables &t = B->tables;
   hipLaunchKernelGGL(batch_reset_kernel, dim3(B->counter_blocks), dim3(256), 0, s, t.counters,
                      t.ncounters, t.ctl);
@@ -240,7 +277,8 @@ extern "C" ccl_status ccl_batch_create(int32_t ngrids, const ccl_batch_grid *gri
   clear_error();
   if (!out || (ngrids > 0 && !grids)) return fail(CCL_E_INVALID, "NULL argument");
   if (ngrids < 1) return fail(CCL_E_INVALID, "ngrids=%d < 1", ngrids);
-  if ((flags & ~CCL_BATCH_NO_GRAPH) != 0) return fail(CCL_E_INVALID, "unknown flags");
+  if ((flags & ~(CCL_BATCH_NO_GRAPH | CCL_BATCH_PER_GRID)) != 0)
+    return fail(CCL_E_INVALID, "unknown flags");
   std::vector<GridDev> gd(ngrids);
   std::vector<int32_t> nblk(ngrids);
   int tmax = 1;
@@ -276,6 +314,32 @@ extern "C" ccl_status ccl_batch_create(int32_t ngrids, const ccl_batch_grid *gri
   }
   tmax = tmax <= 1 ? 1 : tmax <= 2 ? 2 : tmax <= 4 ? 4 : 8;
 
+  BatchImpl *B = nullptr;
+  ccl_status st = CCL_OK;
+  if (flags & CCL_BATCH_PER_GRID) {
+    B = new BatchImpl();
+    B->ngrids = ngrids;
+    B->flags = flags;
+    B->grids.assign(grids, grids + ngrids);
+    B->nblocks = nblk;
+    // the roles ccl_wave_step's rotation leaves: T = 1 blocks swap u_prev
+    // and u_cur, T > 1 blocks swap each with its second buffer
+    for (int g = 0; g < ngrids; ++g) {
+      int up = 0, uc = 1, wp = 2, wc = 3;
+      for (int done = 0; done < grids[g].steps;) {
+        const int tb = std::min(grids[g].temporal_depth, grids[g].steps - done);
+        if (tb == 1) {
+          std::swap(up, uc);
+        } else {
+          std::swap(up, wp);
+          std::swap(uc, wc);
+        }
+        done += tb;
+      }
+      B->final_prev.push_back(up);
+      B->final_cur.push_back(uc);
+    }
+  } else {
   // persistent grid: as many blocks as fit on the device at once
   int dev = 0, cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -355,7 +419,7 @@ extern "C" ccl_status ccl_batch_create(int32_t ngrids, const ccl_batch_grid *gri
   const int32_t nseg = static_cast<int32_t>(seg_block.size());
   seg_start.push_back(static_cast<int32_t>(total));
 
-  BatchImpl *B = new BatchImpl();
+  B = new BatchImpl();
   B->ngrids = ngrids;
   B->tmax = tmax;
   B->flags = flags;
@@ -374,7 +438,7 @@ extern "C" ccl_status ccl_batch_create(int32_t ngrids, const ccl_batch_grid *gri
   const size_t o_ctl = al(o_count + sizeof(int32_t) * std::max<int64_t>(counters, 1));
   const size_t o_wait = al(o_ctl + sizeof(int32_t) * 2);
   const size_t bytes = al(o_wait + sizeof(int64_t));
-  ccl_status st = hip_check(hipMalloc(&B->dev, bytes), "hipMalloc(batch tables)");
+  st = hip_check(hipMalloc(&B->dev, bytes), "hipMalloc(batch tables)");
   if (st != CCL_OK) {
     delete B;
     return st == CCL_E_HIP ? fail(CCL_E_NOMEM, "batch tables: %s", ccl_last_error()) : st;
@@ -412,7 +476,9 @@ extern "C" ccl_status ccl_batch_create(int32_t ngrids, const ccl_batch_grid *gri
   t.ncounters = static_cast<int32_t>(counters);
   B->counter_blocks = static_cast<int>((std::max<int64_t>(counters, 2) + 255) / 256);
   B->blocks = total == 0 ? 1 : blocks;
+  }
 
+  hipError_t e = hipSuccess;
   if (!(flags & CCL_BATCH_NO_GRAPH)) {
     e = hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking);
     e = e ? e : hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal);
@@ -458,6 +524,7 @@ extern "C" ccl_status ccl_batch_check(ccl_batch *b, void *hip_stream) {
   ccl_status st = hip_check(hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)),
                             "hipStreamSynchronize");
   if (st != CCL_OK) return st;
+  if (B->flags & CCL_BATCH_PER_GRID) return CCL_OK;  // no waits to time out
   int32_t ctl[2] = {0, 0};
   st = hip_check(hipMemcpy(ctl, B->tables.ctl, sizeof(ctl), hipMemcpyDeviceToHost),
                  "hipMemcpy(batch status)");
@@ -470,6 +537,7 @@ extern "C" ccl_status ccl_batch_set_wait_limit(ccl_batch *b, int64_t microsecond
   clear_error();
   if (!b || !b->impl) return fail(CCL_E_INVALID, "NULL batch");
   if (microseconds < 0) return fail(CCL_E_INVALID, "negative wait limit");
+  if (b->impl->flags & CCL_BATCH_PER_GRID) return CCL_OK;  // nothing waits
   const int64_t ticks = microseconds * 100;  // 100 MHz wall clock
   return hip_check(hipMemcpy(b->impl->wait_ticks_dev, &ticks, sizeof(ticks),
                              hipMemcpyHostToDevice),
@@ -481,6 +549,11 @@ extern "C" ccl_status ccl_batch_result(const ccl_batch *b, int32_t grid, int32_t
   clear_error();
   if (!b || !b->impl || !prev_buf || !cur_buf) return fail(CCL_E_INVALID, "NULL argument");
   if (grid < 0 || grid >= b->impl->ngrids) return fail(CCL_E_INVALID, "grid %d out of range", grid);
+  if (b->impl->flags & CCL_BATCH_PER_GRID) {
+    *prev_buf = b->impl->final_prev[grid];
+    *cur_buf = b->impl->final_cur[grid];
+    return CCL_OK;
+  }
   const int set = b->impl->nblocks[grid] & 1;
   *prev_buf = 2 * set;
   *cur_buf = 2 * set + 1;

@@ -42,8 +42,10 @@ def inputs(i, s):
     return up, uc
 
 
-@pytest.mark.parametrize("flags", [0, 1])
+@pytest.mark.parametrize("flags", [0, 1, 2, 3])
 def test_batch_matches_oracle(flags):
+    """Persistent kernel (flags 0, 1 = without the graph) and per-grid
+    ccl_wave_step sequences (2, 3 = without the graph)."""
     from paper_2505_06022_amd.fields import BatchedWaves
     bw = BatchedWaves(SPECS, flags=flags, fill=float("nan"))
     refs = []
@@ -64,13 +66,14 @@ def test_batch_matches_oracle(flags):
     bw.close()
 
 
-def test_graph_replays_repeat():
+@pytest.mark.parametrize("mode", [0, 2])
+def test_graph_replays_repeat(mode):
     """Replays of the captured graph, with eager work in between, each equal
     the eager (no-graph) result."""
     import paper_2505_06022_amd as ccl
     from paper_2505_06022_amd.fields import BatchedWaves
     specs = SPECS[:2] + SPECS[3:5]
-    bw = BatchedWaves(specs, flags=0)
+    bw = BatchedWaves(specs, flags=mode)
     ref = BatchedWaves(specs, flags=ccl.CCL_BATCH_NO_GRAPH)
     ins = [inputs(i, s) for i, s in enumerate(specs)]
     for i in range(len(specs)):
