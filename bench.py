@@ -7,9 +7,10 @@ domain, Dirichlet zero outside the share) split into 4 device-local chunks,
 halo exchanges included, through ccl_wave_step.  Inputs are resident in HBM
 before the timed region; the timed region is bracketed by synchronisation.
 
-The launch config (temporal depth T, rows per tile) is the learned cost
-model's pick when a trained model is present, else the best of a quick
-autotuner sweep; ``--depth``/``--tile-rows`` override both.  Besides the
+The launch config (temporal depth T, rows per tile) is the fastest, as
+measured, of the learned cost model's three best candidates when a trained
+model is present, else the best of a quick autotuner sweep; ``--depth``
+(with ``--tile-rows``, 0 = automatic) overrides both.  Besides the
 headline ("tuned") form the line reports the plain form (T = 1), device
 energy per step, and the 64-grid batched workload run as one graph launch
 against a per-grid loop of plain calls.
@@ -35,21 +36,23 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def load_traffic(depth: int, rows: int):
+def load_traffic(depth: int, rows: int, path: str | None = None):
     """HBM bytes per stencil launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source and config."""
+    summary (one section per profiled launch configuration), if one was
+    taken on the current kernel source and this config."""
     from paper_2505_06022_amd.profile_run import kernel_source_hash
-    path = os.path.join(ROOT, "profiles", "traffic_wave2d_8192_share_k4.md")
+    path = path or os.path.join(ROOT, "profiles", "traffic_wave2d_8192_share_k4.md")
     try:
         with open(path) as f:
-            line = next(l for l in f if l.startswith("traffic-json: "))
-        doc = json.loads(line[len("traffic-json: "):])
-    except (OSError, ValueError, StopIteration):
+            docs = [json.loads(l[len("traffic-json: "):]) for l in f
+                    if l.startswith("traffic-json: ")]
+    except (OSError, ValueError):
         return None
-    if (doc.get("kernel_hash") != kernel_source_hash() or doc.get("depth") != depth
-            or doc.get("tile_rows") != rows):
-        return None
-    return doc.get("bytes_per_launch")
+    for doc in docs:
+        if (doc.get("kernel_hash") == kernel_source_hash() and doc.get("depth") == depth
+                and doc.get("tile_rows") == rows):
+            return doc.get("bytes_per_launch")
+    return None
 
 
 def cpu_baseline(w, seconds: float = 12.0):
@@ -129,7 +132,7 @@ def average_power(run_once, min_span=2.0, limit=30.0):
 
 def pick_config(w, args):
     """(T, rows, how) for the headline share."""
-    if args.depth and args.tile_rows:
+    if args.depth:
         return args.depth, args.tile_rows, "given"
     from paper_2505_06022_amd import tune
     return tune.launch_config(w["shape"], w["chunks"], w["r2"],
@@ -303,7 +306,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10, help="timed bench steps (full runs)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--depth", type=int, default=0, help="temporal depth T (0 = pick)")
-    ap.add_argument("--tile-rows", type=int, default=0, help="rows per tile (0 = pick)")
+    ap.add_argument("--tile-rows", type=int, default=0,
+                    help="rows per tile with --depth (0 = automatic)")
     ap.add_argument("--sweep", action="store_true", help="pick by autotuner sweep, not model")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",

@@ -1,10 +1,12 @@
 // 3D seven-point leapfrog stencil, T = 2..8 steps per pass over HBM.
 //
-// Work unit: one 256-thread block owns a patch of 64 columns by 16*P rows
+// Work unit: one 512-thread block owns a patch of 64 columns by 32*P rows
 // and streams along z through a segment of planes.  Thread (ly, lx) holds
 // four consecutive columns (one 16-byte group) of P consecutive rows; the
 // 16 threads of a patch row are one DPP row, so x-neighbours come from DPP
-// row shifts.  For every level l < T the thread keeps the last three planes
+// row shifts.  A taller patch re-computes less of its overlap with the
+// neighbouring patches (at T = 6 a 64 x 64 patch stores 48 x 52 cells, a
+// 64 x 32 patch 48 x 20), at the same registers per thread.  For every level l < T the thread keeps the last three planes
 // of u^{n+l} over its cells in registers (a rotating three-slot ring), so
 // z-neighbours are register reads.  y-neighbours inside a thread's P rows
 // are its own registers; the first and last of its rows take their outer
@@ -30,8 +32,21 @@
 namespace ccl {
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kPatchCols = 64;
+// Block shape: kThreads threads in rows of kLX; a patch row is kLX groups
+// of four columns and the patch has kThreads / kLX thread rows.
+#ifndef CCL_W3T_THREADS
+#define CCL_W3T_THREADS 512
+#endif
+#ifndef CCL_W3T_LX
+#define CCL_W3T_LX 16
+#endif
+constexpr int kThreads = CCL_W3T_THREADS;
+constexpr int kLX = CCL_W3T_LX;
+constexpr int kLY = kThreads / kLX;
+constexpr int kPatchCols = 4 * kLX;
+static_assert(kLX == 16 || kLX == 32 || kLX == 64, "a patch row is 16, 32 or 64 lanes");
+static_assert(kThreads % 64 == 0 && kThreads % kLX == 0, "whole waves and thread rows");
+static_assert((kThreads & (kThreads - 1)) == 0, "row neighbours wrap with a power-of-two mask");
 constexpr int kMaxChunksPerLaunch = 8;
 
 // Rows per thread, planes loaded ahead, overlap, output extent and LDS
@@ -47,7 +62,9 @@ __host__ __device__ constexpr int tb_prefetch(int) { return CCL_W3T_PF; }
 #endif
 __host__ __device__ constexpr int tb_overlap(int T) { return 4 * ((T + 3) / 4); }
 __host__ __device__ constexpr int tb_out_cols(int T) { return kPatchCols - 2 * tb_overlap(T); }
-__host__ __device__ constexpr int tb_out_rows(int T) { return 16 * tb_rows(T) - 2 * T; }
+__host__ __device__ constexpr int tb_out_rows(int T) { return kLY * tb_rows(T) - 2 * T; }
+static_assert(tb_out_cols(CCL_MAX_DEPTH) > 0 && tb_out_rows(CCL_MAX_DEPTH) > 0,
+              "every depth leaves an interior to store");
 #ifndef CCL_W3T_NB
 __host__ __device__ constexpr int tb_lds_buffers(int T) { return T <= 4 ? 2 : 1; }
 #else
@@ -81,13 +98,17 @@ struct W3TArgs {
   W3TChunk ch[kMaxChunksPerLaunch];
 };
 
+// x-neighbours across the lanes of a patch row.  16-lane rows are DPP rows
+// (row_shr:1 / row_shl:1); wider rows use the wave shifts (wave_shr:1 /
+// wave_shl:1), where the first lane of the second row of a wave receives
+// the last lane of the first: a patch-edge cell, never valid, so harmless.
 __device__ __forceinline__ float row_from_left(float v) {
-  // lane l receives lane l-1's value within its 16-lane row (row_shr:1)
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kLX == 16 ? 0x111 : 0x138,
+                                                    0xf, 0xf, false));
 }
 __device__ __forceinline__ float row_from_right(float v) {
-  // lane l receives lane l+1's value within its 16-lane row (row_shl:1)
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kLX == 16 ? 0x101 : 0x130,
+                                                    0xf, 0xf, false));
 }
 
 // One buffer as the streaming loop sees it: its base, the plane index of
@@ -235,8 +256,8 @@ __device__ __forceinline__ void stream_patch(const Patch<tb_rows(T)> &S, float r
       // outer y-neighbours of this thread's rows in plane r of u^{n+t-1}
       // (the top thread row reads the bottom one's words: patch-edge cells
       // are never valid, so any value there is harmless)
-      const float4 up = xch[b][t - 1][1][(tid - 16) & (kThreads - 1)];
-      const float4 dn = xch[b][t - 1][0][(tid + 16) & (kThreads - 1)];
+      const float4 up = xch[b][t - 1][1][(tid - kLX) & (kThreads - 1)];
+      const float4 dn = xch[b][t - 1][0][(tid + kLX) & (kThreads - 1)];
       float4 o[P];
 #pragma unroll
       for (int j = 0; j < P; ++j) {
@@ -307,7 +328,7 @@ __global__ __launch_bounds__(kThreads) void wave3d_tb_kernel(const W3TArgs a) {
   const int strip = local - rb * C.nstrips;
 
   const int tid = threadIdx.x;
-  const int lx = tid & 15, ly = tid >> 4;
+  const int lx = tid % kLX, ly = tid / kLX;
   const int px = C.cx0 - A + strip * OW;  // patch origin
   const int py = C.cy0 - T + rb * OH;
   const int xl = px + 4 * lx;
@@ -339,7 +360,7 @@ __global__ __launch_bounds__(kThreads) void wave3d_tb_kernel(const W3TArgs a) {
   S.lpx = w2::cols_of(xl, C.lp[4], C.lp[5]);
   S.dom = w2::cols_of(xl, a.gx0, a.gx1);
   S.out = w2::cols_of(xl, max(C.cx0, px + A), min(C.cx1, px + A + OW));
-  S.xy_in = px >= a.gx0 && px + kPatchCols <= a.gx1 && py >= a.gy0 && py + 16 * P <= a.gy1;
+  S.xy_in = px >= a.gx0 && px + kPatchCols <= a.gx1 && py >= a.gy0 && py + kLY * P <= a.gy1;
   __shared__ float4 xch[tb_lds_buffers(T)][T][2][kThreads];
   stream_patch<T>(S, a.r2, tid, xch);
 }

@@ -2,6 +2,7 @@
 
     python -m paper_2505_06022_amd.learn collect  --out DIR [--shapes 250 --per-shape 16 --append]
     python -m paper_2505_06022_amd.learn energy   --out DIR [--count 120 --window 1.0]
+    python -m paper_2505_06022_amd.learn remeasure --out DIR [--dims 3 --min-depth 2]
     python -m paper_2505_06022_amd.learn train    --data DIR/samples.json --model MODEL.json
     python -m paper_2505_06022_amd.learn evaluate --model MODEL.json --out DIR [--shapes 200]
 
@@ -10,6 +11,8 @@ collect  : seeded training shapes (2D sides log-uniform on 256..16384, 3D
            timed by the library's autotuner;
 energy   : device energy for a seeded subset of those samples (each needs a
            window spanning two updates of the ~1 Hz energy counter);
+remeasure: new time (and energy, where labelled) for the samples of one
+           kernel family after that kernel changed, in place;
 train    : the 12-64-64-2 MLP fitted on the GPU by the library's kernels;
 evaluate : seeded held-out shapes never seen in training, each swept
            exhaustively (every candidate measured); the model's pick is
@@ -117,6 +120,52 @@ def energy(out_dir, count=120, window_s=1.0, budget_s=600.0):
             break
     _save(out_dir, doc)
     _log(f"energy labels: {done}/{len(pick)} in {time.perf_counter() - t0:.0f} s")
+
+
+def remeasure(out_dir, dims=3, min_depth=2, window_s=1.0):
+    """Re-measures in place the samples of one kernel family (domains of
+    `dims` dimensions at depth T >= min_depth), for use after that kernel
+    changed: every such sample gets a new time, and those that held an
+    energy label a new energy label, so the labelled subset and the order
+    of the samples stay as they were."""
+    from . import ccl_costmodel_features, make_tune_config, tune
+    path = os.path.join(out_dir, "samples.json")
+    with open(path) as f:
+        doc = json.load(f)
+    samples, feats = doc["samples"], doc["features"]
+    by_shape = {}
+    for j, s in enumerate(samples):
+        shape, _, T, _ = s["key"]
+        if len(shape) == dims and T >= min_depth:
+            by_shape.setdefault(tuple(shape), []).append(j)
+    _log(f"{sum(map(len, by_shape.values()))} samples over {len(by_shape)} shapes to re-measure")
+    t0 = time.perf_counter()
+    relabelled = 0
+    for i, (sh, idx) in enumerate(by_shape.items()):
+        cfgs = [make_tune_config(*samples[j]["key"]) for j in idx]
+        new = tune.measure(cfgs)
+        x = ccl_costmodel_features(cfgs).tolist()
+        for j, c, r, f in zip(idx, cfgs, new, x):
+            old = samples[j]
+            had_energy = old.get("j_per_cell_step") is not None and np.isfinite(
+                old["j_per_cell_step"])
+            if had_energy:
+                e = tune.measure([c], energy_window_s=window_s)[0]
+                r["j_per_step"], r["j_per_cell_step"] = e["j_per_step"], e["j_per_cell_step"]
+                r["window_s"] = e["window_s"]
+                relabelled += 1
+            samples[j], feats[j] = r, f
+        if (i + 1) % 10 == 0:
+            _save(out_dir, doc)
+            _log(f"  {i + 1}/{len(by_shape)} shapes, {relabelled} energy labels, "
+                 f"{time.perf_counter() - t0:.0f} s")
+    doc["meta"]["remeasured"] = dict(dims=dims, min_depth=min_depth,
+                                     samples=sum(map(len, by_shape.values())),
+                                     energy_labels=relabelled,
+                                     seconds=time.perf_counter() - t0)
+    _save(out_dir, doc)
+    _log(f"re-measured {sum(map(len, by_shape.values()))} samples ({relabelled} energy labels) "
+         f"in {time.perf_counter() - t0:.0f} s")
 
 
 def _pick_quality(model, X, Y, groups):
@@ -229,11 +278,14 @@ def evaluate(model_path, out_dir, n_shapes=200, start=0, count=None, budget_s=1e
     return rows
 
 
-def energy_check(model_path, out_dir, n_shapes=200, count=4, window_s=1.0, top=3):
+def energy_check(model_path, out_dir, n_shapes=200, count=4, window_s=1.0, top=3, repeats=2):
     """For the first held-out shapes: device energy of the model's energy
     pick and of the `top` fastest configs of the time sweep (the energy
     judge is restricted to those, since a full energy sweep would need ~2 s
-    of counter time per candidate)."""
+    of counter time per candidate).  Each config's energy is the mean over
+    `repeats` windows with a valid reading: one window reads the ~1 Hz
+    counter at two updates only, and a single misplaced update can shift it
+    by tens of percent."""
     from . import tune
     import synth
     shapes = synth.cost_model_shapes(n_shapes, HELD_OUT_SEED)[:count]
@@ -247,16 +299,21 @@ def energy_check(model_path, out_dir, n_shapes=200, count=4, window_s=1.0, top=3
         pick_cfg, _ = model.pick(sh, "energy")
         pick = keys.index(tune.cfg_key(pick_cfg))
         idx = sorted(set(int(j) for j in order) | {pick})
-        meas = tune.measure([cfgs[j] for j in idx], energy_window_s=window_s)
-        e = {j: m["j_per_step"] for j, m in zip(idx, meas)
-             if m["j_per_step"] is not None and np.isfinite(m["j_per_step"])
-             and m["j_per_step"] > 0}
+        reads = {j: [] for j in idx}
+        for _ in range(repeats):
+            meas = tune.measure([cfgs[j] for j in idx], energy_window_s=window_s)
+            for j, m in zip(idx, meas):
+                v = m["j_per_step"]
+                if v is not None and np.isfinite(v) and v > 0:
+                    reads[j].append(v)
+        e = {j: float(np.mean(v)) for j, v in reads.items() if v}
         if pick not in e:
             _log(f"  energy {sh}: no valid energy window for the pick; shape skipped")
             continue
         best = min(e, key=e.get)
         out.append(dict(shape=list(sh), pick=keys[pick], best=keys[best], e_pick=e[pick],
                         e_best=e[best], ratio=e[pick] / e[best],
+                        reads={str(keys[j][1:]): v for j, v in reads.items()},
                         time_pick_over_best=res[pick]["s_per_step"] / res[order[0]]["s_per_step"]))
         _log(f"  energy {sh}: pick/best {e[pick] / e[best]:.3f} ({keys[pick][1:]} vs "
              f"{keys[best][1:]})")
@@ -325,6 +382,11 @@ def main(argv=None):
     en.add_argument("--count", type=int, default=120)
     en.add_argument("--window", type=float, default=1.0)
     en.add_argument("--budget", type=float, default=600.0)
+    rm = sub.add_parser("remeasure")
+    rm.add_argument("--out", required=True)
+    rm.add_argument("--dims", type=int, default=3)
+    rm.add_argument("--min-depth", type=int, default=2)
+    rm.add_argument("--window", type=float, default=1.0)
     t = sub.add_parser("train")
     t.add_argument("--data", required=True)
     t.add_argument("--model", required=True)
@@ -342,6 +404,7 @@ def main(argv=None):
     ec.add_argument("--model", required=True)
     ec.add_argument("--out", required=True)
     ec.add_argument("--count", type=int, default=4)
+    ec.add_argument("--repeats", type=int, default=2)
     sm = sub.add_parser("summarise")
     sm.add_argument("--out", required=True)
     sm.add_argument("--model", default=None)
@@ -354,12 +417,14 @@ def main(argv=None):
                 a.shapes_3d_large)
     elif a.cmd == "energy":
         energy(a.out, a.count, a.window, a.budget)
+    elif a.cmd == "remeasure":
+        remeasure(a.out, a.dims, a.min_depth, a.window)
     elif a.cmd == "train":
         train(a.data, a.model, a.epochs, a.lr, seeds=a.seeds)
     elif a.cmd == "evaluate":
         evaluate(a.model, a.out, a.shapes, a.start, a.count, a.budget)
     elif a.cmd == "energy-check":
-        energy_check(a.model, a.out, count=a.count)
+        energy_check(a.model, a.out, count=a.count, repeats=a.repeats)
     else:
         summarise(a.out, a.model)
     return 0

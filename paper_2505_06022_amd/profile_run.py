@@ -81,7 +81,7 @@ def _per_kernel(path, counter):
     return out
 
 
-def summarise(fetch_csv, write_csv, depth, rows, md_path, dims=2):
+def summarise(fetch_csv, write_csv, depth, rows, md_path, dims=2, append=False):
     fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
     write = _per_kernel(write_csv, "WRITE_SIZE")
     kern = "wave2d" if dims == 2 else "wave3d"
@@ -119,7 +119,8 @@ def summarise(fetch_csv, write_csv, depth, rows, md_path, dims=2):
         f"paper_2505_06022_amd.profile_run run --dims {dims} --depth {depth} --rows {rows}",
         f"python3 -m paper_2505_06022_amd.profile_run summarise --fetch OUT/fetch/.../"
         f"p_counter_collection.csv --write OUT/write/.../p_counter_collection.csv --dims {dims} "
-        f"--depth {depth} --rows {rows} --md {os.path.relpath(md_path, ROOT)}",
+        f"--depth {depth} --rows {rows} --md {os.path.relpath(md_path, ROOT)}"
+        + (" --append" if append and os.path.exists(md_path) else ""),
         "```",
         "",
         "The first stencil dispatch (cold caches after the host scatter) is left out of the "
@@ -137,12 +138,18 @@ def summarise(fetch_csv, write_csv, depth, rows, md_path, dims=2):
         "traffic-json: " + json.dumps(doc),
         "",
     ]
-    with open(md_path, "w") as f:
-        f.write("\n".join(lines))
+    if append and os.path.exists(md_path):
+        # one section per launch configuration in the same file
+        lines[0] = "#" + lines[0]
+        with open(md_path, "a") as f:
+            f.write("\n" + "\n".join(lines))
+    else:
+        with open(md_path, "w") as f:
+            f.write("\n".join(lines))
     print("\n".join(lines))
 
 
-def trace_summary(db_path, md_path, title, command):
+def trace_summary(db_path, md_path, title, command, append=False):
     """Per-kernel call counts and durations from a rocprofv3 kernel-trace
     database (its `top_kernels` view), as a markdown table."""
     import sqlite3
@@ -156,8 +163,14 @@ def trace_summary(db_path, md_path, title, command):
         short = short.split("(")[0][:90]
         lines.append(f"| `{short}` | {calls} | {total:.1f} | {avg:.3f} | {pct:.2f} |")
     lines.append("")
-    with open(md_path, "w") as f:
-        f.write("\n".join(lines))
+    if append and os.path.exists(md_path):
+        # one section per launch configuration in the same file
+        lines[0] = "#" + lines[0]
+        with open(md_path, "a") as f:
+            f.write("\n" + "\n".join(lines))
+    else:
+        with open(md_path, "w") as f:
+            f.write("\n".join(lines))
     print("\n".join(lines))
 
 
@@ -176,19 +189,22 @@ def main(argv=None):
     s.add_argument("--rows", type=int, required=True)
     s.add_argument("--md", required=True)
     s.add_argument("--dims", type=int, default=2)
+    s.add_argument("--append", action="store_true",
+                   help="add a section for this configuration to an existing summary")
     t = sub.add_parser("trace-summary")
     t.add_argument("--db", required=True)
     t.add_argument("--md", required=True)
     t.add_argument("--title", required=True)
     t.add_argument("--command", required=True)
+    t.add_argument("--append", action="store_true")
     a = ap.parse_args(argv)
     if a.cmd == "trace-summary":
-        trace_summary(a.db, a.md, a.title, a.command)
+        trace_summary(a.db, a.md, a.title, a.command, a.append)
         return 0
     if a.cmd == "run":
         run(a.depth, a.rows, a.blocks, a.dims)
     else:
-        summarise(a.fetch, a.write, a.depth, a.rows, a.md, a.dims)
+        summarise(a.fetch, a.write, a.depth, a.rows, a.md, a.dims, a.append)
     return 0
 
 

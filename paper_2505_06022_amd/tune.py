@@ -291,18 +291,33 @@ def sample_space(n_shapes: int, seed: int, per_shape: int, rng_seed: int, n_shap
 MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "costmodel.json")
 
 
-def launch_config(shape, nchunks, r2=0.25, model_path=MODEL_PATH):
-    """(T, tile rows, how) for a shape split into `nchunks` chunks: the
-    trained cost model's pick among the candidates with that many chunks,
-    or, without a model, the fastest of a quick autotuner sweep of them."""
-    cands = [c for c in candidates(shape) if c.nchunks == nchunks]
+def shortlist(shape, nchunks, k=3, model_path=MODEL_PATH):
+    """The trained cost model's k best candidates (by predicted time) for a
+    shape split into `nchunks` chunks, best first, as (T, tile rows) pairs."""
+    m = CostModel.load(model_path)
+    try:
+        cfgs = candidates(shape)
+        return [(cfgs[i].temporal_depth, cfgs[i].tile_rows)
+                for i in m.rank(shape, "time", nchunks=nchunks)[:k]]
+    finally:
+        m.close()
+
+
+def launch_config(shape, nchunks, r2=0.25, model_path=MODEL_PATH, verify=3):
+    """(T, tile rows, how) for a shape split into `nchunks` chunks.  With a
+    trained cost model: its `verify` best candidates, timed by the
+    autotuner, the fastest of them (verify = 1: the model's pick unmeasured).
+    Without a model: the fastest of a quick autotuner sweep of all
+    candidates with that many chunks."""
     if model_path and os.path.exists(model_path):
-        m = CostModel.load(model_path)
-        try:
-            c, _ = m.pick(shape, "time", nchunks=nchunks)
-        finally:
-            m.close()
-        return c.temporal_depth, c.tile_rows, "cost model"
+        top = shortlist(shape, nchunks, max(1, verify), model_path)
+        if len(top) == 1:
+            return top[0][0], top[0][1], "cost model"
+        cfgs = [make_tune_config(shape, nchunks, T, rows) for T, rows in top]
+        res = measure(cfgs, r2, reps=3, steps=48)
+        i = int(np.argmin([r["s_per_step"] for r in res]))
+        return top[i][0], top[i][1], f"cost model, fastest of its top {len(top)} measured"
+    cands = [c for c in candidates(shape) if c.nchunks == nchunks]
     res = measure(cands, r2, reps=3, steps=48)
     i = int(np.argmin([r["s_per_step"] for r in res]))
     return cands[i].temporal_depth, cands[i].tile_rows, "autotuner sweep"

@@ -271,11 +271,11 @@ def test_costmodel_features_host():
     s3 = ccl.ccl_wave_slots(3, 1)
     want3 = [math.log2(96), math.log2(768), math.log2(768), 1, math.log2(red3), 3, 5, 1,
              fill(waves3, s3), math.log2(1 + halo3), 12.0, math.log2(waves3)]
-    # 3D, T = 5: patches of 64 x 32 cells writing 48 x 22; chunks of 33, 33, 34 planes
+    # 3D, T = 5: 8-wave patches of 64 x 64 cells writing 48 x 54; chunks of 33, 33, 34 planes
     segs = [math.ceil(33 / 16), math.ceil(33 / 16), math.ceil(34 / 16)]
-    tiles = [s * math.ceil(300 / 48) * math.ceil(200 / 22) for s in segs]
-    waves3b = 4 * sum(tiles)
-    red3b = sum(t * (16 + 10) * 64 * 32 for t in tiles) / (100 * 200 * 300)
+    tiles = [s * math.ceil(300 / 48) * math.ceil(200 / 54) for s in segs]
+    waves3b = 8 * sum(tiles)
+    red3b = sum(t * (16 + 10) * 64 * 64 for t in tiles) / (100 * 200 * 300)
     halo3b = 2 * 2 * 9 * (4 * 200 * 300) * 2 / 5
     s3b = ccl.ccl_wave_slots(3, 5)
     want3b = [math.log2(100), math.log2(200), math.log2(300), 1, math.log2(red3b),

@@ -215,26 +215,27 @@ def cone_sample(u_prev, u_cur, r2, steps, point):
 
 def test_headline_share_full_size():
     """8192 x 8192 share of 32768 x 8192 at offset 8192, 1000 steps, 4 chunks,
-    in the launch configuration the benchmark times (the committed cost
-    model's pick, as bench.py takes it): bitwise equal to the unchunked T = 1
-    run everywhere, and to the oracle at sampled cells (corners, chunk
-    boundaries, centre)."""
+    in every launch configuration the benchmark may time (the committed cost
+    model's three best, of which bench.py times the fastest as measured):
+    bitwise equal to the unchunked T = 1 run everywhere, and to the oracle
+    at sampled cells (corners, chunk boundaries, centre)."""
     from paper_2505_06022_amd import tune
     w = synth.WORKLOADS["wave2d_8192_share_k4"]
-    T, rows, how = tune.launch_config(w["shape"], w["chunks"], w["r2"])
-    print(f"headline launch configuration: T={T}, tile rows={rows} ({how})")
     u0 = synth.gaussian_field(w["shape"], w["sigma"], w["seed"])
-    _, chunked = gpu_run(u0, u0, w["r2"], w["steps"], w["chunks"], T, tile_rows=rows,
-                         offset=w["share_offset"], buffer_range=w["global_shape"])
     _, plain = gpu_run(u0, u0, w["r2"], w["steps"], 1, 1, offset=w["share_offset"],
                        buffer_range=w["global_shape"])
-    assert np.all(np.isfinite(chunked))
-    assert np.array_equal(chunked, plain)
+    for T, rows in tune.shortlist(w["shape"], w["chunks"]):
+        print(f"headline launch configuration candidate: T={T}, tile rows={rows}")
+        _, chunked = gpu_run(u0, u0, w["r2"], w["steps"], w["chunks"], T, tile_rows=rows,
+                             offset=w["share_offset"], buffer_range=w["global_shape"])
+        assert np.all(np.isfinite(chunked))
+        assert np.array_equal(chunked, plain), f"T={T}, rows={rows} differs from T=1"
+        del chunked
     n = w["shape"][0]
     pts = [(0, 0), (n - 1, n - 1), (2047, 5), (2048, n - 3), (6143, 7), (n - 2, 1)]
     for p in pts:
         ref = cone_sample(u0, u0, w["r2"], w["steps"], p)
-        assert chunked[p] == ref, f"sample {p}: {chunked[p]!r} vs oracle {ref!r}"
+        assert plain[p] == ref, f"sample {p}: {plain[p]!r} vs oracle {ref!r}"
 
 
 # ---------------------------------------------------------------- 3D wave --
@@ -283,9 +284,9 @@ def test_wave3d_tile_planes():
 
 def test_wave3d_768_full_size():
     """768^3, r2 = 0.1, 8 z-slab chunks: 200 steps bitwise equal to the
-    unchunked run, also in the launch configuration the benchmark times for
-    it (the cost model's pick), and 8 steps bitwise equal to the oracle
-    everywhere."""
+    unchunked run, also in every launch configuration the benchmark may time
+    for it (the cost model's three best) and at T = 4, and 8 steps bitwise
+    equal to the oracle everywhere."""
     from paper_2505_06022_amd import tune
     w = synth.WORKLOADS["wave3d_768_k8"]
     u0 = synth.gaussian_field(w["shape"], w["sigma"], w["seed"])
@@ -297,14 +298,12 @@ def test_wave3d_768_full_size():
     _, b = gpu_run(u0, u0, w["r2"], w["steps"], 1, 1, fill=0.0)
     assert np.all(np.isfinite(a)) and np.array_equal(a, b)
     del b
-    T, planes, how = tune.launch_config(w["shape"], w["chunks"], w["r2"])
-    print(f"3D launch configuration: T={T}, tile planes={planes} ({how})")
-    _, c = gpu_run(u0, u0, w["r2"], w["steps"], w["chunks"], T, tile_rows=planes, fill=0.0)
-    assert np.array_equal(a, c), f"768^3: T={T}, planes={planes} differs from T=1"
-    if T != 4:
+    top = tune.shortlist(w["shape"], w["chunks"])
+    for T, planes in top + [(4, 0)] * all(T != 4 for T, _ in top):
+        print(f"3D launch configuration candidate: T={T}, tile planes={planes}")
+        _, c = gpu_run(u0, u0, w["r2"], w["steps"], w["chunks"], T, tile_rows=planes, fill=0.0)
+        assert np.array_equal(a, c), f"768^3: T={T}, planes={planes} differs from T=1"
         del c
-        _, c = gpu_run(u0, u0, w["r2"], w["steps"], w["chunks"], 4, fill=0.0)
-        assert np.array_equal(a, c), "768^3: T=4 differs from T=1"
 
 
 # ------------------------------------------------------------ measurement --

@@ -48,3 +48,74 @@ def test_steps_for():
     assert tune.steps_for((16384, 16384)) == 24
     assert tune.steps_for((256, 256)) == 960
     assert tune.steps_for((4096, 4096)) % 24 == 0
+
+
+def test_remeasure_replaces_one_family_in_place(tmp_path, monkeypatch):
+    """`learn remeasure` re-times only the chosen kernel family, keeps the
+    sample order and re-labels energy exactly where a label was held."""
+    import json
+    from paper_2505_06022_amd import learn
+    nan = float("nan")
+    keys = [((512, 512), 1, 4, 0), ((64, 96, 128), 2, 1, 0), ((64, 96, 128), 2, 5, 0),
+            ((64, 96, 128), 1, 3, 0), ((96, 64, 64), 4, 8, 0)]
+    samples = [dict(key=[list(k[0]), *k[1:]], steps=24, s_per_step=1.0, j_per_step=nan,
+                    s_per_cell_step=1.0, j_per_cell_step=nan, window_s=0.0) for k in keys]
+    samples[2]["j_per_cell_step"] = samples[2]["j_per_step"] = 5.0
+    samples[0]["j_per_cell_step"] = samples[0]["j_per_step"] = 7.0
+    doc = dict(samples=samples, features=[[0.0] * 12 for _ in keys], meta={})
+    (tmp_path / "samples.json").write_text(json.dumps(doc))
+    calls = []
+
+    def fake_measure(cfgs, energy_window_s=0.0, **kw):
+        calls.append(([tune.cfg_key(c) for c in cfgs], energy_window_s))
+        return [dict(key=tune.cfg_key(c), steps=24, s_per_step=2.0, j_per_step=3.0 if
+                     energy_window_s else nan, s_per_cell_step=2.0,
+                     j_per_cell_step=3.0 if energy_window_s else nan, window_s=energy_window_s)
+                for c in cfgs]
+
+    monkeypatch.setattr(tune, "measure", fake_measure)
+    learn.remeasure(str(tmp_path), dims=3, min_depth=2, window_s=0.5)
+    out = json.loads((tmp_path / "samples.json").read_text())
+    got = [tuple([tuple(s["key"][0]), *s["key"][1:]]) for s in out["samples"]]
+    assert got == keys
+    t = [s["s_per_step"] for s in out["samples"]]
+    assert t == [1.0, 1.0, 2.0, 2.0, 2.0]
+    e = [s["j_per_cell_step"] for s in out["samples"]]
+    assert e[0] == 7.0 and e[2] == 3.0 and all(np.isnan(e[j]) for j in (1, 3, 4))
+    assert [w for _, w in calls].count(0.5) == 1
+    assert out["features"][0] == [0.0] * 12 and out["features"][2] != [0.0] * 12
+    assert out["meta"]["remeasured"]["samples"] == 3
+
+
+def test_traffic_summary_sections(tmp_path):
+    """Counter summaries of several launch configs share one file; the
+    bench finds the section of the config it timed."""
+    import csv
+    import bench
+    from paper_2505_06022_amd import profile_run as pr
+
+    def fake_csv(path, counter, stencil_kib):
+        with open(path, "w", newline="") as f:
+            w = csv.DictWriter(f, ["Kernel_Name", "Counter_Name", "Counter_Value"])
+            w.writeheader()
+            for v in stencil_kib:
+                w.writerow(dict(Kernel_Name="void ccl::wave2d_kernel<8, false>(W2Args)",
+                                Counter_Name=counter, Counter_Value=v))
+            # the SAXPY counted at 4 B per element for both counters: half
+            # its 8 B read (scale 2), all of its 4 B written (scale 1)
+            sx = 4.0 * pr.SAXPY_N / 1024.0
+            w.writerow(dict(Kernel_Name="saxpy_kernel", Counter_Name=counter, Counter_Value=sx))
+
+    md = tmp_path / "traffic.md"
+    for rows, (fk, wk) in ((0, (1000.0, 2000.0)), (32, (1500.0, 2500.0))):
+        fc, wc = tmp_path / f"f{rows}.csv", tmp_path / f"w{rows}.csv"
+        fake_csv(fc, "FETCH_SIZE", [9e9, fk, fk])
+        fake_csv(wc, "WRITE_SIZE", [9e9, wk, wk])
+        pr.summarise(str(fc), str(wc), 8, rows, str(md), dims=2, append=True)
+    text = md.read_text()
+    assert text.count("traffic-json: ") == 2 and text.startswith("# ")
+    assert "\n## HBM traffic" in text
+    # fetch doubled by the SAXPY's factor, the first (cold) dispatch left out
+    assert bench.load_traffic(8, 0, str(md)) == int(round((2 * 1000.0 + 2000.0) * 1024))
+    assert bench.load_traffic(8, 32, str(md)) == int(round((2 * 1500.0 + 2500.0) * 1024))
+    assert bench.load_traffic(8, 64, str(md)) is None
