@@ -37,6 +37,7 @@ constexpr int kPrefetch = 3;
 constexpr int kUnroll = CCL_W2_UNROLL;
 static_assert(kUnroll % kPrefetch == 0, "the unrolled body must be whole ring turns");
 
+
 // Overlap columns per side and output columns per strip for depth T.
 __host__ __device__ constexpr int overlap(int T) { return 4 * ((T + 3) / 4); }
 __host__ __device__ constexpr int strip_width(int T) { return 256 - 2 * overlap(T); }
@@ -233,10 +234,38 @@ __device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, floa
     q0[u] = load4<true>(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch, row_p(first + u - 1), xgp);
   }
 
+  // Stores are issued one loop iteration late.  One counter tracks both
+  // loads and stores on this target, and stores and loads may complete out
+  // of order, so the compiler's wait for a load at the loop head also waits
+  // for every store issued before it; a store issued at the top of the
+  // previous iteration has had a whole iteration of arithmetic to complete
+  // (measured: +7-8% at T = 8 on an 8192 x 8192 share).  Issuing the next
+  // iteration's loads at its top as well was slower than this alone.  The
+  // in-place T = 1 update keeps its stores in place.
+  constexpr bool DEFER = !IN_PLACE;
+  // level-T rows of the previous iteration (u^{n+T}, u^{n+T-1}) and whether
+  // each lies in the tile's output rows (wave-uniform)
+  float4 d1[kUnroll], d0[kUnroll];
+  bool dok[kUnroll];
+#pragma unroll
+  for (int uu = 0; uu < kUnroll; ++uu) dok[uu] = false;
+  int jlast = 0;
+
   // kUnroll rows per loop iteration (a multiple of the ring length): the
-  // compiler waits for all outstanding loads once per iteration, at the
-  // loop head, so a longer body exposes that latency less often
+  // compiler waits for all outstanding memory operations once per
+  // iteration, at the loop head, so a longer body exposes that latency
+  // less often
   for (int jb = 0; jb < nrows; jb += kUnroll) {
+    if constexpr (DEFER) {
+#pragma unroll
+      for (int uu = 0; uu < kUnroll; ++uu) {
+        if (dok[uu]) {
+          const int r = first + jb - kUnroll + uu - T;
+          store4(C.out_cur, C.oc_y0, C.oc_x0, C.oc_pitch, r, xl, out, d1[uu]);
+          store4(C.out_prev, C.op_y0, C.op_x0, C.op_pitch, r, xl, out, d0[uu]);
+        }
+      }
+    }
 #pragma unroll
     for (int uu = 0; uu < kUnroll; ++uu) {
       const int u = uu % kPrefetch;
@@ -256,11 +285,26 @@ __device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, floa
         if (k < T) {
           pv = ring[k - 1][OLD];
           ring[k < T ? k : 0][NEW] = nv;
+        } else if constexpr (DEFER) {
+          dok[uu] = r >= y0 && r < y1;
+          d1[uu] = nv;
+          d0[uu] = ring[T - 1][MID];
         } else if (r >= y0 && r < y1) {
           store4(C.out_cur, C.oc_y0, C.oc_x0, C.oc_pitch, r, xl, out, nv);
           if (!IN_PLACE)
             store4(C.out_prev, C.op_y0, C.op_x0, C.op_pitch, r, xl, out, ring[T - 1][MID]);
         }
+      }
+    }
+    jlast = jb;
+  }
+  if constexpr (DEFER) {
+#pragma unroll
+    for (int uu = 0; uu < kUnroll; ++uu) {
+      if (dok[uu]) {
+        const int r = first + jlast + uu - T;
+        store4(C.out_cur, C.oc_y0, C.oc_x0, C.oc_pitch, r, xl, out, d1[uu]);
+        store4(C.out_prev, C.op_y0, C.op_x0, C.op_pitch, r, xl, out, d0[uu]);
       }
     }
   }

@@ -278,14 +278,15 @@ def evaluate(model_path, out_dir, n_shapes=200, start=0, count=None, budget_s=1e
     return rows
 
 
-def energy_check(model_path, out_dir, n_shapes=200, count=4, window_s=1.0, top=3, repeats=2):
+def energy_check(model_path, out_dir, n_shapes=200, count=4, window_s=1.0, top=3, repeats=3):
     """For the first held-out shapes: device energy of the model's energy
     pick and of the `top` fastest configs of the time sweep (the energy
     judge is restricted to those, since a full energy sweep would need ~2 s
-    of counter time per candidate).  Each config's energy is the mean over
+    of counter time per candidate).  Each config's energy is the median over
     `repeats` windows with a valid reading: one window reads the ~1 Hz
-    counter at two updates only, and a single misplaced update can shift it
-    by tens of percent."""
+    counter at two updates only, and now and then a window reads a third
+    to two thirds of what the windows around it read; the median of three
+    discards one such reading."""
     from . import tune
     import synth
     shapes = synth.cost_model_shapes(n_shapes, HELD_OUT_SEED)[:count]
@@ -306,7 +307,7 @@ def energy_check(model_path, out_dir, n_shapes=200, count=4, window_s=1.0, top=3
                 v = m["j_per_step"]
                 if v is not None and np.isfinite(v) and v > 0:
                     reads[j].append(v)
-        e = {j: float(np.mean(v)) for j, v in reads.items() if v}
+        e = {j: float(np.median(v)) for j, v in reads.items() if v}
         if pick not in e:
             _log(f"  energy {sh}: no valid energy window for the pick; shape skipped")
             continue
@@ -404,7 +405,7 @@ def main(argv=None):
     ec.add_argument("--model", required=True)
     ec.add_argument("--out", required=True)
     ec.add_argument("--count", type=int, default=4)
-    ec.add_argument("--repeats", type=int, default=2)
+    ec.add_argument("--repeats", type=int, default=3)
     sm = sub.add_parser("summarise")
     sm.add_argument("--out", required=True)
     sm.add_argument("--model", default=None)
