@@ -156,12 +156,15 @@ def test_chunked_ragged_all_depths(T):
         assert_bitwise(gc, ref, f"K={K} T={T}")
 
 
-@pytest.mark.parametrize("tile_rows", [8, 16, 33, 1000])
+@pytest.mark.parametrize("tile_rows", [1, 2, 5, 8, 16, 33, 1000])
 def test_tile_rows_invariance(tile_rows):
+    """Tiles of every height, down to one row: segments shorter than the
+    kernel's three-row loop body and row counts (rows + 2T) that are not a
+    multiple of three, so the rows stored after the loop are exercised."""
     shape = (200, 300)
     u0 = synth.gaussian_field(shape, 12.0, seed=9)
     _, ref = oracle.wave(u0.copy(), u0, 0.25, 24)
-    for T in (1, 3, 6):
+    for T in (1, 3, 6, 7, 8):
         _, gc = gpu_run(u0, u0, 0.25, 24, 3, T, tile_rows=tile_rows)
         assert_bitwise(gc, ref, f"tile_rows={tile_rows} T={T}")
 
