@@ -230,20 +230,32 @@ def train(data_path, model_path, epochs=4000, lr=3e-3, seed=0, seeds=1, val_frac
     return m
 
 
+def held_out_shapes(n_shapes, dims=2):
+    """Seeded held-out shapes: 2D as the training shapes' distribution, 3D
+    with sides 64..768; seeds that no training set uses."""
+    import synth
+    if dims == 2:
+        return synth.cost_model_shapes(n_shapes, HELD_OUT_SEED)
+    return synth.cost_model_shapes_3d(n_shapes, HELD_OUT_SEED + 100)
+
+
+def _tag(dims):
+    return "" if dims == 2 else "_3d"
+
+
 def evaluate(model_path, out_dir, n_shapes=200, start=0, count=None, budget_s=1e9,
-             reps=2, target_cell_steps=1.5e9):
+             reps=2, target_cell_steps=1.5e9, dims=2):
     """Exhaustive time sweep of held-out shapes [start, start+count): every
-    candidate measured; rows written to evaluation_part_<start>.json."""
+    candidate measured; rows written to evaluation[_3d]_part_<start>.json."""
     from . import tune
     os.makedirs(out_dir, exist_ok=True)
-    import synth
-    shapes = synth.cost_model_shapes(n_shapes, HELD_OUT_SEED)
+    shapes = held_out_shapes(n_shapes, dims)
     count = len(shapes) - start if count is None else count
     model = tune.CostModel.load(model_path)
     untrained = tune.CostModel(tune.CostModel.init_params(1), model.xs, model.ys)
     rows = []
     t0 = time.perf_counter()
-    path = os.path.join(out_dir, f"evaluation_part_{start:04d}.json")
+    path = os.path.join(out_dir, f"evaluation{_tag(dims)}_part_{start:04d}.json")
     for i, sh in enumerate(shapes[start:start + count]):
         cfgs = tune.candidates(sh)
         res = tune.measure(cfgs, reps=reps,
@@ -324,12 +336,12 @@ def energy_check(model_path, out_dir, n_shapes=200, count=4, window_s=1.0, top=3
     return out
 
 
-def summarise(out_dir, model_path=None):
-    """Merges evaluation parts into evaluation.json with the summary (also
-    stored in the model's metadata when `model_path` is given)."""
+def summarise(out_dir, model_path=None, dims=2):
+    """Merges evaluation parts into evaluation[_3d].json with the summary
+    (also stored in the model's metadata when `model_path` is given)."""
     import glob
     rows = []
-    for p in sorted(glob.glob(os.path.join(out_dir, "evaluation_part_*.json"))):
+    for p in sorted(glob.glob(os.path.join(out_dir, f"evaluation{_tag(dims)}_part_*.json"))):
         with open(p) as f:
             rows.extend(json.load(f))
     seen = {}
@@ -349,17 +361,17 @@ def summarise(out_dir, model_path=None):
                                                frac_within_5pct=float(np.mean(rk <= 1.05)),
                                                worst=float(rk.max()))
     ep = os.path.join(out_dir, "energy_check.json")
-    if os.path.exists(ep):
+    if dims == 2 and os.path.exists(ep):
         with open(ep) as f:
             er = json.load(f)
         summary["energy"] = dict(shapes=len(er), geomean_pick_over_best=gm([r["ratio"] for r in er]),
                                  frac_within_5pct=float(np.mean([r["ratio"] <= 1.05 for r in er])))
-    with open(os.path.join(out_dir, "evaluation.json"), "w") as f:
+    with open(os.path.join(out_dir, f"evaluation{_tag(dims)}.json"), "w") as f:
         json.dump(dict(summary=summary, rows=rows), f)
     if model_path:
         with open(model_path) as f:
             doc = json.load(f)
-        doc.setdefault("meta", {})["evaluation"] = summary
+        doc.setdefault("meta", {})[f"evaluation{_tag(dims)}"] = summary
         with open(model_path, "w") as f:
             json.dump(doc, f)
     _log(json.dumps(summary))
@@ -401,6 +413,7 @@ def main(argv=None):
     e.add_argument("--start", type=int, default=0)
     e.add_argument("--count", type=int, default=None)
     e.add_argument("--budget", type=float, default=1e9)
+    e.add_argument("--dims", type=int, default=2, choices=(2, 3))
     ec = sub.add_parser("energy-check")
     ec.add_argument("--model", required=True)
     ec.add_argument("--out", required=True)
@@ -409,6 +422,7 @@ def main(argv=None):
     sm = sub.add_parser("summarise")
     sm.add_argument("--out", required=True)
     sm.add_argument("--model", default=None)
+    sm.add_argument("--dims", type=int, default=2, choices=(2, 3))
     a = ap.parse_args(argv)
     if a.cmd != "summarise":
         import torch
@@ -423,11 +437,11 @@ def main(argv=None):
     elif a.cmd == "train":
         train(a.data, a.model, a.epochs, a.lr, seeds=a.seeds)
     elif a.cmd == "evaluate":
-        evaluate(a.model, a.out, a.shapes, a.start, a.count, a.budget)
+        evaluate(a.model, a.out, a.shapes, a.start, a.count, a.budget, dims=a.dims)
     elif a.cmd == "energy-check":
         energy_check(a.model, a.out, count=a.count, repeats=a.repeats)
     else:
-        summarise(a.out, a.model)
+        summarise(a.out, a.model, a.dims)
     return 0
 
 

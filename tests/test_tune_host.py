@@ -119,3 +119,11 @@ def test_traffic_summary_sections(tmp_path):
     assert bench.load_traffic(8, 0, str(md)) == int(round((2 * 1000.0 + 2000.0) * 1024))
     assert bench.load_traffic(8, 32, str(md)) == int(round((2 * 1500.0 + 2500.0) * 1024))
     assert bench.load_traffic(8, 64, str(md)) is None
+
+
+def test_held_out_3d_shapes_are_not_trained_on():
+    from paper_2505_06022_amd import learn
+    trained, _ = tune.sample_space(250, learn.TRAIN_SHAPE_SEED, 1, 0, 40, 40)
+    held = learn.held_out_shapes(40, dims=3)
+    assert len(held) == 40 and all(len(s) == 3 for s in held)
+    assert len(set(held) & set(trained)) <= 2
