@@ -333,10 +333,6 @@ def main():
     name = "wave2d_8192_share_k4"
     w = synth.WORKLOADS[name]
     depth, rows, how = pick_config(w, args)
-    if args.depth:
-        depth = args.depth
-    if args.tile_rows:
-        rows = args.tile_rows
     log(f"workload {name}: T={depth}, tile rows={rows} ({how}); generating input")
     u0 = synth.gaussian_field(w["shape"], w["sigma"], w["seed"])
     cw = ChunkedWave(w["share_offset"], w["shape"], w["chunks"], w["r2"], depth=depth,
