@@ -131,8 +131,11 @@ __device__ __forceinline__ int clamp_group(int xl, int x0, int x1, int bx0) {
 // the buffer holds (clamped into the loadable box), so the load needs no
 // branch and stays in flight until its value is used; cells outside the box
 // are zeroed later by mask4, where the value is consumed.  STREAM marks
-// data read once (u^{n-1}): a nontemporal load keeps it from displacing the
-// u^n rows that neighbouring tiles re-read from cache.
+// data read once: u^{n-1} in the in-place T = 1 update, where a
+// nontemporal load keeps it from displacing the u^n rows that neighbouring
+// tiles re-read from cache (15% faster than a cached load).  For T > 1 the
+// u^{n-1} rows in the overlap of vertically adjacent segments are read
+// twice too, and a cached load is 1-2% faster at T = 7, 8.
 template <bool STREAM>
 __device__ __forceinline__ float4 load4(const float *base, int32_t by0, int32_t bx0,
                                         int32_t pitch, int row, int xg) {
@@ -231,7 +234,7 @@ __device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, floa
 #pragma unroll
   for (int u = 0; u < kPrefetch; ++u) {
     q1[u] = load4<false>(C.in_cur, C.ic_y0, C.ic_x0, C.ic_pitch, row_c(first + u), xgc);
-    q0[u] = load4<true>(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch, row_p(first + u - 1), xgp);
+    q0[u] = load4<IN_PLACE>(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch, row_p(first + u - 1), xgp);
   }
 
   // Stores are issued one loop iteration late.  One counter tracks both
@@ -274,7 +277,7 @@ __device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, floa
       ring[0][NEW] = mask4(q1[u], i >= C.lc_y0 && i < C.lc_y1, lc);
       float4 pv = mask4(q0[u], i - 1 >= lpy0 && i - 1 < lpy1, lp);
       q1[u] = load4<false>(C.in_cur, C.ic_y0, C.ic_x0, C.ic_pitch, row_c(i + kPrefetch), xgc);
-      q0[u] = load4<true>(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch, row_p(i + kPrefetch - 1),
+      q0[u] = load4<IN_PLACE>(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch, row_p(i + kPrefetch - 1),
                           xgp);
 #pragma unroll
       for (int k = 1; k <= T; ++k) {
