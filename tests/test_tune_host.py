@@ -127,3 +127,41 @@ def test_held_out_3d_shapes_are_not_trained_on():
     held = learn.held_out_shapes(40, dims=3)
     assert len(held) == 40 and all(len(s) == 3 for s in held)
     assert len(set(held) & set(trained)) <= 2
+
+
+def test_launch_config_takes_fastest_of_shortlist(tmp_path, monkeypatch):
+    """With a model, the launcher times the model's shortlist and returns the
+    fastest; verify = 1 returns the model's pick without measuring."""
+    model = tmp_path / "m.json"
+    model.write_text("{}")
+    monkeypatch.setattr(tune, "shortlist", lambda shape, K, k, path: [(8, 32), (8, 0), (7, 64)][:k])
+    times = {(8, 32): 3.0, (8, 0): 2.0, (7, 64): 2.5}
+    seen = []
+
+    def fake_measure(cfgs, r2, reps=3, steps=None, **kw):
+        seen.append([(c.temporal_depth, c.tile_rows) for c in cfgs])
+        return [dict(s_per_step=times[(c.temporal_depth, c.tile_rows)]) for c in cfgs]
+
+    monkeypatch.setattr(tune, "measure", fake_measure)
+    T, rows, how = tune.launch_config((8192, 8192), 4, 0.25, str(model))
+    assert (T, rows) == (8, 0) and "top 3" in how
+    assert seen == [[(8, 32), (8, 0), (7, 64)]]
+    T, rows, how = tune.launch_config((8192, 8192), 4, 0.25, str(model), verify=1)
+    assert (T, rows, how) == (8, 32, "cost model") and len(seen) == 1
+
+
+def test_summarise_3d_parts(tmp_path):
+    """The 3D evaluation parts merge into evaluation_3d.json and the model's
+    `evaluation_3d` metadata, apart from the 2D summary."""
+    import json
+    from paper_2505_06022_amd import learn
+    rows = [dict(index=i, shape=[64, 64, 64], ratio=r, ratio_default=3.0, ratio_untrained=4.0,
+                 ratio_top3=1.0, ratio_top5=1.0) for i, r in enumerate((1.0, 1.21, 1.0, 1.02))]
+    (tmp_path / "evaluation_3d_part_0000.json").write_text(json.dumps(rows))
+    (tmp_path / "m.json").write_text(json.dumps(dict(meta=dict(evaluation=dict(shapes=200)))))
+    s = learn.summarise(str(tmp_path), str(tmp_path / "m.json"), dims=3)
+    assert s["shapes"] == 4 and np.isclose(s["frac_within_5pct"], 0.75)
+    assert np.isclose(s["geomean_pick_over_best"], (1.21 * 1.02) ** 0.25)
+    meta = json.loads((tmp_path / "m.json").read_text())["meta"]
+    assert meta["evaluation"] == dict(shapes=200) and meta["evaluation_3d"]["shapes"] == 4
+    assert (tmp_path / "evaluation_3d.json").exists() and not (tmp_path / "evaluation.json").exists()
