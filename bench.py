@@ -55,35 +55,86 @@ def load_traffic(depth: int, rows: int, path: str | None = None):
     return None
 
 
+def host_cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo) and logical CPU count."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{name}, {os.cpu_count()} logical CPUs visible"
+
+
+def _oracle_rate(u_prev, u_cur, r2, steps, threads, seconds):
+    """Mcells/s of the oracle stepping (u_prev, u_cur): `steps` steps when they
+    fit in about `seconds`, else as many as fit; repeated while time is left
+    (at most 5 runs).  Returns (Mcells/s, steps per run, runs, seconds)."""
+    import numpy as np
+
+    import oracle
+    oracle.wave(u_prev, u_cur, r2, 2, threads=threads)  # page in, spin up threads
+    t0 = time.perf_counter()
+    oracle.wave(u_prev, u_cur, r2, 10, threads=threads)
+    per_step = max((time.perf_counter() - t0) / 10, 1e-6)
+    n = int(max(10, min(steps, seconds / per_step)))
+    runs, dt = 0, 0.0
+    while runs < 5 and (runs == 0 or dt < seconds):
+        t0 = time.perf_counter()
+        oracle.wave(u_prev, u_cur, r2, n, threads=threads)
+        dt += time.perf_counter() - t0
+        runs += 1
+    return float(np.prod(u_cur.shape)) * n * runs / dt / 1e6, n, runs, dt
+
+
 def cpu_baseline(w, seconds: float = 12.0):
-    """The float32 oracle on the host cores over a bounded sample of the
-    workload: runs of the 8192 x 8192 share (the whole workload's 1000 steps
-    when they fit, else as many steps as fit) repeated until about `seconds`
-    of CPU time have passed."""
+    """The oracle on the host cores over bounded samples of the workloads.
+
+    `value`: the float32 oracle on the 8192 x 8192 share (the whole 1000
+    steps when they fit in about `seconds`, else as many steps as fit),
+    repeated while time is left.  Beside it, shorter samples of the float64
+    oracle on the same share, of the float32 oracle on the 768^3 workload,
+    and of the float32 oracle on grids of the 64-grid batch."""
     import numpy as np
 
     import oracle
     import synth
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or oracle.max_threads()
     u0 = synth.gaussian_field(w["shape"], w["sigma"], w["seed"])
-    oracle.wave(u0.copy(), u0, w["r2"], 2, threads=threads)  # page in, spin up threads
-    t0 = time.perf_counter()
-    oracle.wave(u0.copy(), u0, w["r2"], 20, threads=threads)
-    per_step = max((time.perf_counter() - t0) / 20, 1e-5)
-    steps = int(max(20, min(w["steps"], seconds / per_step)))
-    runs, dt = 0, 0.0
-    while runs < 5 and (runs == 0 or dt < seconds):
-        t0 = time.perf_counter()
-        oracle.wave(u0.copy(), u0, w["r2"], steps, threads=threads)
-        dt += time.perf_counter() - t0
-        runs += 1
-    cells = int(np.prod(w["shape"]))
-    what = ("the whole workload" if steps == w["steps"] else
-            f"{steps} of the workload's {w['steps']} steps")
-    return {"value": round(cells * steps * runs / dt / 1e6, 1), "unit": "Mcells/s",
-            "cores": threads, "kind": "oracle",
-            "sample": f"float32 oracle, {w['shape'][0]}x{w['shape'][1]} share, {what} "
-                      f"x {runs}, {dt:.1f} s on {threads} host threads"}
+    rate, n, runs, dt = _oracle_rate(u0.copy(), u0, w["r2"], w["steps"], threads, seconds)
+    what = ("the whole workload" if n == w["steps"] else
+            f"{n} of the workload's {w['steps']} steps")
+    out = {"value": round(rate, 1), "unit": "Mcells/s", "cores": threads, "kind": "oracle",
+           "host_cpu": host_cpu_model(),
+           "sample": f"float32 oracle, {w['shape'][0]}x{w['shape'][1]} share, {what} "
+                     f"x {runs}, {dt:.1f} s on {threads} host threads"}
+    u64 = u0.astype(np.float64)
+    rate, n, runs, dt = _oracle_rate(u64.copy(), u64, w["r2"], w["steps"], threads, 4.0)
+    out["fp64_share"] = {"mcells": round(rate, 1),
+                         "sample": f"float64 oracle, same share, {n} steps x {runs}, "
+                                   f"{dt:.1f} s"}
+    del u0, u64
+    w3 = synth.WORKLOADS["wave3d_768_k8"]
+    v0 = synth.gaussian_field(w3["shape"], w3["sigma"], w3["seed"])
+    rate, n, runs, dt = _oracle_rate(v0.copy(), v0, w3["r2"], w3["steps"], threads, 4.0)
+    out["wave3d_768"] = {"mcells": round(rate, 1),
+                         "sample": f"float32 oracle, 768^3, {n} of 200 steps x {runs}, "
+                                   f"{dt:.1f} s"}
+    del v0
+    # the batch: its first 8 grids, each for its own step count when it fits
+    cells_steps, t_total = 0.0, 0.0
+    for d in synth.batched_grids()[:8]:
+        g0 = synth.gaussian_field((d["ny"], d["nx"]), d["sigma"], d["seed"])
+        rate, n, runs, dt = _oracle_rate(g0.copy(), g0, 0.25, d["steps"], threads, 0.5)
+        cells_steps += d["ny"] * d["nx"] * n * runs
+        t_total += dt
+    out["batched_64"] = {"mcells": round(cells_steps / t_total / 1e6, 1),
+                         "sample": f"float32 oracle, the batch's first 8 grids, "
+                                   f"{t_total:.1f} s"}
+    return out
 
 
 def saxpy_calibration(n: int = 1 << 28, reps: int = 10):
@@ -135,7 +186,7 @@ def pick_config(w, args):
     if args.depth:
         return args.depth, args.tile_rows, "given"
     from paper_2505_06022_amd import tune
-    return tune.launch_config(w["shape"], w["chunks"], w["r2"],
+    return tune.launch_config(w["shape"], w["chunks"], w["steps"], w["r2"],
                               model_path=None if args.sweep else MODEL_PATH)
 
 
@@ -159,8 +210,11 @@ def batched_forms(log_energy=False):
       picked by the cost model, else T=4; tile rows sized by the batch);
     * batched_per_grid: one graph launch holding every grid's own
       ccl_wave_step sequence (the cost model's depth and rows per grid);
-    * per_grid_loop: a loop of plain T=1 ccl_wave_step calls."""
-    import numpy as np
+    * per_grid_learned_loop: a host loop of ordinary ccl_wave_step calls, one
+      per grid, with the same per-grid depth and rows and no graph (the same
+      work as batched_per_grid, launched one call at a time: the gain of the
+      graph launch over it is the gain of batching itself);
+    * per_grid_loop: a host loop of plain T=1 ccl_wave_step calls."""
     import torch
 
     import paper_2505_06022_amd as ccl
@@ -168,21 +222,7 @@ def batched_forms(log_energy=False):
     from paper_2505_06022_amd import tune
     from paper_2505_06022_amd.fields import BatchedWaves, ChunkedWave
     grids = synth.batched_grids()
-    model = tune.CostModel.load(MODEL_PATH) if os.path.exists(MODEL_PATH) else None
-    specs, specs_pg = [], []
-    for d in grids:
-        depth, rows = 4, 64
-        if model is not None:
-            c, _ = model.pick((d["ny"], d["nx"]), "time", nchunks=1)
-            depth, rows = c.temporal_depth, c.tile_rows
-        base = dict(ny=d["ny"], nx=d["nx"], steps=d["steps"], r2=0.25, depth=depth)
-        # the persistent kernel sizes tiles for all grids at once (the
-        # model's row pick is for a grid launched alone); the per-grid form
-        # launches each grid alone, so it takes the model's rows
-        specs.append(dict(base, tile_rows=0 if model is not None else rows))
-        specs_pg.append(dict(base, tile_rows=rows))
-    if model is not None:
-        model.close()
+    specs, specs_pg, how = tune.batch_specs(grids, MODEL_PATH)
     cell_steps = sum(d["ny"] * d["nx"] * d["steps"] for d in grids)
 
     def run_batch(sp, flags):
@@ -208,44 +248,56 @@ def batched_forms(log_energy=False):
         torch.cuda.empty_cache()
         return t, p
 
+    def run_loop(depth_rows):
+        """A host loop of one ccl_wave_step call per grid (one chunk each)."""
+        cws = []
+        for g, d in enumerate(grids):
+            T, rows = depth_rows(g)
+            cw = ChunkedWave((0, 0), (d["ny"], d["nx"]), 1, 0.25, depth=T, tile_rows=rows)
+            u0 = synth.gaussian_field((d["ny"], d["nx"]), d["sigma"], d["seed"])
+            cw.scatter(u0, u0)
+            cws.append(cw)
+
+        def loop_once():
+            for cw, d in zip(cws, grids):
+                cw.step(d["steps"])
+
+        loop_once()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        reps = 2
+        a.record()
+        for _ in range(reps):
+            loop_once()
+        b.record()
+        torch.cuda.synchronize()
+        t = a.elapsed_time(b) * 1e-3 / reps
+        p = average_power(loop_once) if log_energy else None
+        del cws
+        torch.cuda.empty_cache()
+        return t, p
+
     t_batched, p_batched = run_batch(specs, 0)
     t_pg, p_pg = run_batch(specs_pg, ccl.CCL_BATCH_PER_GRID)
-    # per-grid loop of plain (T=1) calls on the same grids, same data
-    cws = []
-    for g, d in enumerate(grids):
-        cw = ChunkedWave((0, 0), (d["ny"], d["nx"]), 1, 0.25, depth=1)
-        u0 = synth.gaussian_field((d["ny"], d["nx"]), d["sigma"], d["seed"])
-        cw.scatter(u0, u0)
-        cws.append(cw)
-
-    def loop_once():
-        for cw, d in zip(cws, grids):
-            cw.step(d["steps"])
-
-    loop_once()
-    torch.cuda.synchronize()
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record()
-    loop_once()
-    b.record()
-    torch.cuda.synchronize()
-    t_loop = a.elapsed_time(b) * 1e-3
-    p_loop = average_power(loop_once) if log_energy else None
-    del cws
-    torch.cuda.empty_cache()
+    t_ll, p_ll = run_loop(lambda g: (specs_pg[g]["depth"], specs_pg[g]["tile_rows"]))
+    t_loop, p_loop = run_loop(lambda g: (1, 0))
     nj = lambda p, t: None if p is None else round(p * t / cell_steps * 1e9, 4)
     return {"grids": len(grids), "cell_steps": cell_steps,
             "batched_mcells": round(cell_steps / t_batched / 1e6, 1),
             "batched_ms": round(t_batched * 1e3, 3),
+            "batched_nj_per_cell_step": nj(p_batched, t_batched),
             "batched_per_grid_mcells": round(cell_steps / t_pg / 1e6, 1),
             "batched_per_grid_ms": round(t_pg * 1e3, 3),
             "batched_per_grid_nj_per_cell_step": nj(p_pg, t_pg),
+            "per_grid_learned_loop_mcells": round(cell_steps / t_ll / 1e6, 1),
+            "per_grid_learned_loop_ms": round(t_ll * 1e3, 3),
+            "per_grid_learned_loop_nj_per_cell_step": nj(p_ll, t_ll),
+            "batching_gain": round(t_ll / min(t_batched, t_pg), 4),
             "per_grid_loop_mcells": round(cell_steps / t_loop / 1e6, 1),
             "per_grid_loop_ms": round(t_loop * 1e3, 3),
-            "batched_nj_per_cell_step": nj(p_batched, t_batched),
             "per_grid_loop_nj_per_cell_step": nj(p_loop, t_loop),
-            "configs": "cost model" if model is not None else "T=4, 64 rows"}
+            "configs": how}
 
 
 def wave3d_forms(with_energy=False):
@@ -261,8 +313,10 @@ def wave3d_forms(with_energy=False):
     from paper_2505_06022_amd.fields import ChunkedWave
     w = synth.WORKLOADS["wave3d_768_k8"]
     shape = w["shape"]
+    # every candidate is timed over the workload's own step count, so a
+    # depth that does not divide it pays for its shorter last block
     cands = [c for c in tune.candidates(shape) if c.nchunks == w["chunks"]]
-    res = tune.measure(cands, w["r2"], reps=3, steps=20)
+    res = tune.measure(cands, w["r2"], reps=3, steps=w["steps"])
     swept = cands[int(np.argmin([r["s_per_step"] for r in res]))]
     learned = verified = None
     if os.path.exists(MODEL_PATH):
@@ -272,7 +326,7 @@ def wave3d_forms(with_energy=False):
         # (3 measurements instead of the sweep's len(cands))
         order = m.rank(shape, "time", nchunks=w["chunks"])[:3]
         allc = tune.candidates(shape)
-        vres = tune.measure([allc[i] for i in order], w["r2"], reps=3, steps=20)
+        vres = tune.measure([allc[i] for i in order], w["r2"], reps=3, steps=w["steps"])
         verified = allc[order[int(np.argmin([r["s_per_step"] for r in vres]))]]
         m.close()
     u0 = synth.gaussian_field(shape, w["sigma"], w["seed"])
@@ -297,6 +351,10 @@ def wave3d_forms(with_energy=False):
         out[name] = entry
         del cw
         torch.cuda.empty_cache()
+    for name in ("learned", "learned_top3_measured"):
+        if name in out:
+            out[name]["time_over_swept"] = round(out[name]["ms_per_run"] /
+                                                 out["swept"]["ms_per_run"], 4)
     return out
 
 

@@ -1,6 +1,9 @@
-// The per-cell update of the 3D seven-point leapfrog scheme (section 4.1,
-// the wave propagation benchmark), shared by the one-step and the
-// temporally blocked 3D kernels so that both produce bitwise equal values.
+// The per-cell update of the 3D seven-point leapfrog scheme, shared by the
+// one-step and the temporally blocked 3D kernels so that both produce
+// bitwise equal values.  The paper has no stencil of its own: the scheme is
+// the chunk kernel this library stands in for the paper's data-parallel
+// kernels (the second-order central-difference leapfrog for u_tt = c^2
+// lap u, with r2 = (c dt / dx)^2).
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -303,21 +303,55 @@ def shortlist(shape, nchunks, k=3, model_path=MODEL_PATH):
         m.close()
 
 
-def launch_config(shape, nchunks, r2=0.25, model_path=MODEL_PATH, verify=3):
-    """(T, tile rows, how) for a shape split into `nchunks` chunks.  With a
-    trained cost model: its `verify` best candidates, timed by the
-    autotuner, the fastest of them (verify = 1: the model's pick unmeasured).
-    Without a model: the fastest of a quick autotuner sweep of all
-    candidates with that many chunks."""
+def launch_config(shape, nchunks, steps, r2=0.25, model_path=MODEL_PATH, verify=3):
+    """(T, tile rows, how) for `steps` leapfrog steps of a shape split into
+    `nchunks` chunks.  With a trained cost model: its `verify` best
+    candidates, timed by the autotuner, the fastest of them (verify = 1: the
+    model's pick unmeasured).  Without a model: the fastest of an autotuner
+    sweep of all candidates with that many chunks.  Candidates are timed over
+    the workload's own step count, so a depth whose last block is shorter
+    (steps not a multiple of T) is charged for it as the workload will be."""
     if model_path and os.path.exists(model_path):
         top = shortlist(shape, nchunks, max(1, verify), model_path)
         if len(top) == 1:
             return top[0][0], top[0][1], "cost model"
         cfgs = [make_tune_config(shape, nchunks, T, rows) for T, rows in top]
-        res = measure(cfgs, r2, reps=3, steps=48)
+        res = measure(cfgs, r2, reps=3, steps=steps)
         i = int(np.argmin([r["s_per_step"] for r in res]))
         return top[i][0], top[i][1], f"cost model, fastest of its top {len(top)} measured"
     cands = [c for c in candidates(shape) if c.nchunks == nchunks]
-    res = measure(cands, r2, reps=3, steps=48)
+    res = measure(cands, r2, reps=3, steps=steps)
     i = int(np.argmin([r["s_per_step"] for r in res]))
     return cands[i].temporal_depth, cands[i].tile_rows, "autotuner sweep"
+
+
+def batch_specs(grids, model_path=MODEL_PATH, r2=0.25):
+    """Launch specs of a batch of independent 2D grids (dicts with ny, nx,
+    steps as ``synth.batched_grids`` gives them), as the batched forms run
+    them.  Returns (persistent, per_grid, how):
+
+    * persistent: specs for the persistent kernel, each grid's depth from
+      the cost model's time pick for the grid alone (one chunk), tile rows
+      left to the batch (0), which sizes tiles for all grids at once;
+    * per_grid: the same depths with the model's own rows, for forms that
+      launch each grid alone (CCL_BATCH_PER_GRID, a loop of ccl_wave_step
+      calls);
+    * how: what chose the configs.
+
+    Without a trained model every grid takes T = 4 with 64 rows."""
+    model = CostModel.load(model_path) if model_path and os.path.exists(model_path) else None
+    persistent, per_grid = [], []
+    try:
+        for d in grids:
+            depth, rows = 4, 64
+            if model is not None:
+                c, _ = model.pick((d["ny"], d["nx"]), "time", nchunks=1)
+                depth, rows = c.temporal_depth, c.tile_rows
+            base = dict(ny=int(d["ny"]), nx=int(d["nx"]), steps=int(d["steps"]), r2=r2,
+                        depth=int(depth))
+            persistent.append(dict(base, tile_rows=0 if model is not None else rows))
+            per_grid.append(dict(base, tile_rows=int(rows)))
+    finally:
+        if model is not None:
+            model.close()
+    return persistent, per_grid, ("cost model" if model is not None else "T=4, 64 rows")

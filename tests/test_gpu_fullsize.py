@@ -1,0 +1,218 @@
+"""Full-size parity: the measured workloads, every cell, against the oracle.
+
+Each workload is run through the C ABI exactly as the benchmark runs it
+(same shapes, offsets, chunk counts, step counts and launch configurations)
+and every cell of the final two levels u^n and u^{n-1} is compared with the
+float32 oracle, bitwise (the HIP path evaluates the same float32 expression in
+the same order; the 1e-5 relative max-abs bound is asserted as well).  The
+headline share is also compared with the float64 oracle: within 1e-4
+relative max-abs after its 1000 steps.
+
+* 8192 x 8192 share of a 32768 x 8192 domain, 1000 steps: unchunked T = 1,
+  4 chunks at T = 1 (the plain form) and the cost model's three best launch
+  configurations (the benchmark times the fastest of them as measured).
+* 768^3, 200 steps, 8 z-slab chunks: T = 1 chunked and unchunked, every
+  depth with automatic planes, the deep depths with 128-plane tiles (the
+  sweep's fastest in past measurements) and the cost model's three best.
+* The 64-grid batch (sides 512..4096, 100..500 steps), per-grid depth and
+  rows from the cost model as the benchmark builds them: the persistent
+  kernel, the per-grid graph (CCL_BATCH_PER_GRID) and a host loop of
+  ccl_wave_step calls at the same depth and rows; all 64 grids.
+
+Buffers start NaN-poisoned, so a read of anything the halo exchange did not
+fill shows up as a NaN.  The oracle runs once per workload (module-scoped
+fixtures, OpenMP over the host's cores).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    import paper_2505_06022_amd as ccl
+    ccl.lib()  # raises loudly if the library is missing
+    yield
+
+
+def rel_err(a, b):
+    return float(np.max(np.abs(a.astype(np.float64) - b.astype(np.float64))) /
+                 max(float(np.max(np.abs(b))), 1e-300))
+
+
+def assert_bitwise(got, ref, what):
+    assert got.shape == ref.shape, f"{what}: shape {got.shape} vs {ref.shape}"
+    assert np.all(np.isfinite(got)), f"{what}: non-finite values (stray halo read?)"
+    e = rel_err(got, ref)
+    assert e <= 1e-5, f"{what}: relative max-abs error {e:.3e} > 1e-5"
+    if not np.array_equal(got, ref):
+        n = int(np.count_nonzero(got != ref))
+        raise AssertionError(f"{what}: within 1e-5 ({e:.3e}) but {n} cells not bitwise equal")
+
+
+def run_chunked(w, u0, K, T, rows, fill=float("nan")):
+    from paper_2505_06022_amd.fields import ChunkedWave
+    print(f"run: {w['shape']} K={K} T={T} rows={rows}", flush=True)
+    cw = ChunkedWave(w["share_offset"], w["shape"], K, w["r2"], depth=T, tile_rows=rows,
+                     buffer_range=w.get("global_shape"), fill=fill)
+    cw.scatter(u0, u0)
+    cw.step(w["steps"])
+    torch.cuda.synchronize()
+    out = cw.gather("prev"), cw.gather("cur")
+    del cw
+    torch.cuda.empty_cache()
+    return out
+
+
+# ------------------------------------------------- 8192^2 share, 1000 steps --
+
+@pytest.fixture(scope="module")
+def share():
+    w = synth.WORKLOADS["wave2d_8192_share_k4"]
+    u0 = synth.gaussian_field(w["shape"], w["sigma"], w["seed"])
+    th = oracle.max_threads()
+    ref_p, ref_c = oracle.wave(u0.copy(), u0, w["r2"], w["steps"], threads=th)
+    u64 = u0.astype(np.float64)
+    _, ref64 = oracle.wave(u64.copy(), u64, w["r2"], w["steps"], threads=th)
+    del u64
+    return dict(w=w, u0=u0, ref_p=ref_p, ref_c=ref_c, ref64=ref64)
+
+
+def check_share(share, K, T, rows, what):
+    gp, gc = run_chunked(share["w"], share["u0"], K, T, rows)
+    assert_bitwise(gc, share["ref_c"], f"{what} u^1000")
+    assert_bitwise(gp, share["ref_p"], f"{what} u^999")
+    e64 = rel_err(gc, share["ref64"])
+    print(f"{what}: float64 oracle relative max-abs {e64:.3e}", flush=True)
+    assert e64 <= 1e-4, f"{what}: {e64:.3e} from the float64 oracle"
+
+
+@pytest.mark.parametrize("K", [1, 4])
+def test_share_plain_full_size(share, K):
+    """T = 1 (the plain form at K = 4, and unchunked)."""
+    check_share(share, K, 1, 0, f"share K={K} T=1")
+
+
+@pytest.mark.parametrize("i", [0, 1, 2])
+def test_share_learned_full_size(share, i):
+    """The cost model's i-th best launch configuration for the share (the
+    benchmark measures these three and times the fastest)."""
+    from paper_2505_06022_amd import tune
+    w = share["w"]
+    T, rows = tune.shortlist(w["shape"], w["chunks"])[i]
+    check_share(share, w["chunks"], T, rows, f"share K={w['chunks']} T={T} rows={rows}")
+
+
+# ------------------------------------------------------ 768^3, 200 steps --
+
+@pytest.fixture(scope="module")
+def cube():
+    w = synth.WORKLOADS["wave3d_768_k8"]
+    u0 = synth.gaussian_field(w["shape"], w["sigma"], w["seed"])
+    ref_p, ref_c = oracle.wave(u0.copy(), u0, w["r2"], w["steps"], threads=oracle.max_threads())
+    return dict(w=w, u0=u0, ref_p=ref_p, ref_c=ref_c)
+
+
+def check_cube(cube, K, T, rows):
+    what = f"768^3 K={K} T={T} planes={rows}"
+    gp, gc = run_chunked(cube["w"], cube["u0"], K, T, rows)
+    assert_bitwise(gc, cube["ref_c"], f"{what} u^200")
+    assert_bitwise(gp, cube["ref_p"], f"{what} u^199")
+    return gc
+
+
+def test_cube_plain_full_size(cube):
+    """T = 1 over 8 z-slabs, also against the float64 oracle."""
+    w = cube["w"]
+    gc = check_cube(cube, w["chunks"], 1, 0)
+    u64 = cube["u0"].astype(np.float64)
+    _, ref64 = oracle.wave(u64.copy(), u64, w["r2"], w["steps"], threads=oracle.max_threads())
+    del u64
+    e64 = rel_err(gc, ref64)
+    print(f"768^3 T=1: float64 oracle relative max-abs {e64:.3e}", flush=True)
+    assert e64 <= 1e-4
+
+
+def test_cube_unchunked_full_size(cube):
+    check_cube(cube, 1, 1, 0)
+
+
+@pytest.mark.parametrize("T,rows", [(T, 0) for T in range(2, 9)] +
+                         [(T, 128) for T in range(5, 9)])
+def test_cube_depths_full_size(cube, T, rows):
+    check_cube(cube, cube["w"]["chunks"], T, rows)
+
+
+@pytest.mark.parametrize("i", [0, 1, 2])
+def test_cube_learned_full_size(cube, i):
+    from paper_2505_06022_amd import tune
+    w = cube["w"]
+    T, rows = tune.shortlist(w["shape"], w["chunks"])[i]
+    check_cube(cube, w["chunks"], T, rows)
+
+
+# ------------------------------------------------------- the 64-grid batch --
+
+@pytest.fixture(scope="module")
+def batch():
+    from paper_2505_06022_amd import tune
+    grids = synth.batched_grids()
+    specs, specs_pg, how = tune.batch_specs(grids)
+    th = oracle.max_threads()
+    inputs, refs = [], []
+    for d in grids:
+        u0 = synth.gaussian_field((d["ny"], d["nx"]), d["sigma"], d["seed"])
+        inputs.append(u0)
+        refs.append(oracle.wave(u0.copy(), u0, 0.25, d["steps"], threads=th))
+    return dict(grids=grids, specs=specs, specs_pg=specs_pg, how=how, inputs=inputs, refs=refs)
+
+
+@pytest.mark.parametrize("mode", ["persistent", "per_grid"])
+def test_batched_workload_full(batch, mode):
+    """All 64 grids of one graph launch, in the configuration the benchmark
+    times, bitwise equal to the oracle (u^n and u^{n-1})."""
+    import paper_2505_06022_amd as ccl
+    from paper_2505_06022_amd.fields import BatchedWaves
+    specs, flags = ((batch["specs"], 0) if mode == "persistent" else
+                    (batch["specs_pg"], ccl.CCL_BATCH_PER_GRID))
+    print(f"batch mode {mode}, configs from {batch['how']}: depths "
+          f"{sorted(set(s['depth'] for s in specs))}", flush=True)
+    bw = BatchedWaves(specs, flags=flags, fill=float("nan"))
+    for g, u0 in enumerate(batch["inputs"]):
+        bw.scatter(g, u0, u0)
+    bw.run()
+    ccl.ccl_batch_check(bw.handle)
+    for g, (rp, rc) in enumerate(batch["refs"]):
+        assert_bitwise(bw.gather(g, "cur"), rc, f"{mode} grid {g} ({specs[g]}) u^n")
+        assert_bitwise(bw.gather(g, "prev"), rp, f"{mode} grid {g} u^(n-1)")
+    bw.close()
+    del bw
+    torch.cuda.empty_cache()
+
+
+def test_batched_workload_learned_loop(batch):
+    """The same grids as a host loop of ccl_wave_step calls (one chunk per
+    grid, the cost model's depth and rows): the like-for-like per-grid form
+    the benchmark compares the batched forms with."""
+    from paper_2505_06022_amd.fields import ChunkedWave
+    for g, (d, s) in enumerate(zip(batch["grids"], batch["specs_pg"])):
+        cw = ChunkedWave((0, 0), (d["ny"], d["nx"]), 1, 0.25, depth=s["depth"],
+                         tile_rows=s["tile_rows"], fill=float("nan"))
+        u0 = batch["inputs"][g]
+        cw.scatter(u0, u0)
+        cw.step(d["steps"])
+        torch.cuda.synchronize()
+        rp, rc = batch["refs"][g]
+        assert_bitwise(cw.gather("cur"), rc, f"loop grid {g} ({s}) u^n")
+        assert_bitwise(cw.gather("prev"), rp, f"loop grid {g} u^(n-1)")
+        del cw
+    torch.cuda.empty_cache()

@@ -130,8 +130,9 @@ def test_held_out_3d_shapes_are_not_trained_on():
 
 
 def test_launch_config_takes_fastest_of_shortlist(tmp_path, monkeypatch):
-    """With a model, the launcher times the model's shortlist and returns the
-    fastest; verify = 1 returns the model's pick without measuring."""
+    """With a model, the launcher times the model's shortlist over the
+    workload's own step count and returns the fastest; verify = 1 returns
+    the model's pick without measuring."""
     model = tmp_path / "m.json"
     model.write_text("{}")
     monkeypatch.setattr(tune, "shortlist", lambda shape, K, k, path: [(8, 32), (8, 0), (7, 64)][:k])
@@ -140,13 +141,14 @@ def test_launch_config_takes_fastest_of_shortlist(tmp_path, monkeypatch):
 
     def fake_measure(cfgs, r2, reps=3, steps=None, **kw):
         seen.append([(c.temporal_depth, c.tile_rows) for c in cfgs])
+        assert steps == 1000
         return [dict(s_per_step=times[(c.temporal_depth, c.tile_rows)]) for c in cfgs]
 
     monkeypatch.setattr(tune, "measure", fake_measure)
-    T, rows, how = tune.launch_config((8192, 8192), 4, 0.25, str(model))
+    T, rows, how = tune.launch_config((8192, 8192), 4, 1000, 0.25, str(model))
     assert (T, rows) == (8, 0) and "top 3" in how
     assert seen == [[(8, 32), (8, 0), (7, 64)]]
-    T, rows, how = tune.launch_config((8192, 8192), 4, 0.25, str(model), verify=1)
+    T, rows, how = tune.launch_config((8192, 8192), 4, 1000, 0.25, str(model), verify=1)
     assert (T, rows, how) == (8, 32, "cost model") and len(seen) == 1
 
 
