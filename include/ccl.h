@@ -80,19 +80,29 @@ typedef struct {
   int64_t global_range[CCL_MAX_DIMS];
 } ccl_chunk;
 
-/* Range mappers (section 3).  ONE_TO_ONE: the chunk touches exactly its own
- * indices (the mapper of the paper's second listing).  NEIGHBORHOOD: the
- * chunk grown by extent[d] on both sides of every dimension (a stencil's
- * read set).  ALL: the whole buffer. */
+/* Range mappers (section 3: the accessor's range mapper ties a chunk of the
+ * kernel's range to the data it touches).  ONE_TO_ONE: the chunk touches
+ * exactly its own indices (the mapper of the paper's second listing).
+ * NEIGHBORHOOD: the chunk grown by extent[d] on both sides of every
+ * dimension (a stencil's read set).  ALL: the whole buffer.  FIXED: the box
+ * [offset, offset + extent), whatever the chunk (data every chunk reads,
+ * such as a coefficient table).  SLICE: the chunk, taken whole along
+ * dimension `dim` (a row or column reduction's read set).  Every region is
+ * clipped to the buffer's index range. */
 typedef enum {
   CCL_MAP_ONE_TO_ONE = 0,
   CCL_MAP_NEIGHBORHOOD = 1,
-  CCL_MAP_ALL = 2
+  CCL_MAP_ALL = 2,
+  CCL_MAP_FIXED = 3,
+  CCL_MAP_SLICE = 4
 } ccl_mapper_kind;
 
 typedef struct {
-  int32_t kind;                   /* a ccl_mapper_kind                 */
-  int64_t extent[CCL_MAX_DIMS];   /* used by NEIGHBORHOOD, >= 0        */
+  int32_t kind;                   /* a ccl_mapper_kind                      */
+  int64_t extent[CCL_MAX_DIMS];   /* NEIGHBORHOOD: growth per side, >= 0;
+                                     FIXED: extent of the box, >= 0         */
+  int64_t offset[CCL_MAX_DIMS];   /* FIXED: first index of the box          */
+  int32_t dim;                    /* SLICE: the dimension taken whole       */
 } ccl_range_mapper;
 
 /* A chunk's slice of one buffer in device memory (caller-owned). */
@@ -139,11 +149,27 @@ const char *ccl_last_error(void);
 ccl_status ccl_split_range(const ccl_subrange *range, int32_t nchunks,
                            int32_t split_dim, ccl_chunk *chunks_out);
 
+/* Split a kernel range into a grid of chunks: counts[d] pieces along every
+ * dimension d (section 3: the kernel is split across the available devices;
+ * a block split keeps each chunk's halo short in every dimension).  Chunk
+ * (k_0, ..., k_{D-1}) covers, along each d, [o + floor(k_d n / K_d),
+ * o + floor((k_d + 1) n / K_d)) with o, n the range's offset and extent and
+ * K_d = counts[d]; chunks are numbered row-major over the grid (the last
+ * dimension fastest).  With one count above 1 this is ccl_split_range along
+ * that dimension.
+ *   counts     : range->dims entries, each >= 1
+ *   chunks_out : caller array of counts[0] * ... * counts[D-1] entries
+ * Errors: INVALID (NULL, dims, a count < 1), RANGE (a count larger than the
+ * extent along its dimension). */
+ccl_status ccl_split_grid(const ccl_subrange *range, const int32_t *counts,
+                          ccl_chunk *chunks_out);
+
 /* Region of a buffer that a chunk accesses through a range mapper (section
  * 3: the range mapper ties a chunk of the execution range to its data
- * requirements).  NEIGHBORHOOD and ALL are clipped to [0, buffer_range).
+ * requirements).  Every region is clipped to [0, buffer_range).
  *   buffer_range : extent of the (virtual) buffer, dims entries
- * Errors: INVALID (NULL, dims mismatch, unknown kind, negative extent). */
+ * Errors: INVALID (NULL, dims mismatch, unknown kind, negative extent, SLICE
+ * dim outside [0, dims)). */
 ccl_status ccl_region_of(const ccl_chunk *chunk, const ccl_range_mapper *mapper,
                          const int64_t *buffer_range, ccl_subrange *region_out);
 
@@ -231,6 +257,60 @@ ccl_status ccl_energy_read(int32_t device, void *hip_stream, double *joules,
  * (forced by CCL_ENERGY_BACKEND=fake, for host-only tests), "unsupported"
  * or "unprobed".  Static storage. */
 const char *ccl_energy_backend(int32_t device);
+
+/* ---- Generic chunked parallel_for ----------------------------------------
+ * One data-parallel function over the chunks of a kernel range, with
+ * accessors that carry a range mapper and an access mode: the paper's
+ * second listing (section 3), where SAXPY's three accessors use the
+ * one_to_one mapper, the kernel is split across the devices and the range
+ * mappers tell the runtime which transfers must precede each chunk. */
+enum {
+  CCL_ACCESS_READ = 1,
+  CCL_ACCESS_WRITE = 2,
+  CCL_ACCESS_READ_WRITE = 3
+};
+
+typedef struct {
+  ccl_range_mapper mapper;        /* chunk -> region of this buffer it touches */
+  int32_t mode;                   /* CCL_ACCESS_*                              */
+  int64_t buffer_range[CCL_MAX_DIMS]; /* the buffer's index range [0, range)   */
+  const ccl_chunk_buffer *bufs;   /* one float32 buffer per chunk (caller-owned
+                                     device memory); bufs[k].region holds chunk
+                                     k and region_of(chunk k, mapper)          */
+} ccl_accessor;
+
+enum {
+  CCL_FN_SAXPY = 0,      /* accessors x (read), y (read), z (write):
+                            z[i] = fma(a, x[i], y[i])                        */
+  CCL_FN_SUM_ALONG = 1   /* accessors x (read; its mapper's region spans the
+                            range along `dim`, e.g. SLICE(dim) or ALL), out
+                            (write): out[i] = x[i with i_dim = lo] + ... +
+                            x[i with i_dim = hi - 1], summed in index order
+                            from 0 in float32, lo/hi the range's bounds       */
+};
+
+typedef struct {
+  int32_t fn;    /* CCL_FN_*                        */
+  float a;       /* CCL_FN_SAXPY: the scalar        */
+  int32_t dim;   /* CCL_FN_SUM_ALONG: the dimension */
+} ccl_kernel_fn;
+
+/* Runs `fn` at every index of every chunk.  Before the launch, for every
+ * readable accessor whose mapper reaches beyond the chunk, the part of
+ * region_of(chunk j, mapper) that chunk k owns (its chunk box) is copied
+ * from bufs[k] to bufs[j], as ccl_halo_exchange does; each chunk's own cells
+ * of a readable buffer must hold the data on entry.  Written accessors must
+ * use ONE_TO_ONE (the functions write only at their own index).  All work
+ * is enqueued on `hip_stream`: one copy launch, then one launch per 8
+ * chunks.
+ *   chunks    : nchunks chunks of one range (ccl_split_range, ccl_split_grid
+ *               or any disjoint cover)
+ *   acc       : naccessors accessors, in the order the function lists them
+ * Errors: INVALID (NULL, unknown function, wrong accessor count or modes, a
+ * written accessor with another mapper, bad buffers), RANGE (a buffer region
+ * lacks its mapper's region, the range outside a buffer), HIP. */
+ccl_status ccl_parallel_for(const ccl_kernel_fn *fn, int32_t nchunks, const ccl_chunk *chunks,
+                            int32_t naccessors, const ccl_accessor *acc, void *hip_stream);
 
 /* z[i] = fma(a, x[i], y[i]) for i < n, float32: the kernel of the paper's
  * first listing (section 2), used to measure achievable HBM bandwidth.

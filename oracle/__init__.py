@@ -8,9 +8,12 @@ Contents
   * ``oracle.c`` (built to ``liboracle.so`` with gcc, no HIP headers): the
     float32 and float64 leapfrog wave steppers in 1D/2D/3D, the discrete
     leapfrog energy, and the SAXPY of the paper's first listing (section 2).
-  * ``ranges``: the split of a kernel's index range into chunks and the range
-    mappers one_to_one / neighborhood / all (section 3, second listing and
-    the paragraph after it), as interval arithmetic.
+  * ``ranges``: the split of a kernel's index range into chunks (along one
+    dimension, or a block split along several) and the range mappers
+    one_to_one / neighborhood / all / fixed / slice (section 3, second
+    listing and the paragraph after it), as interval arithmetic.
+  * ``sum_along``: the float32 reduction along one dimension that a kernel
+    reading through a slice mapper computes.
   * ``exact``: the leapfrog iterated in exact rational arithmetic (tiny grids).
   * ``mlp``: the 12-64-64-2 cost-model MLP in float64: forward, analytic
     backward, mean-squared-error loss and Adam.
@@ -155,6 +158,19 @@ def energy(u_new, u_old, r2: float, _lib_override=None) -> float:
         return float(L.oracle_energy3d(_ptr(a, _f64p), _ptr(b, _f64p), a.shape[0],
                                        a.shape[1], a.shape[2], r2))
     raise ValueError("rank must be 1, 2 or 3")
+
+
+def sum_along(x, dim: int):
+    """out[i] = x[i with i_dim = 0] + x[i with i_dim = 1] + ... in float32,
+    summed in index order starting from 0 (each addition rounded once), the
+    same value at every index along `dim`: the reduction a kernel with a
+    slice(dim) range mapper computes (section 3: a mapper naming the whole
+    extent along one dimension)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    acc = np.zeros(x.shape[:dim] + x.shape[dim + 1:], dtype=np.float32)
+    for v in range(x.shape[dim]):
+        acc = acc + np.take(x, v, axis=dim)  # float32 + float32 -> float32, rounded
+    return np.ascontiguousarray(np.broadcast_to(np.expand_dims(acc, dim), x.shape))
 
 
 def saxpy(a: float, x, y):

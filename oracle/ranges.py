@@ -8,10 +8,17 @@ what must be transferred before the chunk runs.
 Definitions (plain interval arithmetic, one dimension at a time):
   * split: along ``split_dim`` of extent n starting at offset o, chunk k of K
     covers [o + floor(k n / K), o + floor((k+1) n / K)); other dims are whole.
+  * block split (split_grid): the same 1D split applied independently along
+    every dimension d with counts[d] pieces; the chunks are all products of
+    one piece per dimension, numbered with the last dimension fastest.
   * one_to_one: region = the chunk itself (the kernel touches only index i).
   * neighborhood(e): region = chunk grown by e_d on both sides of each dim,
     intersected with the buffer's index range [0, buffer_range_d).
   * all: region = the whole buffer.
+  * fixed(box): region = the given box, whatever the chunk, intersected with
+    the buffer's index range.
+  * slice(d): region = the chunk with dimension d replaced by the buffer's
+    whole extent [0, buffer_range_d).
   * halo = region minus chunk; transfers = for every ordered pair of chunks
     (owner, reader), region(reader) intersected with chunk(owner).
 
@@ -19,7 +26,7 @@ Boxes are (offset tuple, range tuple).
 """
 from __future__ import annotations
 
-ONE_TO_ONE, NEIGHBORHOOD, ALL = 0, 1, 2
+ONE_TO_ONE, NEIGHBORHOOD, ALL, FIXED, SLICE = 0, 1, 2, 3, 4
 
 
 def split_range(offset, rng, nchunks: int, split_dim: int = 0):
@@ -43,13 +50,53 @@ def split_range(offset, rng, nchunks: int, split_dim: int = 0):
     return out
 
 
-def region_of(chunk, kind: int, extent, buffer_range):
+def split_grid(offset, rng, counts):
+    dims = len(rng)
+    if dims not in (1, 2, 3) or len(offset) != dims or len(counts) != dims:
+        raise ValueError("dims must be 1, 2 or 3, with one count per dimension")
+    pieces = []
+    for d in range(dims):
+        if counts[d] < 1 or counts[d] > rng[d]:
+            raise ValueError("a count is below 1 or above the extent")
+        n, K = rng[d], counts[d]
+        pieces.append([(offset[d] + (k * n) // K, ((k + 1) * n) // K - (k * n) // K)
+                       for k in range(K)])
+    out = []
+    for combo in _product(pieces):  # last dimension fastest
+        out.append((tuple(o for o, _ in combo), tuple(r for _, r in combo)))
+    return out
+
+
+def _product(lists):
+    if not lists:
+        return [()]
+    rest = _product(lists[1:])
+    return [(x,) + r for x in lists[0] for r in rest]
+
+
+def region_of(chunk, kind: int, extent, buffer_range, offset=None, dim=0):
+    """`extent`: neighborhood's growth per side, or fixed's box extent;
+    `offset`: fixed's box origin; `dim`: the dimension slice takes whole."""
     off, rng = chunk
     dims = len(rng)
     if kind == ONE_TO_ONE:
         return (tuple(off), tuple(rng))
     if kind == ALL:
         return (tuple([0] * dims), tuple(buffer_range))
+    if kind == FIXED:
+        lo, r = [], []
+        for d in range(dims):
+            a = min(max(0, offset[d]), buffer_range[d])
+            b = max(a, min(buffer_range[d], offset[d] + extent[d]))
+            lo.append(a)
+            r.append(b - a)
+        return (tuple(lo), tuple(r))
+    if kind == SLICE:
+        if not 0 <= dim < dims:
+            raise ValueError("slice dimension out of range")
+        lo, r = list(off), list(rng)
+        lo[dim], r[dim] = 0, buffer_range[dim]
+        return (tuple(lo), tuple(r))
     if kind != NEIGHBORHOOD:
         raise ValueError("unknown mapper")
     lo, r = [], []

@@ -29,7 +29,7 @@ CCL_MAX_DIMS = 3
 CCL_MAX_CHUNKS = 64
 CCL_MAX_DEPTH = 8
 
-ONE_TO_ONE, NEIGHBORHOOD, ALL = 0, 1, 2
+ONE_TO_ONE, NEIGHBORHOOD, ALL, FIXED, SLICE = 0, 1, 2, 3, 4
 
 _I64x3 = ctypes.c_int64 * 3
 
@@ -52,11 +52,25 @@ class ccl_chunk(ctypes.Structure):
 
 
 class ccl_range_mapper(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("extent", _I64x3)]
+    _fields_ = [("kind", ctypes.c_int32), ("extent", _I64x3), ("offset", _I64x3),
+                ("dim", ctypes.c_int32)]
 
 
 class ccl_chunk_buffer(ctypes.Structure):
     _fields_ = [("base", ctypes.c_void_p), ("region", ccl_subrange), ("pitch", _I64x3)]
+
+
+class ccl_accessor(ctypes.Structure):
+    _fields_ = [("mapper", ccl_range_mapper), ("mode", ctypes.c_int32),
+                ("buffer_range", _I64x3), ("bufs", ctypes.c_void_p)]
+
+
+class ccl_kernel_fn(ctypes.Structure):
+    _fields_ = [("fn", ctypes.c_int32), ("a", ctypes.c_float), ("dim", ctypes.c_int32)]
+
+
+CCL_ACCESS_READ, CCL_ACCESS_WRITE, CCL_ACCESS_READ_WRITE = 1, 2, 3
+CCL_FN_SAXPY, CCL_FN_SUM_ALONG = 0, 1
 
 
 class ccl_transfer(ctypes.Structure):
@@ -108,6 +122,7 @@ _SIGS = {
     "ccl_last_error": (ctypes.c_char_p, []),
     "ccl_split_range": (ctypes.c_int32, [_P(ccl_subrange), ctypes.c_int32, ctypes.c_int32,
                                          _P(ccl_chunk)]),
+    "ccl_split_grid": (ctypes.c_int32, [_P(ccl_subrange), _P(ctypes.c_int32), _P(ccl_chunk)]),
     "ccl_region_of": (ctypes.c_int32, [_P(ccl_chunk), _P(ccl_range_mapper), _P(ctypes.c_int64),
                                        _P(ccl_subrange)]),
     "ccl_transfers": (ctypes.c_int32, [ctypes.c_int32, _P(ccl_chunk), _P(ccl_range_mapper),
@@ -128,6 +143,8 @@ _SIGS = {
     "ccl_energy_read": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_void_p, _P(ctypes.c_double),
                                          _P(ctypes.c_uint64)]),
     "ccl_energy_backend": (ctypes.c_char_p, [ctypes.c_int32]),
+    "ccl_parallel_for": (ctypes.c_int32, [_P(ccl_kernel_fn), ctypes.c_int32, _P(ccl_chunk),
+                                          ctypes.c_int32, _P(ccl_accessor), ctypes.c_void_p]),
     "ccl_saxpy": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_float, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "ccl_batch_create": (ctypes.c_int32, [ctypes.c_int32, _P(ccl_batch_grid), ctypes.c_int32,
@@ -223,11 +240,20 @@ def make_subrange(offset, rng) -> ccl_subrange:
     return s
 
 
-def make_mapper(kind: int, extent=(0, 0, 0)) -> ccl_range_mapper:
+def make_mapper(kind: int, extent=(0, 0, 0), offset=(0, 0, 0), dim: int = 0) -> ccl_range_mapper:
+    """extent: NEIGHBORHOOD's growth per side or FIXED's box extent; offset:
+    FIXED's box origin; dim: the dimension SLICE takes whole."""
     m = ccl_range_mapper()
     m.kind = int(kind)
     m.extent = _i64(extent)
+    m.offset = _i64(offset)
+    m.dim = int(dim)
     return m
+
+
+def _mapper(kind, extent) -> ccl_range_mapper:
+    """A mapper given as a ccl_range_mapper, or as (kind, extent)."""
+    return kind if isinstance(kind, ccl_range_mapper) else make_mapper(kind, extent)
 
 
 def ccl_version() -> str:
@@ -245,8 +271,20 @@ def ccl_split_range(offset, rng, nchunks: int, split_dim: int = 0):
     return out
 
 
+def ccl_split_grid(offset, rng, counts):
+    """Chunks of the block split with counts[d] pieces along dimension d."""
+    total = 1
+    for c in counts:
+        total *= max(1, int(c))
+    out = (ccl_chunk * total)()
+    r = make_subrange(offset, rng)
+    cn = (ctypes.c_int32 * 3)(*[int(c) for c in counts], *([1] * (3 - len(counts))))
+    _check("ccl_split_grid", lib().ccl_split_grid(ctypes.byref(r), cn, out))
+    return out
+
+
 def ccl_region_of(chunk: ccl_chunk, kind: int, extent, buffer_range) -> ccl_subrange:
-    m = make_mapper(kind, extent)
+    m = _mapper(kind, extent)
     br = _i64(buffer_range)
     out = ccl_subrange()
     _check("ccl_region_of", lib().ccl_region_of(ctypes.byref(chunk), ctypes.byref(m), br,
@@ -255,7 +293,7 @@ def ccl_region_of(chunk: ccl_chunk, kind: int, extent, buffer_range) -> ccl_subr
 
 
 def ccl_transfers(chunks, kind: int, extent, buffer_range):
-    m = make_mapper(kind, extent)
+    m = _mapper(kind, extent)
     br = _i64(buffer_range)
     n = ctypes.c_int32(0)
     st = lib().ccl_transfers(len(chunks), chunks, ctypes.byref(m), br, None, 0, ctypes.byref(n))
@@ -268,7 +306,7 @@ def ccl_transfers(chunks, kind: int, extent, buffer_range):
 
 
 def ccl_halo_exchange(chunks, kind: int, extent, bufs, elem_bytes: int = 4, stream=None):
-    m = make_mapper(kind, extent)
+    m = _mapper(kind, extent)
     _check("ccl_halo_exchange", lib().ccl_halo_exchange(len(chunks), chunks, ctypes.byref(m),
                                                         bufs, elem_bytes, _stream(stream)))
 
@@ -312,6 +350,26 @@ def ccl_energy_read(device: int = 0, stream=None):
 
 def ccl_energy_backend(device: int = 0) -> str:
     return lib().ccl_energy_backend(device).decode()
+
+
+def make_accessor(mapper: ccl_range_mapper, mode: int, buffer_range, bufs) -> ccl_accessor:
+    """`bufs`: a ctypes array of ccl_chunk_buffer, one per chunk (kept alive
+    by the returned object)."""
+    a = ccl_accessor()
+    a.mapper = mapper
+    a.mode = int(mode)
+    a.buffer_range = _i64(buffer_range)
+    a.bufs = ctypes.cast(bufs, ctypes.c_void_p)
+    a._keep = bufs
+    return a
+
+
+def ccl_parallel_for(fn: int, chunks, accessors, a: float = 0.0, dim: int = 0, stream=None):
+    k = ccl_kernel_fn()
+    k.fn, k.a, k.dim = int(fn), float(a), int(dim)
+    arr = (ccl_accessor * len(accessors))(*accessors)
+    _check("ccl_parallel_for", lib().ccl_parallel_for(ctypes.byref(k), len(chunks), chunks,
+                                                      len(accessors), arr, _stream(stream)))
 
 
 def ccl_saxpy(n: int, a: float, x_ptr: int, y_ptr: int, z_ptr: int, stream=None):

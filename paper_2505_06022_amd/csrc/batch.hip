@@ -239,21 +239,26 @@ static ccl_status enqueue_per_grid(BatchImpl *B, hipStream_t s) {
   return CCL_OK;
 }
 
-static ccl_status enqueue_batch(BatchImpl *B, hipStream_t s) {
-  if (B->flags & CCL_BATCH_PER_GRID) return enqueue_per_grid(B, s);
-  const BatchTables &t = B->tables;
-  hipLaunchKernelGGL(batch_reset_kernel, dim3(B->counter_blocks), dim3(256), 0, s, t.counters,
+// The counter reset and the persistent kernel over tables `t`.
+static ccl_status launch_persistent(const BatchTables &t, int tmax, int blocks,
+                                    int counter_blocks, hipStream_t s) {
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(counter_blocks), dim3(256), 0, s, t.counters,
                      t.ncounters, t.ctl);
   ccl_status st = hip_check(hipGetLastError(), "batch_reset_kernel launch");
   if (st != CCL_OK) return st;
   TimedLaunch tl(CCL_KERNEL_STENCIL, s);
-  switch (B->tmax) {
-    case 1: hipLaunchKernelGGL(batch_kernel<1>, dim3(B->blocks), dim3(kThreads), 0, s, t); break;
-    case 2: hipLaunchKernelGGL(batch_kernel<2>, dim3(B->blocks), dim3(kThreads), 0, s, t); break;
-    case 4: hipLaunchKernelGGL(batch_kernel<4>, dim3(B->blocks), dim3(kThreads), 0, s, t); break;
-    default: hipLaunchKernelGGL(batch_kernel<8>, dim3(B->blocks), dim3(kThreads), 0, s, t); break;
+  switch (tmax) {
+    case 1: hipLaunchKernelGGL(batch_kernel<1>, dim3(blocks), dim3(kThreads), 0, s, t); break;
+    case 2: hipLaunchKernelGGL(batch_kernel<2>, dim3(blocks), dim3(kThreads), 0, s, t); break;
+    case 4: hipLaunchKernelGGL(batch_kernel<4>, dim3(blocks), dim3(kThreads), 0, s, t); break;
+    default: hipLaunchKernelGGL(batch_kernel<8>, dim3(blocks), dim3(kThreads), 0, s, t); break;
   }
   return hip_check(hipGetLastError(), "batch_kernel launch");
+}
+
+static ccl_status enqueue_batch(BatchImpl *B, hipStream_t s) {
+  if (B->flags & CCL_BATCH_PER_GRID) return enqueue_per_grid(B, s);
+  return launch_persistent(B->tables, B->tmax, B->blocks, B->counter_blocks, s);
 }
 
 static void release(BatchImpl *B) {
@@ -272,15 +277,19 @@ struct ccl_batch {
   BatchImpl *impl;
 };
 
-extern "C" ccl_status ccl_batch_create(int32_t ngrids, const ccl_batch_grid *grids,
-                                       int32_t flags, ccl_batch **out) {
-  clear_error();
-  if (!out || (ngrids > 0 && !grids)) return fail(CCL_E_INVALID, "NULL argument");
+namespace ccl {
+
+// Checks the grids and fills their device descriptors (tile rows still 0
+// where automatic); tmax is rounded up to a depth the kernel is built for.
+static ccl_status validate_grids(int32_t ngrids, const ccl_batch_grid *grids,
+                                 std::vector<GridDev> *gd_out, std::vector<int32_t> *nblk_out,
+                                 int *tmax_out) {
+  if (ngrids > 0 && !grids) return fail(CCL_E_INVALID, "NULL argument");
   if (ngrids < 1) return fail(CCL_E_INVALID, "ngrids=%d < 1", ngrids);
-  if ((flags & ~(CCL_BATCH_NO_GRAPH | CCL_BATCH_PER_GRID)) != 0)
-    return fail(CCL_E_INVALID, "unknown flags");
-  std::vector<GridDev> gd(ngrids);
-  std::vector<int32_t> nblk(ngrids);
+  std::vector<GridDev> &gd = *gd_out;
+  std::vector<int32_t> &nblk = *nblk_out;
+  gd.assign(ngrids, GridDev{});
+  nblk.assign(ngrids, 0);
   int tmax = 1;
   for (int g = 0; g < ngrids; ++g) {
     const ccl_batch_grid &G = grids[g];
@@ -304,7 +313,7 @@ extern "C" ccl_status ccl_batch_create(int32_t ngrids, const ccl_batch_grid *gri
     D.pitch = static_cast<int32_t>(G.pitch);
     D.T = G.temporal_depth;
     D.A = w2::overlap(D.T);
-    D.tile_rows = G.tile_rows;  // 0: planned below
+    D.tile_rows = G.tile_rows;  // 0: planned later
     D.nstrips = static_cast<int32_t>((G.nx + w2::strip_width(D.T) - 1) / w2::strip_width(D.T));
     D.nblocks = (G.steps + D.T - 1) / D.T;
     D.last_T = G.steps - D.T * (D.nblocks > 0 ? D.nblocks - 1 : 0);
@@ -312,34 +321,23 @@ extern "C" ccl_status ccl_batch_create(int32_t ngrids, const ccl_batch_grid *gri
     nblk[g] = D.nblocks;
     tmax = std::max(tmax, D.T);
   }
-  tmax = tmax <= 1 ? 1 : tmax <= 2 ? 2 : tmax <= 4 ? 4 : 8;
+  *tmax_out = tmax <= 1 ? 1 : tmax <= 2 ? 2 : tmax <= 4 ? 4 : 8;
+  return CCL_OK;
+}
 
-  BatchImpl *B = nullptr;
-  ccl_status st = CCL_OK;
-  if (flags & CCL_BATCH_PER_GRID) {
-    B = new BatchImpl();
-    B->ngrids = ngrids;
-    B->flags = flags;
-    B->grids.assign(grids, grids + ngrids);
-    B->nblocks = nblk;
-    // the roles ccl_wave_step's rotation leaves: T = 1 blocks swap u_prev
-    // and u_cur, T > 1 blocks swap each with its second buffer
-    for (int g = 0; g < ngrids; ++g) {
-      int up = 0, uc = 1, wp = 2, wc = 3;
-      for (int done = 0; done < grids[g].steps;) {
-        const int tb = std::min(grids[g].temporal_depth, grids[g].steps - done);
-        if (tb == 1) {
-          std::swap(up, uc);
-        } else {
-          std::swap(up, wp);
-          std::swap(uc, wc);
-        }
-        done += tb;
-      }
-      B->final_prev.push_back(up);
-      B->final_cur.push_back(uc);
-    }
-  } else {
+// Host-side plan of one persistent launch: the queue order, tile counters
+// and the grid size.
+struct PersistentPlan {
+  int32_t tmax = 1;
+  int blocks = 1;
+  std::vector<GridDev> sorted;  // by depth class, then block count
+  std::vector<int32_t> prefix, seg_start, seg_block, seg_g0, seg_gend;
+  int64_t counters = 0, total = 0;
+  int32_t nseg = 0;
+};
+
+static ccl_status plan_persistent(std::vector<GridDev> gd, int tmax, PersistentPlan *P) {
+  const int ngrids = static_cast<int>(gd.size());
   // persistent grid: as many blocks as fit on the device at once
   int dev = 0, cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -387,95 +385,177 @@ extern "C" ccl_status ccl_batch_create(int32_t ngrids, const ccl_batch_grid *gri
     counters += static_cast<int64_t>(D.nstrips) * D.nsegs;
     if (counters > INT32_MAX / 4) return fail(CCL_E_RANGE, "too many tiles");
   }
-  std::vector<GridDev> sorted(ngrids);
-  std::vector<int32_t> prefix(ngrids + 1, 0);
+  P->sorted.assign(ngrids, GridDev{});
+  P->prefix.assign(ngrids + 1, 0);
   for (int i = 0; i < ngrids; ++i) {
-    sorted[i] = gd[order[i]];
-    prefix[i + 1] = prefix[i] + sorted[i].nstrips * sorted[i].nsegs;
+    P->sorted[i] = gd[order[i]];
+    P->prefix[i + 1] = P->prefix[i] + P->sorted[i].nstrips * P->sorted[i].nsegs;
   }
   // queue segments: (block, depth class) -> the class's grids still active
   // (a prefix of the class, which is sorted by block count)
   std::vector<int32_t> cls;  // first grid of each depth class, then ngrids
   for (int i = 0; i < ngrids; ++i)
-    if (i == 0 || sorted[i].T != sorted[i - 1].T) cls.push_back(i);
+    if (i == 0 || P->sorted[i].T != P->sorted[i - 1].T) cls.push_back(i);
   cls.push_back(ngrids);
   int32_t max_blocks = 0;
-  for (const GridDev &D : sorted) max_blocks = std::max(max_blocks, D.nblocks);
-  std::vector<int32_t> seg_start, seg_block, seg_g0, seg_gend;
+  for (const GridDev &D : P->sorted) max_blocks = std::max(max_blocks, D.nblocks);
+  P->seg_start.clear();
+  P->seg_block.clear();
+  P->seg_g0.clear();
+  P->seg_gend.clear();
   int64_t total = 0;
   for (int b = 0; b < max_blocks; ++b) {
     for (size_t c = 0; c + 1 < cls.size(); ++c) {
       int a = cls[c];
-      while (a < cls[c + 1] && sorted[a].nblocks > b) ++a;
+      while (a < cls[c + 1] && P->sorted[a].nblocks > b) ++a;
       if (a == cls[c]) continue;
-      seg_start.push_back(static_cast<int32_t>(total));
-      seg_block.push_back(b);
-      seg_g0.push_back(cls[c]);
-      seg_gend.push_back(a);
-      total += prefix[a] - prefix[cls[c]];
+      P->seg_start.push_back(static_cast<int32_t>(total));
+      P->seg_block.push_back(b);
+      P->seg_g0.push_back(cls[c]);
+      P->seg_gend.push_back(a);
+      total += P->prefix[a] - P->prefix[cls[c]];
       if (total > INT32_MAX / 2) return fail(CCL_E_RANGE, "batch queue too long");
     }
   }
-  const int32_t nseg = static_cast<int32_t>(seg_block.size());
-  seg_start.push_back(static_cast<int32_t>(total));
+  P->nseg = static_cast<int32_t>(P->seg_block.size());
+  P->seg_start.push_back(static_cast<int32_t>(total));
+  P->counters = counters;
+  P->total = total;
+  P->tmax = tmax;
+  P->blocks = total == 0 ? 1 : blocks;
+  return CCL_OK;
+}
 
-  B = new BatchImpl();
-  B->ngrids = ngrids;
-  B->tmax = tmax;
-  B->flags = flags;
-  B->grids.assign(grids, grids + ngrids);
-  B->nblocks = nblk;
-  // device layout: grids | prefix | segment tables | counters | ctl | wait_ticks
+// Byte offsets of the tables in one contiguous device range:
+// grids | prefix | segment tables | counters | ctl | wait ticks.
+struct TableLayout {
+  size_t grids, prefix, sstart, sblock, sg0, sgend, count, ctl, wait, bytes;
+};
+
+static TableLayout layout_of(const PersistentPlan &P) {
   auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
-  const size_t nsg = static_cast<size_t>(std::max(nseg, 1));
-  const size_t o_grids = 0;
-  const size_t o_prefix = al(o_grids + sizeof(GridDev) * ngrids);
-  const size_t o_sstart = al(o_prefix + sizeof(int32_t) * (ngrids + 1));
-  const size_t o_sblock = al(o_sstart + sizeof(int32_t) * (nsg + 1));
-  const size_t o_sg0 = al(o_sblock + sizeof(int32_t) * nsg);
-  const size_t o_sgend = al(o_sg0 + sizeof(int32_t) * nsg);
-  const size_t o_count = al(o_sgend + sizeof(int32_t) * nsg);
-  const size_t o_ctl = al(o_count + sizeof(int32_t) * std::max<int64_t>(counters, 1));
-  const size_t o_wait = al(o_ctl + sizeof(int32_t) * 2);
-  const size_t bytes = al(o_wait + sizeof(int64_t));
-  st = hip_check(hipMalloc(&B->dev, bytes), "hipMalloc(batch tables)");
-  if (st != CCL_OK) {
-    delete B;
-    return st == CCL_E_HIP ? fail(CCL_E_NOMEM, "batch tables: %s", ccl_last_error()) : st;
-  }
-  char *d = static_cast<char *>(B->dev);
-  const int64_t wait_ticks = int64_t(100000000) * 10;  // 10 s of the 100 MHz wall clock
+  const size_t ng = P.sorted.size();
+  const size_t nsg = static_cast<size_t>(std::max(P.nseg, 1));
+  TableLayout L;
+  L.grids = 0;
+  L.prefix = al(L.grids + sizeof(GridDev) * ng);
+  L.sstart = al(L.prefix + sizeof(int32_t) * (ng + 1));
+  L.sblock = al(L.sstart + sizeof(int32_t) * (nsg + 1));
+  L.sg0 = al(L.sblock + sizeof(int32_t) * nsg);
+  L.sgend = al(L.sg0 + sizeof(int32_t) * nsg);
+  L.count = al(L.sgend + sizeof(int32_t) * nsg);
+  L.ctl = al(L.count + sizeof(int32_t) * static_cast<size_t>(std::max<int64_t>(P.counters, 1)));
+  L.wait = al(L.ctl + sizeof(int32_t) * 2);
+  L.bytes = al(L.wait + sizeof(int64_t));
+  return L;
+}
+
+constexpr int64_t kDefaultWaitTicks = int64_t(100000000) * 10;  // 10 s of the 100 MHz clock
+
+// The tables' bytes as they must appear in device memory (counters and
+// control words zero; the reset kernel clears them again before each run).
+static void write_tables(const PersistentPlan &P, const TableLayout &L, char *h) {
+  memset(h, 0, L.bytes);
   auto put = [&](size_t off, const void *src, size_t n) {
-    if (e == hipSuccess && n > 0) e = hipMemcpy(d + off, src, n, hipMemcpyHostToDevice);
+    if (n > 0) memcpy(h + off, src, n);
   };
-  e = hipSuccess;
-  put(o_grids, sorted.data(), sizeof(GridDev) * ngrids);
-  put(o_prefix, prefix.data(), sizeof(int32_t) * (ngrids + 1));
-  put(o_sstart, seg_start.data(), sizeof(int32_t) * seg_start.size());
-  put(o_sblock, seg_block.data(), sizeof(int32_t) * seg_block.size());
-  put(o_sg0, seg_g0.data(), sizeof(int32_t) * seg_g0.size());
-  put(o_sgend, seg_gend.data(), sizeof(int32_t) * seg_gend.size());
-  put(o_wait, &wait_ticks, sizeof(int64_t));
-  if (e != hipSuccess) {
-    release(B);
-    return hip_check(e, "hipMemcpy(batch tables)");
-  }
-  BatchTables &t = B->tables;
-  t.grids = reinterpret_cast<const GridDev *>(d + o_grids);
-  t.prefix_tiles = reinterpret_cast<const int32_t *>(d + o_prefix);
-  t.seg_start = reinterpret_cast<const int32_t *>(d + o_sstart);
-  t.seg_block = reinterpret_cast<const int32_t *>(d + o_sblock);
-  t.seg_g0 = reinterpret_cast<const int32_t *>(d + o_sg0);
-  t.seg_gend = reinterpret_cast<const int32_t *>(d + o_sgend);
-  t.counters = reinterpret_cast<int32_t *>(d + o_count);
-  t.ctl = reinterpret_cast<int32_t *>(d + o_ctl);
-  t.wait_ticks = reinterpret_cast<const int64_t *>(d + o_wait);
-  B->wait_ticks_dev = reinterpret_cast<int64_t *>(d + o_wait);
-  t.total = static_cast<int32_t>(total);
-  t.nseg = nseg;
-  t.ncounters = static_cast<int32_t>(counters);
-  B->counter_blocks = static_cast<int>((std::max<int64_t>(counters, 2) + 255) / 256);
-  B->blocks = total == 0 ? 1 : blocks;
+  put(L.grids, P.sorted.data(), sizeof(GridDev) * P.sorted.size());
+  put(L.prefix, P.prefix.data(), sizeof(int32_t) * P.prefix.size());
+  put(L.sstart, P.seg_start.data(), sizeof(int32_t) * P.seg_start.size());
+  put(L.sblock, P.seg_block.data(), sizeof(int32_t) * P.seg_block.size());
+  put(L.sg0, P.seg_g0.data(), sizeof(int32_t) * P.seg_g0.size());
+  put(L.sgend, P.seg_gend.data(), sizeof(int32_t) * P.seg_gend.size());
+  put(L.wait, &kDefaultWaitTicks, sizeof(int64_t));
+}
+
+// The kernel's view of tables laid out by `L` at device address `d`.
+static BatchTables tables_at(const PersistentPlan &P, const TableLayout &L, char *d) {
+  BatchTables t;
+  t.grids = reinterpret_cast<const GridDev *>(d + L.grids);
+  t.prefix_tiles = reinterpret_cast<const int32_t *>(d + L.prefix);
+  t.seg_start = reinterpret_cast<const int32_t *>(d + L.sstart);
+  t.seg_block = reinterpret_cast<const int32_t *>(d + L.sblock);
+  t.seg_g0 = reinterpret_cast<const int32_t *>(d + L.sg0);
+  t.seg_gend = reinterpret_cast<const int32_t *>(d + L.sgend);
+  t.counters = reinterpret_cast<int32_t *>(d + L.count);
+  t.ctl = reinterpret_cast<int32_t *>(d + L.ctl);
+  t.wait_ticks = reinterpret_cast<const int64_t *>(d + L.wait);
+  t.total = static_cast<int32_t>(P.total);
+  t.nseg = P.nseg;
+  t.ncounters = static_cast<int32_t>(P.counters);
+  return t;
+}
+
+static int counter_blocks_of(const PersistentPlan &P) {
+  return static_cast<int>((std::max<int64_t>(P.counters, 2) + 255) / 256);
+}
+
+}  // namespace ccl
+
+extern "C" ccl_status ccl_batch_create(int32_t ngrids, const ccl_batch_grid *grids,
+                                       int32_t flags, ccl_batch **out) {
+  clear_error();
+  if (!out || (ngrids > 0 && !grids)) return fail(CCL_E_INVALID, "NULL argument");
+  if ((flags & ~(CCL_BATCH_NO_GRAPH | CCL_BATCH_PER_GRID)) != 0)
+    return fail(CCL_E_INVALID, "unknown flags");
+  std::vector<GridDev> gd;
+  std::vector<int32_t> nblk;
+  int tmax = 1;
+  ccl_status st = validate_grids(ngrids, grids, &gd, &nblk, &tmax);
+  if (st != CCL_OK) return st;
+
+  BatchImpl *B = nullptr;
+  if (flags & CCL_BATCH_PER_GRID) {
+    B = new BatchImpl();
+    B->ngrids = ngrids;
+    B->flags = flags;
+    B->grids.assign(grids, grids + ngrids);
+    B->nblocks = nblk;
+    // the roles ccl_wave_step's rotation leaves: T = 1 blocks swap u_prev
+    // and u_cur, T > 1 blocks swap each with its second buffer
+    for (int g = 0; g < ngrids; ++g) {
+      int up = 0, uc = 1, wp = 2, wc = 3;
+      for (int done = 0; done < grids[g].steps;) {
+        const int tb = std::min(grids[g].temporal_depth, grids[g].steps - done);
+        if (tb == 1) {
+          std::swap(up, uc);
+        } else {
+          std::swap(up, wp);
+          std::swap(uc, wc);
+        }
+        done += tb;
+      }
+      B->final_prev.push_back(up);
+      B->final_cur.push_back(uc);
+    }
+  } else {
+    PersistentPlan P;
+    st = plan_persistent(gd, tmax, &P);
+    if (st != CCL_OK) return st;
+    B = new BatchImpl();
+    B->ngrids = ngrids;
+    B->tmax = tmax;
+    B->flags = flags;
+    B->grids.assign(grids, grids + ngrids);
+    B->nblocks = nblk;
+    const TableLayout L = layout_of(P);
+    st = hip_check(hipMalloc(&B->dev, L.bytes), "hipMalloc(batch tables)");
+    if (st != CCL_OK) {
+      delete B;
+      return fail(CCL_E_NOMEM, "batch tables: %s", ccl_last_error());
+    }
+    std::vector<char> host(L.bytes);
+    write_tables(P, L, host.data());
+    hipError_t e = hipMemcpy(B->dev, host.data(), L.bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      release(B);
+      return hip_check(e, "hipMemcpy(batch tables)");
+    }
+    char *d = static_cast<char *>(B->dev);
+    B->tables = tables_at(P, L, d);
+    B->wait_ticks_dev = reinterpret_cast<int64_t *>(d + L.wait);
+    B->counter_blocks = counter_blocks_of(P);
+    B->blocks = P.blocks;
   }
 
   hipError_t e = hipSuccess;

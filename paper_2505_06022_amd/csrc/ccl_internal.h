@@ -46,6 +46,9 @@ Box intersect(const Box &a, const Box &b);
 bool contains(const Box &outer, const Box &inner);
 Box grow(const Box &b, int64_t e);  // by e along every dimension
 
+// Region of the buffer [0, buffer_range) that chunk `c` touches through `m`.
+ccl_status region_box(const ccl_chunk &c, const ccl_range_mapper &m, const int64_t *buffer_range,
+                      Box *out);
 ccl_status check_chunks(int32_t nchunks, const ccl_chunk *chunks, int32_t dims);
 ccl_status check_buffer(const ccl_chunk_buffer &b, int32_t dims, const char *what,
                         bool need_vec_align);

@@ -177,22 +177,14 @@ ccl_status exchange_jobs(int32_t nchunks, const ccl_chunk *chunks, const ccl_ran
   // buffer range: the chunks' regions are clipped to the domain, which
   // already lies inside the buffer; clipping to the domain gives the same
   // boxes because a transfer box always lies inside the owner chunk.
+  // (the chunks' global range starts at or above 0 and ends at `upto`)
+  int64_t upto[CCL_MAX_DIMS] = {1, 1, 1};
+  const Box dom = domain_box(chunks[0]);
+  for (int d = 0; d < dims; ++d) upto[d] = dom.hi[d];
   for (int j = 0; j < nchunks; ++j) {
     Box need;
-    need.dims = dims;
-    const Box cj = chunk_box(chunks[j]);
-    switch (mapper.kind) {
-      case CCL_MAP_ONE_TO_ONE: need = cj; break;
-      case CCL_MAP_NEIGHBORHOOD:
-        for (int d = 0; d < dims; ++d) {
-          if (mapper.extent[d] < 0) return fail(CCL_E_INVALID, "negative extent");
-          need.lo[d] = cj.lo[d] - mapper.extent[d];
-          need.hi[d] = cj.hi[d] + mapper.extent[d];
-        }
-        break;
-      case CCL_MAP_ALL: need = domain_box(chunks[j]); break;
-      default: return fail(CCL_E_INVALID, "unknown range mapper kind %d", mapper.kind);
-    }
+    ccl_status st = region_box(chunks[j], mapper, upto, &need);
+    if (st != CCL_OK) return st;
     for (int k = 0; k < nchunks; ++k) {
       if (k == j) continue;
       Box b = intersect(need, chunk_box(chunks[k]));

@@ -142,8 +142,8 @@ ccl_status check_buffer(const ccl_chunk_buffer &b, int32_t dims, const char *wha
   return CCL_OK;
 }
 
-static ccl_status region_box(const ccl_chunk &c, const ccl_range_mapper &m,
-                             const int64_t *buffer_range, Box *out) {
+ccl_status region_box(const ccl_chunk &c, const ccl_range_mapper &m, const int64_t *buffer_range,
+                      Box *out) {
   Box r;
   r.dims = c.dims;
   switch (m.kind) {
@@ -165,6 +165,21 @@ static ccl_status region_box(const ccl_chunk &c, const ccl_range_mapper &m,
         r.lo[d] = 0;
         r.hi[d] = buffer_range[d];
       }
+      break;
+    case CCL_MAP_FIXED:
+      for (int d = 0; d < c.dims; ++d) {
+        if (m.extent[d] < 0) return fail(CCL_E_INVALID, "negative fixed extent");
+        const int64_t lo = m.offset[d], hi = m.offset[d] + m.extent[d];
+        r.lo[d] = lo < 0 ? 0 : lo > buffer_range[d] ? buffer_range[d] : lo;
+        r.hi[d] = hi > buffer_range[d] ? buffer_range[d] : hi < r.lo[d] ? r.lo[d] : hi;
+      }
+      break;
+    case CCL_MAP_SLICE:
+      if (m.dim < 0 || m.dim >= c.dims)
+        return fail(CCL_E_INVALID, "slice dim=%d not in [0,%d)", m.dim, c.dims);
+      r = chunk_box(c);
+      r.lo[m.dim] = 0;
+      r.hi[m.dim] = buffer_range[m.dim];
       break;
     default:
       return fail(CCL_E_INVALID, "unknown range mapper kind %d", m.kind);
@@ -212,6 +227,44 @@ ccl_status ccl_split_range(const ccl_subrange *range, int32_t nchunks, int32_t s
     const int64_t hi = (static_cast<int64_t>(k + 1) * n) / nchunks;
     c.offset[split_dim] = range->offset[split_dim] + lo;
     c.range[split_dim] = hi - lo;
+    chunks_out[k] = c;
+  }
+  return CCL_OK;
+}
+
+ccl_status ccl_split_grid(const ccl_subrange *range, const int32_t *counts,
+                          ccl_chunk *chunks_out) {
+  clear_error();
+  if (!range || !counts || !chunks_out) return fail(CCL_E_INVALID, "NULL argument");
+  const int dims = range->dims;
+  if (dims < 1 || dims > CCL_MAX_DIMS) return fail(CCL_E_INVALID, "dims=%d not in 1..3", dims);
+  int64_t total = 1;
+  for (int d = 0; d < dims; ++d) {
+    if (range->range[d] < 1) return fail(CCL_E_INVALID, "empty range in dim %d", d);
+    if (counts[d] < 1) return fail(CCL_E_INVALID, "counts[%d]=%d < 1", d, counts[d]);
+    if (counts[d] > range->range[d])
+      return fail(CCL_E_RANGE, "counts[%d]=%d exceeds extent %lld", d, counts[d],
+                  (long long)range->range[d]);
+    total *= counts[d];
+    if (total > (int64_t(1) << 30)) return fail(CCL_E_RANGE, "too many chunks");
+  }
+  for (int64_t k = 0; k < total; ++k) {
+    ccl_chunk c;
+    memset(&c, 0, sizeof(c));
+    c.dims = dims;
+    // chunk k's grid coordinates, last dimension fastest
+    int64_t rest = k;
+    for (int d = dims - 1; d >= 0; --d) {
+      const int64_t kd = rest % counts[d];
+      rest /= counts[d];
+      const int64_t n = range->range[d];
+      const int64_t lo = (kd * n) / counts[d];
+      const int64_t hi = ((kd + 1) * n) / counts[d];
+      c.offset[d] = range->offset[d] + lo;
+      c.range[d] = hi - lo;
+      c.global_offset[d] = range->offset[d];
+      c.global_range[d] = range->range[d];
+    }
     chunks_out[k] = c;
   }
   return CCL_OK;

@@ -35,6 +35,7 @@ struct W3Chunk {
   int64_t ip_pz, ip_py;
   int32_t lc_z0, lc_z1, lc_y0, lc_y1, lc_x0, lc_x1;  // loadable box of u^n
   int32_t cz0, cz1, cy0, cy1, cx0, cx1;              // chunk box
+  int32_t xs0;                                       // first column of strip 0
   int32_t nstrips, nrowblk;
   int32_t tile_begin;
 };
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(kThreads) void wave3d_kernel(const W3Args a) {
   const int z0 = C.cz0 + seg * a.tile_planes;
   const int z1 = min(C.cz1, z0 + a.tile_planes);
   const int yb = C.cy0 + rb * kRows;
-  const int xs = C.cx0 + strip * 256;
+  const int xs = C.xs0 + strip * 256;
   const int xl = xs + 4 * lane;
   const float r2 = a.r2;
 
@@ -342,25 +343,30 @@ ccl_status launch_wave3d(int32_t depth, bool in_place, float r2, int32_t tile_pl
       C.cy1 = static_cast<int32_t>(P.chunk.hi[1]);
       C.cx0 = static_cast<int32_t>(P.chunk.lo[2]);
       C.cx1 = static_cast<int32_t>(P.chunk.hi[2]);
-      const int64_t nx = P.chunk.hi[2] - P.chunk.lo[2];
+      // strip 0 starts at the chunk's first column aligned down to a
+      // multiple of 4 relative to the u^n buffer, so every lane's group of
+      // four columns is one 16-byte access; the output mask keeps the
+      // columns left of the chunk unchanged
+      const int64_t mis = (((P.chunk.lo[2] - P.in_cur.off[2]) % 4) + 4) % 4;
+      const int64_t xs0 = P.chunk.lo[2] - mis;
+      C.xs0 = static_cast<int32_t>(xs0);
+      const int64_t nx = P.chunk.hi[2] - xs0;
       const int64_t ny = P.chunk.hi[1] - P.chunk.lo[1];
       const int64_t nz = P.chunk.hi[0] - P.chunk.lo[0];
       C.nstrips = static_cast<int32_t>((nx + 255) / 256);
       C.nrowblk = static_cast<int32_t>((ny + kRows - 1) / kRows);
       const int64_t segs = (nz + a.tile_planes - 1) / a.tile_planes;
       {
-        // strips start at the chunk's first column: it must sit on a 16-byte
-        // boundary of both buffers
-        const int64_t rc = P.chunk.lo[2] - P.in_cur.off[2];
-        const int64_t rp = P.chunk.lo[2] - P.in_prev.off[2];
-        if ((rc % 4) != 0 || (rp % 4) != 0 || P.in_cur.pitch[0] % 4 != 0 ||
+        // both buffers must hold the strips' groups at 16-byte boundaries
+        const int64_t rp = xs0 - P.in_prev.off[2];
+        if ((((rp % 4) + 4) % 4) != 0 || P.in_cur.pitch[0] % 4 != 0 ||
             P.in_cur.pitch[1] % 4 != 0 || P.in_prev.pitch[0] % 4 != 0 ||
             P.in_prev.pitch[1] % 4 != 0 ||
             (reinterpret_cast<uintptr_t>(P.in_cur.base) & 15u) != 0 ||
             (reinterpret_cast<uintptr_t>(P.in_prev.base) & 15u) != 0)
           return fail(CCL_E_INVALID,
                       "chunk %d: 3D buffers must be 16-byte aligned with pitches a multiple of 4 "
-                      "and the chunk's first column on a multiple of 4 of the region",
+                      "and the same region column offset modulo 4",
                       first + k);
       }
       C.tile_begin = static_cast<int32_t>(tiles);
@@ -373,7 +379,8 @@ ccl_status launch_wave3d(int32_t depth, bool in_place, float r2, int32_t tile_pl
     bool xin = true;  // every strip of every chunk fully interior in x
     for (int k = 0; k < n; ++k) {
       const W3Chunk &C = a.ch[k];
-      xin = xin && (C.cx1 - C.cx0) % 256 == 0 && C.cx0 >= C.lc_x0 && C.cx1 <= C.lc_x1;
+      xin = xin && C.xs0 == C.cx0 && (C.cx1 - C.cx0) % 256 == 0 && C.cx0 >= C.lc_x0 &&
+            C.cx1 <= C.lc_x1;
     }
     ccl_status st;
     {

@@ -85,6 +85,7 @@ struct W3TChunk {
   int32_t lp[6];  // loadable box of in_prev: z0, z1, y0, y1, x0, x1
   int32_t lc[6];  // loadable box of in_cur
   int32_t cz0, cz1, cy0, cy1, cx0, cx1;  // chunk (output) box
+  int32_t xs0;                           // origin column of strip 0's patches
   int32_t nstrips, nrowblk;
   int32_t tile_begin;
 };
@@ -329,7 +330,7 @@ __global__ __launch_bounds__(kThreads) void wave3d_tb_kernel(const W3TArgs a) {
 
   const int tid = threadIdx.x;
   const int lx = tid % kLX, ly = tid / kLX;
-  const int px = C.cx0 - A + strip * OW;  // patch origin
+  const int px = C.xs0 + strip * OW;  // patch origin
   const int py = C.cy0 - T + rb * OH;
   const int xl = px + 4 * lx;
   const int yl = py + ly * P;
@@ -509,16 +510,22 @@ ccl_status launch_wave3d_tb(int32_t T, float r2, int32_t tile_planes, const Wave
       C.out_cur = P.out_cur.base;
       const WaveField *fs[4] = {&P.in_prev, &P.in_cur, &P.out_prev, &P.out_cur};
       Field3 *gs[4] = {&C.ip, &C.ic, &C.op, &C.oc};
+      // strip 0's patches start A columns left of the chunk, aligned down
+      // to a multiple of 4 relative to the u^n buffer so that every
+      // thread's group of four columns is one 16-byte access
+      const int64_t A = tb_overlap(T);
+      const int64_t mis = (((P.chunk.lo[2] - A - P.in_cur.off[2]) % 4) + 4) % 4;
+      const int64_t xs0 = P.chunk.lo[2] - A - mis;
+      if (!fits_i32(xs0)) return fail(CCL_E_RANGE, "3D indices must fit in int32");
+      C.xs0 = static_cast<int32_t>(xs0);
       for (int b = 0; b < 4; ++b) {
         ccl_status st = field3_of(*fs[b], gs[b]);
         if (st != CCL_OK) return st;
-        // patches start A (a multiple of 4) columns left of the chunk: its
-        // first column must sit on a 16-byte boundary of every buffer
-        if ((P.chunk.lo[2] - fs[b]->off[2]) % 4 != 0 || fs[b]->pitch[0] % 4 != 0 ||
+        if ((((xs0 - fs[b]->off[2]) % 4) + 4) % 4 != 0 || fs[b]->pitch[0] % 4 != 0 ||
             fs[b]->pitch[1] % 4 != 0 || (reinterpret_cast<uintptr_t>(fs[b]->base) & 15u) != 0)
           return fail(CCL_E_INVALID,
                       "chunk %d: 3D buffers must be 16-byte aligned with strides a multiple of 4 "
-                      "and the chunk's first column on a multiple of 4 of the region",
+                      "and the same region column offset modulo 4",
                       first + k);
       }
       box6(P.load_prev, C.lp);
@@ -531,7 +538,7 @@ ccl_status launch_wave3d_tb(int32_t T, float r2, int32_t tile_planes, const Wave
       C.cx1 = static_cast<int32_t>(P.chunk.hi[2]);
       const int64_t nz = P.chunk.hi[0] - P.chunk.lo[0];
       const int64_t ny = P.chunk.hi[1] - P.chunk.lo[1];
-      const int64_t nx = P.chunk.hi[2] - P.chunk.lo[2];
+      const int64_t nx = P.chunk.hi[2] - (xs0 + A);  // output columns from strip 0's first
       C.nstrips = static_cast<int32_t>((nx + tb_out_cols(T) - 1) / tb_out_cols(T));
       C.nrowblk = static_cast<int32_t>((ny + tb_out_rows(T) - 1) / tb_out_rows(T));
       C.tile_begin = static_cast<int32_t>(tiles);

@@ -11,8 +11,8 @@ from __future__ import annotations
 import numpy as np
 
 from . import (NEIGHBORHOOD, ccl_batch_create, ccl_batch_destroy, ccl_batch_grid,
-               ccl_batch_result, ccl_batch_run, ccl_chunk_buffer, ccl_region_of, ccl_split_range,
-               ccl_wave_step, make_subrange, make_wave_params)
+               ccl_batch_result, ccl_batch_run, ccl_chunk_buffer, ccl_region_of, ccl_split_grid,
+               ccl_split_range, ccl_wave_step, make_subrange, make_wave_params)
 
 PITCH_ALIGN = 64  # elements; keeps every row start 256-byte aligned
 
@@ -47,9 +47,13 @@ def view_of(t, region, box):
 
 
 class ChunkedWave:
+    """``nchunks`` chunks along ``split_dim`` (ccl_split_range), or, when
+    ``grid`` gives a count per dimension, the block split of ccl_split_grid
+    (``nchunks`` is then ignored)."""
+
     def __init__(self, domain_offset, domain_shape, nchunks: int, r2: float, depth: int = 1,
                  tile_rows: int = 0, buffer_range=None, split_dim: int = 0, device="cuda",
-                 fill=0.0):
+                 fill=0.0, grid=None):
         self.dims = len(domain_shape)
         self.domain_offset = tuple(int(v) for v in domain_offset)
         self.domain_shape = tuple(int(v) for v in domain_shape)
@@ -57,7 +61,12 @@ class ChunkedWave:
             o + n for o, n in zip(self.domain_offset, self.domain_shape))
         self.depth = depth
         self.params = make_wave_params(self.dims, r2, depth, tile_rows)
-        self.chunks = ccl_split_range(self.domain_offset, self.domain_shape, nchunks, split_dim)
+        if grid is not None:
+            self.chunks = ccl_split_grid(self.domain_offset, self.domain_shape, grid)
+        else:
+            self.chunks = ccl_split_range(self.domain_offset, self.domain_shape, nchunks,
+                                          split_dim)
+        nchunks = len(self.chunks)
         self.nchunks = nchunks
         ext = (depth,) * self.dims
         self.regions = [ccl_region_of(c, NEIGHBORHOOD, ext, self.buffer_range).box()

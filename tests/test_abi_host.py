@@ -73,6 +73,76 @@ def test_region_matches_oracle(dims):
                 assert got == ranges.region_of(c.box(), kind, e, buf)
 
 
+@pytest.mark.parametrize("dims", [1, 2, 3])
+def test_split_grid_matches_oracle(dims):
+    import itertools
+    sizes = (1, 3, 8, 17) if dims < 3 else (1, 4, 9)
+    for rng in itertools.product(sizes, repeat=dims):
+        off = tuple([3, -2, 7][:dims])
+        for counts in itertools.product(*[range(1, min(n, 5) + 1) for n in rng]):
+            got = [c.box() for c in ccl.ccl_split_grid(off, rng, counts)]
+            assert got == ranges.split_grid(off, rng, counts)
+    L = ccl.lib()
+    out = (ccl.ccl_chunk * 64)()
+    r = ccl.make_subrange((0, 0), (4, 4))
+    cn = (ctypes.c_int32 * 3)(5, 1, 1)
+    assert L.ccl_split_grid(ctypes.byref(r), cn, out) == ccl.CCL_E_RANGE
+    cn = (ctypes.c_int32 * 3)(2, 0, 1)
+    assert L.ccl_split_grid(ctypes.byref(r), cn, out) == ccl.CCL_E_INVALID
+    assert L.ccl_split_grid(None, cn, out) == ccl.CCL_E_INVALID
+
+
+@pytest.mark.parametrize("dims", [1, 2, 3])
+def test_fixed_and_slice_match_oracle(dims):
+    import numpy as np
+    rs = np.random.default_rng(12)
+    for _ in range(200):
+        buf = tuple(int(v) for v in rs.integers(1, 30, size=dims))
+        counts = tuple(int(rs.integers(1, min(b, 3) + 1)) for b in buf)
+        for c in ccl.ccl_split_grid((0,) * dims, buf, counts):
+            fo = tuple(int(rs.integers(-5, b + 3)) for b in buf)
+            fe = tuple(int(rs.integers(0, 12)) for _ in buf)
+            m = ccl.make_mapper(ccl.FIXED, fe, offset=fo)
+            assert ccl.ccl_region_of(c, m, None, buf).box() == \
+                ranges.region_of(c.box(), ranges.FIXED, fe, buf, offset=fo)
+            for d in range(dims):
+                m = ccl.make_mapper(ccl.SLICE, dim=d)
+                assert ccl.ccl_region_of(c, m, None, buf).box() == \
+                    ranges.region_of(c.box(), ranges.SLICE, (0,) * dims, buf, dim=d)
+    L = ccl.lib()
+    c = ccl.ccl_split_range((0,) * dims, (4,) * dims, 1)[0]
+    out = ccl.ccl_subrange()
+    br = ccl._i64((4,) * dims)
+    bad = ccl.make_mapper(ccl.SLICE, dim=dims)
+    assert L.ccl_region_of(ctypes.byref(c), ctypes.byref(bad), br, ctypes.byref(out)) == \
+        ccl.CCL_E_INVALID
+    bad = ccl.make_mapper(ccl.FIXED, (-1,) * dims)
+    assert L.ccl_region_of(ctypes.byref(c), ctypes.byref(bad), br, ctypes.byref(out)) == \
+        ccl.CCL_E_INVALID
+
+
+def test_block_split_transfers_match_oracle():
+    """Transfers among the chunks of block splits (corner boxes included)."""
+    for dims, shape, counts in ((2, (37, 29), (2, 2)), (2, (37, 29), (4, 2)),
+                                (2, (9, 40), (3, 5)), (3, (19, 11, 13), (2, 2, 2)),
+                                (3, (19, 11, 13), (1, 2, 3))):
+        chunks = ccl.ccl_split_grid((0,) * dims, shape, counts)
+        for e in (0, 1, 2, 4):
+            got = sorted((t.owner, t.reader, t.box.box()) for t in
+                         ccl.ccl_transfers(chunks, ccl.NEIGHBORHOOD, (e,) * dims, shape))
+            regs = [ranges.region_of(c.box(), ranges.NEIGHBORHOOD, (e,) * dims, shape)
+                    for c in chunks]
+            want = sorted(ranges.transfers([c.box() for c in chunks], regs))
+            assert got == want
+        for d in range(dims):
+            m = ccl.make_mapper(ccl.SLICE, dim=d)
+            got = sorted((t.owner, t.reader, t.box.box()) for t in
+                         ccl.ccl_transfers(chunks, m, None, shape))
+            regs = [ranges.region_of(c.box(), ranges.SLICE, (0,) * dims, shape, dim=d)
+                    for c in chunks]
+            assert got == sorted(ranges.transfers([c.box() for c in chunks], regs))
+
+
 def test_transfers_match_oracle():
     for dims, shape in ((2, (37, 11)), (3, (19, 5, 6))):
         for K in (1, 2, 3, 7):
@@ -289,3 +359,49 @@ def test_costmodel_features_host():
     arr = (ccl.ccl_tune_config * 1)(bad)
     out = (ctypes.c_float * 12)()
     assert L.ccl_costmodel_features(1, arr, out) == ccl.CCL_E_INVALID
+
+
+def test_parallel_for_validation_no_launch():
+    """ccl_parallel_for rejects a bad call on the host before any copy or
+    launch (buffers here are fake addresses that are never touched)."""
+    shape = (40, 30)
+    chunks = ccl.ccl_split_grid((0, 0), shape, (2, 2))
+    o2o = ccl.make_mapper(ccl.ONE_TO_ONE)
+    nbh = ccl.make_mapper(ccl.NEIGHBORHOOD, (1, 1))
+    own = [c.box() for c in chunks]
+    fb = lambda regs, base: _fake_buffers(chunks, regs, base=base)
+    L = ccl.lib()
+
+    def call(fn, accs, a=1.0, dim=0):
+        k = ccl.ccl_kernel_fn()
+        k.fn, k.a, k.dim = fn, a, dim
+        arr = (ccl.ccl_accessor * len(accs))(*accs)
+        return L.ccl_parallel_for(ctypes.byref(k), len(chunks), chunks, len(accs), arr, None)
+
+    R, W = ccl.CCL_ACCESS_READ, ccl.CCL_ACCESS_WRITE
+    x = ccl.make_accessor(o2o, R, shape, fb(own, 0x10000000))
+    y = ccl.make_accessor(o2o, R, shape, fb(own, 0x20000000))
+    z = ccl.make_accessor(o2o, W, shape, fb(own, 0x30000000))
+    assert call(ccl.CCL_FN_SAXPY, [x, y]) == ccl.CCL_E_INVALID            # arity
+    assert call(7, [x, y, z]) == ccl.CCL_E_INVALID                         # unknown function
+    assert call(ccl.CCL_FN_SAXPY, [x, y, ccl.make_accessor(o2o, R, shape, fb(own, 0x30000000))]) \
+        == ccl.CCL_E_INVALID                                               # z not writable
+    assert call(ccl.CCL_FN_SAXPY, [ccl.make_accessor(o2o, W, shape, fb(own, 0x10000000)), y, z]) \
+        == ccl.CCL_E_INVALID                                               # x not readable
+    assert call(ccl.CCL_FN_SAXPY, [x, y, ccl.make_accessor(nbh, W, shape, fb(own, 0x30000000))]) \
+        == ccl.CCL_E_INVALID                                               # written through nbh
+    assert "ONE_TO_ONE" in ccl.ccl_last_error()
+    # a read through neighborhood(1) needs buffers holding the grown chunk
+    assert call(ccl.CCL_FN_SAXPY, [ccl.make_accessor(nbh, R, shape, fb(own, 0x10000000)), y, z]) \
+        == ccl.CCL_E_RANGE
+    # the range must lie inside every accessor's buffer range
+    assert call(ccl.CCL_FN_SAXPY, [ccl.make_accessor(o2o, R, (40, 20), fb(own, 0x10000000)), y, z]) \
+        == ccl.CCL_E_RANGE
+    # sum along a dimension: x's mapper must span the whole range there
+    out = ccl.make_accessor(o2o, W, shape, fb(own, 0x30000000))
+    assert call(ccl.CCL_FN_SUM_ALONG, [x, out], dim=1) == ccl.CCL_E_RANGE
+    assert call(ccl.CCL_FN_SUM_ALONG, [x, out], dim=2) == ccl.CCL_E_INVALID
+    sl = ccl.make_mapper(ccl.SLICE, dim=0)
+    regs = [ccl.ccl_region_of(c, sl, None, shape).box() for c in chunks]
+    xs = ccl.make_accessor(sl, R, shape, fb(regs, 0x10000000))
+    assert call(ccl.CCL_FN_SUM_ALONG, [xs, out], dim=1) == ccl.CCL_E_RANGE  # slice(0) for dim 1

@@ -216,3 +216,118 @@ def test_last_layer_reaches_least_squares():
         mlp.adam_step(params, [dws[2], dbs[2]], m, v, step, lr=lr)
     final = mlp.loss(mlp.forward(ws, bs, x)[-1], t)
     assert best * (1 - 1e-12) <= final <= best * (1 + 1e-8)
+
+
+@pytest.mark.parametrize("dims", [1, 2, 3])
+def test_split_grid_exhaustive(dims):
+    """Block split: every cell of the range in exactly one chunk, chunks are
+    boxes whose extents along each dimension differ by at most one, chunk
+    count = product of the counts, and each dimension's pieces are the 1D
+    split along it (a block split with one count above 1 is split_range)."""
+    sizes = (1, 2, 5, 7) if dims < 3 else (1, 3, 5)
+    for rng in itertools.product(sizes, repeat=dims):
+        off = tuple(2 - d for d in range(dims))
+        for counts in itertools.product(*[range(1, min(n, 4) + 1) for n in rng]):
+            ch = ranges.split_grid(off, rng, counts)
+            assert len(ch) == int(np.prod(counts))
+            cells = []
+            for o, r in ch:
+                cells.extend(itertools.product(*[range(o[d], o[d] + r[d]) for d in range(dims)]))
+            want = list(itertools.product(*[range(off[d], off[d] + rng[d]) for d in range(dims)]))
+            assert sorted(cells) == sorted(want)
+            for d in range(dims):
+                ext = [r[d] for _, r in ch]
+                assert max(ext) - min(ext) <= 1
+                pieces = sorted({(o[d], r[d]) for o, r in ch})
+                one_d = ranges.split_range((off[d],), (rng[d],), counts[d], 0)
+                assert pieces == sorted((o[0], r[0]) for o, r in one_d)
+            # numbering: last dimension fastest
+            assert ch == sorted(ch, key=lambda c: c[0])
+            nz = [i for i, c in enumerate(counts) if c > 1]
+            if len(nz) == 1:
+                assert ch == ranges.split_range(off, rng, counts[nz[0]], nz[0])
+
+
+def test_split_grid_rejects():
+    with pytest.raises(ValueError):
+        ranges.split_grid((0, 0), (4, 4), (5, 1))
+    with pytest.raises(ValueError):
+        ranges.split_grid((0, 0), (4, 4), (0, 1))
+    with pytest.raises(ValueError):
+        ranges.split_grid((0, 0), (4, 4), (2,))
+
+
+def _bbox(pts, dims):
+    if not pts:
+        return None
+    lo = tuple(min(p[d] for p in pts) for d in range(dims))
+    hi = tuple(max(p[d] for p in pts) + 1 for d in range(dims))
+    return lo, tuple(h - l for h, l in zip(hi, lo))
+
+
+@pytest.mark.parametrize("dims", [1, 2, 3])
+def test_fixed_and_slice_brute_force(dims):
+    """fixed(box): the cells of a kernel that reads every cell of the box,
+    whatever its own index, kept if inside the buffer; slice(d): the cells a
+    kernel reads when index i touches every cell that agrees with i outside
+    dimension d (a reduction along d).  Each region is the bounding box of
+    those reads."""
+    rs = np.random.default_rng(8)
+    for _ in range(60):
+        buf = tuple(int(v) for v in rs.integers(1, 7 if dims < 3 else 5, size=dims))
+        off = tuple(int(rs.integers(0, b)) for b in buf)
+        rng = tuple(int(rs.integers(1, b - o + 1)) for o, b in zip(off, buf))
+        chunk = (off, rng)
+        cells = list(itertools.product(*[range(off[d], off[d] + rng[d]) for d in range(dims)]))
+        # fixed: a box that may stick out of the buffer on either side
+        fo = tuple(int(rs.integers(-2, b + 1)) for b in buf)
+        fe = tuple(int(rs.integers(1, 5)) for _ in buf)
+        reads = [q for q in itertools.product(*[range(fo[d], fo[d] + fe[d]) for d in range(dims)])
+                 if all(0 <= q[d] < buf[d] for d in range(dims))]
+        want = _bbox(reads, dims)
+        got = ranges.region_of(chunk, ranges.FIXED, fe, buf, offset=fo)
+        if want is None:
+            assert 0 in got[1]
+        else:
+            assert got == want
+        for d in range(dims):
+            reads = []
+            for c in cells:
+                for v in range(buf[d]):
+                    q = list(c)
+                    q[d] = v
+                    reads.append(tuple(q))
+            assert ranges.region_of(chunk, ranges.SLICE, (0,) * dims, buf, dim=d) == \
+                _bbox(reads, dims)
+
+
+# --------------------------------------------------------------- sum along --
+
+@pytest.mark.parametrize("shape,dim", [((7,), 0), ((5, 9), 0), ((5, 9), 1), ((4, 3, 6), 2),
+                                       ((4, 3, 6), 0)])
+def test_sum_along_exact_on_integers(shape, dim):
+    """Small integers (every partial sum exact in float32): the sum equals
+    the exact integer sum, broadcast along the summed dimension."""
+    rs = np.random.default_rng(3)
+    k = rs.integers(-1000, 1000, size=shape)
+    got = oracle.sum_along(k.astype(np.float32), dim)
+    want = np.broadcast_to(k.sum(axis=dim, keepdims=True), shape)
+    assert np.array_equal(got, want.astype(np.float32))
+
+
+def test_sum_along_error_bound_and_order():
+    """Random reals: within the recursive-summation bound (n-1) u sum|x| of
+    the exact sum; and the order is index order: a sum whose float32 result
+    depends on the order matches the left-to-right one."""
+    rs = np.random.default_rng(4)
+    x = rs.uniform(-1, 1, size=(6, 300)).astype(np.float32)
+    got = oracle.sum_along(x, 1)[:, 0].astype(np.float64)
+    exact = np.array([float(sum(Fraction(float(v)) for v in row)) for row in x])
+    bound = 299 * 2.0 ** -24 * np.abs(x.astype(np.float64)).sum(axis=1)
+    assert np.all(np.abs(got - exact) <= bound)
+    big = np.array([[2.0 ** 24, 1.0, 1.0, -2.0 ** 24]], dtype=np.float32)
+    # left to right: 2^24 + 1 -> 2^24 (ties to even), + 1 -> 2^24, - 2^24 -> 0
+    assert oracle.sum_along(big, 1)[0, 0] == 0.0
+    # right to left: -2^24 + 1 and + 1 are exact, + 2^24 -> 2
+    assert oracle.sum_along(big[:, ::-1].copy(), 1)[0, 0] == 2.0
+    assert oracle.sum_along(np.array([[1.0, 2.0 ** 24, -2.0 ** 24, 1.0]], np.float32), 1)[0, 0] == 1.0
