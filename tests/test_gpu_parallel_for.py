@@ -72,8 +72,11 @@ def test_saxpy_one_to_one(shape, split):
     x = synth.uniform_field(shape, 50).astype(np.float32)
     y = synth.uniform_field(shape, 51).astype(np.float32)
     regs = [c.box() for c in chunks]  # one_to_one: each buffer holds its chunk
-    bx, _ = chunk_buffers(chunks, regs, data=x)
-    by, _ = chunk_buffers(chunks, regs, data=y)
+    # the tensors behind every buffer stay referenced until the results are
+    # read: a dropped one returns its memory to torch's cache, where the
+    # next allocation reuses it
+    bx, tx = chunk_buffers(chunks, regs, data=x)
+    by, ty = chunk_buffers(chunks, regs, data=y)
     bz, tz = chunk_buffers(chunks, regs)
     o2o = ccl.make_mapper(ccl.ONE_TO_ONE)
     acc = [ccl.make_accessor(o2o, ccl.CCL_ACCESS_READ, shape, bx),
@@ -83,6 +86,7 @@ def test_saxpy_one_to_one(shape, split):
     torch.cuda.synchronize()
     got = gather(chunks, tz, shape)
     assert np.array_equal(got, oracle.saxpy(1.75, x, y))
+    del tx, ty
 
 
 def test_saxpy_unaligned_chunk_starts():
@@ -94,8 +98,8 @@ def test_saxpy_unaligned_chunk_starts():
     x = synth.uniform_field(shape, 52).astype(np.float32)
     y = synth.uniform_field(shape, 53).astype(np.float32)
     whole = [((0,), shape)] * 3
-    bx, _ = chunk_buffers(chunks, whole, data=x)
-    by, _ = chunk_buffers(chunks, whole, data=y)
+    bx, tx = chunk_buffers(chunks, whole, data=x)
+    by, ty = chunk_buffers(chunks, whole, data=y)
     bz, tz = chunk_buffers(chunks, whole)
     o2o = ccl.make_mapper(ccl.ONE_TO_ONE)
     acc = [ccl.make_accessor(o2o, ccl.CCL_ACCESS_READ, shape, bx),
@@ -104,6 +108,7 @@ def test_saxpy_unaligned_chunk_starts():
     ccl.ccl_parallel_for(ccl.CCL_FN_SAXPY, chunks, acc, a=-0.5)
     torch.cuda.synchronize()
     assert np.array_equal(gather(chunks, tz, shape), oracle.saxpy(-0.5, x, y))
+    del tx, ty
 
 
 @pytest.mark.parametrize("shape,grid,dim", [((37, 50), (2, 3), 1), ((37, 50), (3, 2), 0),
@@ -119,10 +124,11 @@ def test_sum_along_slice_mapper(shape, grid, dim):
     x = synth.uniform_field(shape, 54).astype(np.float32)
     sl_map = ccl.make_mapper(ccl.SLICE, dim=dim)
     regs = [ccl.ccl_region_of(c, sl_map, None, shape).box() for c in chunks]
-    bx, _ = chunk_buffers(chunks, regs, data=x)
+    bx, tx = chunk_buffers(chunks, regs, data=x)
     bo, to = chunk_buffers(chunks, [c.box() for c in chunks])
     acc = [ccl.make_accessor(sl_map, ccl.CCL_ACCESS_READ, shape, bx),
            ccl.make_accessor(ccl.make_mapper(ccl.ONE_TO_ONE), ccl.CCL_ACCESS_WRITE, shape, bo)]
     ccl.ccl_parallel_for(ccl.CCL_FN_SUM_ALONG, chunks, acc, dim=dim)
     torch.cuda.synchronize()
     assert np.array_equal(gather(chunks, to, shape), oracle.sum_along(x, dim))
+    del tx
