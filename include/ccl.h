@@ -365,6 +365,35 @@ ccl_status ccl_batch_result(const ccl_batch *b, int32_t grid, int32_t *prev_buf,
                             int32_t *cur_buf);
 ccl_status ccl_batch_destroy(ccl_batch *b);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one run
+ * of the persistent batched kernel, planned on every call: the same kernel
+ * and the same results as ccl_batch_create (flags 0 or CCL_BATCH_NO_GRAPH)
+ * followed by ccl_batch_run, enqueued on `hip_stream`.  Its tile tables,
+ * per-tile progress counters and control words live in a fixed device array
+ * of CCL_BATCH_STATIC_BYTES inside the library; every device the library
+ * runs on holds its own copy until the process ends.  The call allocates no
+ * device memory (no hipMalloc, hipFree or allocating library routine; its
+ * host-side plan uses ordinary host memory) and copies the tables host to
+ * device on `hip_stream`, then clears the counters with a kernel.
+ * Every call on one device shares that device's array, which keeps the last
+ * call's contents: calls that overlap on one device (two streams, two host
+ * threads) race and must be serialised by the caller.
+ *   grids        : as for ccl_batch_create; the buffers are the caller's
+ *   prev_buf,
+ *   cur_buf      : host arrays of ngrids entries, or NULL: which of each
+ *                  grid's buffers hold u^{steps-1} and u^{steps} afterwards
+ *   wait_failed  : NULL (the call returns once the work is enqueued) or a
+ *                  host int: the call then synchronises `hip_stream` and sets
+ *                  it to 1 if a tile's dependency wait passed its 10 s limit
+ *                  (results incomplete, status TIMEOUT), else 0
+ * Errors: INVALID (as ccl_batch_create), RANGE (the plan needs more than
+ * CCL_BATCH_STATIC_BYTES: fewer grids or taller tiles fit), HIP, TIMEOUT. */
+#define CCL_BATCH_STATIC_BYTES (4u << 20)
+ccl_status ccl_batch_run_static(int32_t ngrids, const ccl_batch_grid *grids,
+                                int32_t *prev_buf, int32_t *cur_buf, int32_t *wait_failed,
+                                void *hip_stream);
+
 /* ---- Autotuner ------------------------------------------------------------
  * A launch configuration of ccl_wave_step for one domain shape (offset 0,
  * split along dimension 0), and what measuring it gave. */

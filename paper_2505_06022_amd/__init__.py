@@ -155,6 +155,9 @@ _SIGS = {
     "ccl_batch_result": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_int32),
                                           _P(ctypes.c_int32)]),
     "ccl_batch_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
+    "ccl_batch_run_static": (ctypes.c_int32, [ctypes.c_int32, _P(ccl_batch_grid),
+                                              _P(ctypes.c_int32), _P(ctypes.c_int32),
+                                              _P(ctypes.c_int32), ctypes.c_void_p]),
     "ccl_autotune_measure": (ctypes.c_int32, [ctypes.c_int32, _P(ccl_tune_config), ctypes.c_float,
                                               ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                               ctypes.c_int32, ctypes.c_void_p,
@@ -421,6 +424,25 @@ def ccl_batch_result(h, grid: int):
 
 def ccl_batch_destroy(h):
     _check("ccl_batch_destroy", lib().ccl_batch_destroy(h))
+
+
+CCL_BATCH_STATIC_BYTES = 4 << 20
+
+
+def ccl_batch_run_static(grids, stream=None, check: bool = False):
+    """One persistent run of `grids` (a list of ccl_batch_grid) with the
+    library's static device tables (no device allocation).  Returns the
+    (prev, cur) buffer index of every grid; with `check`, the call also
+    synchronises the stream and raises on a dependency-wait timeout."""
+    n = len(grids)
+    arr = (ccl_batch_grid * n)(*grids)
+    prev = (ctypes.c_int32 * n)()
+    cur = (ctypes.c_int32 * n)()
+    failed = ctypes.c_int32(0)
+    _check("ccl_batch_run_static",
+           lib().ccl_batch_run_static(n, arr, prev, cur, ctypes.byref(failed) if check else None,
+                                      _stream(stream)))
+    return list(zip(prev, cur))
 
 
 def make_tune_config(shape, nchunks: int, temporal_depth: int, tile_rows: int = 0):

@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -645,5 +646,96 @@ extern "C" ccl_status ccl_batch_destroy(ccl_batch *b) {
   if (!b) return CCL_OK;
   if (b->impl) release(b->impl);
   delete b;
+  return CCL_OK;
+}
+
+// ---- the persistent run without device allocation --------------------------
+//
+// The tables, tile counters and control words of one persistent run live in
+// `scratch`, a fixed file-scope device array: every GPU the library runs on
+// holds its own copy until the process ends.  In host code the array's name
+// stands for no device address, so host code uses only the address
+// hipGetSymbolAddress returns for the current device, taken once per device.
+
+static __device__ __align__(256) unsigned char scratch[CCL_BATCH_STATIC_BYTES];
+
+namespace ccl {
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_dev[kMaxScratchDevices] = {};
+
+// The current device's copy of `scratch` (its address is looked up on the
+// first call made with that device current).
+ccl_status scratch_of_current_device(char **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_check(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    return fail(CCL_E_UNSUPPORTED, "device %d: at most %d devices", dev, kMaxScratchDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_check(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(CCL_E_HIP, "hipGetSymbolAddress(scratch) gave NULL");
+    g_scratch_dev[dev] = static_cast<char *>(ptr);
+  }
+  *out = g_scratch_dev[dev];
+  return CCL_OK;
+}
+
+}  // namespace
+}  // namespace ccl
+
+extern "C" ccl_status ccl_batch_run_static(int32_t ngrids, const ccl_batch_grid *grids,
+                                           int32_t *prev_buf, int32_t *cur_buf,
+                                           int32_t *wait_failed, void *hip_stream) {
+  clear_error();
+  std::vector<GridDev> gd;
+  std::vector<int32_t> nblk;
+  int tmax = 1;
+  ccl_status st = validate_grids(ngrids, grids, &gd, &nblk, &tmax);
+  if (st != CCL_OK) return st;
+  PersistentPlan P;
+  st = plan_persistent(gd, tmax, &P);
+  if (st != CCL_OK) return st;
+  const TableLayout L = layout_of(P);
+  if (L.bytes > sizeof(scratch))
+    return fail(CCL_E_RANGE,
+                "the batch needs %zu bytes of tables and counters, more than the %zu of the "
+                "static array (fewer grids or taller tiles fit)",
+                L.bytes, sizeof(scratch));
+  char *d = nullptr;
+  st = scratch_of_current_device(&d);
+  if (st != CCL_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  // tables from host memory (the copy is ordered on `s`; the host copy may
+  // go once the call returns), then the counters and control words cleared
+  // by the reset kernel inside launch_persistent
+  std::vector<char> host(L.bytes);
+  write_tables(P, L, host.data());
+  st = hip_check(hipMemcpyAsync(d, host.data(), L.bytes, hipMemcpyHostToDevice, s),
+                 "hipMemcpyAsync(batch tables)");
+  if (st != CCL_OK) return st;
+  const BatchTables t = tables_at(P, L, d);
+  st = launch_persistent(t, P.tmax, P.blocks, counter_blocks_of(P), s);
+  if (st != CCL_OK) return st;
+  for (int g = 0; g < ngrids; ++g) {
+    const int set = nblk[g] & 1;
+    if (prev_buf) prev_buf[g] = 2 * set;
+    if (cur_buf) cur_buf[g] = 2 * set + 1;
+  }
+  if (wait_failed) {
+    st = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (st != CCL_OK) return st;
+    int32_t ctl[2] = {0, 0};
+    st = hip_check(hipMemcpy(ctl, t.ctl, sizeof(ctl), hipMemcpyDeviceToHost),
+                   "hipMemcpy(batch status)");
+    if (st != CCL_OK) return st;
+    *wait_failed = ctl[1] != 0 ? 1 : 0;
+    if (ctl[1] != 0) return fail(CCL_E_TIMEOUT, "a tile's dependency wait passed its limit");
+  }
   return CCL_OK;
 }

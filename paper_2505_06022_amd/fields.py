@@ -135,9 +135,10 @@ class BatchedWaves:
     """Buffers (four per grid, pitched rows) and a ccl_batch over them.
 
     ``specs``: list of dicts with ny, nx, steps, r2, depth and optionally
-    tile_rows."""
+    tile_rows.  With ``create=False`` only the buffers and the grid
+    descriptors (``grids``) are made, for ccl_batch_run_static."""
 
-    def __init__(self, specs, device="cuda", flags=0, fill=0.0):
+    def __init__(self, specs, device="cuda", flags=0, fill=0.0, create=True):
         import torch
         self.specs = [dict(s) for s in specs]
         self.tensors = []
@@ -156,7 +157,7 @@ class BatchedWaves:
                 g.buf[k] = ts[k].data_ptr()
             self.tensors.append(ts)
             self.grids.append(g)
-        self.handle = ccl_batch_create(self.grids, flags)
+        self.handle = ccl_batch_create(self.grids, flags) if create else None
 
     def scatter(self, g, u_prev, u_cur):
         import torch
