@@ -7,7 +7,9 @@ code with the HIP library and never imports it.
 Contents
   * ``oracle.c`` (built to ``liboracle.so`` with gcc, no HIP headers): the
     float32 and float64 leapfrog wave steppers in 1D/2D/3D, the discrete
-    leapfrog energy, and the SAXPY of the paper's first listing (section 2).
+    leapfrog energy, the SAXPY of the paper's first listing (section 2), and
+    the leapfrog with bfloat16 / binary16 storage between passes of float32
+    steps (with the round-to-nearest-even conversion it stores through).
   * ``ranges``: the split of a kernel's index range into chunks (along one
     dimension, or a block split along several) and the range mappers
     one_to_one / neighborhood / all / fixed / slice (section 3, second
@@ -81,6 +83,11 @@ def load(path) -> ctypes.CDLL:
     for name in ("oracle_energy1d", "oracle_energy2d", "oracle_energy3d"):
         getattr(L, name).restype = ctypes.c_double
     L.oracle_saxpy_f32.argtypes = [_i64, ctypes.c_float, _f32p, _f32p, _f32p]
+    L.oracle_round_to_format.argtypes = [_i64, _f32p, _f32p, ctypes.c_int]
+    L.oracle_round_to_format.restype = ctypes.c_int
+    L.oracle_wave_stored.argtypes = [_i64, _i64, _i64, ctypes.c_float, _i64, _i64, ctypes.c_int,
+                                     _f32p, _f32p, _f32p, _f32p, ctypes.c_int]
+    L.oracle_wave_stored.restype = ctypes.c_int
     return L
 
 
@@ -139,6 +146,44 @@ def wave(u_prev, u_cur, r2: float, steps: int, threads: int = 1, _lib_override=N
         raise ValueError(f"unsupported rank {len(shp)}")
     if rc != 0:
         raise RuntimeError(f"oracle wave failed with status {rc}")
+    return out_prev, out_cur
+
+
+FORMATS = {"bf16": 1, "f16": 2}
+
+
+def round_to_format(x, fmt: str, _lib_override=None):
+    """``x`` (float32) rounded to nearest, ties to even, to bfloat16 ("bf16")
+    or IEEE binary16 ("f16"), returned as float32 holding the exact values."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    out = np.empty_like(x)
+    L = _lib_override or lib()
+    rc = L.oracle_round_to_format(x.size, _ptr(x, _f32p), _ptr(out, _f32p), FORMATS[fmt])
+    if rc != 0:
+        raise RuntimeError(f"oracle rounding failed with status {rc}")
+    return out
+
+
+def wave_stored(u_prev, u_cur, r2: float, steps: int, depth: int, fmt: str, threads: int = 1,
+                _lib_override=None):
+    """The leapfrog with the fields stored in ``fmt`` ("bf16" or "f16") and
+    float32 arithmetic: inputs rounded to the format, then passes of
+    min(depth, steps left) float32 steps, each storing its last two levels
+    rounded to the format.  2D or 3D float32 inputs; returns (u^{steps-1},
+    u^{steps}) as float32 arrays of exactly representable values."""
+    u_prev = np.ascontiguousarray(u_prev, dtype=np.float32)
+    u_cur = np.ascontiguousarray(u_cur, dtype=np.float32)
+    if u_prev.shape != u_cur.shape or u_cur.ndim not in (2, 3):
+        raise ValueError("2D or 3D inputs of one shape")
+    shp = (0,) + u_cur.shape if u_cur.ndim == 2 else u_cur.shape
+    out_prev = np.empty_like(u_cur)
+    out_cur = np.empty_like(u_cur)
+    L = _lib_override or lib()
+    rc = L.oracle_wave_stored(shp[0], shp[1], shp[2], float(np.float32(r2)), int(steps),
+                              int(depth), FORMATS[fmt], _ptr(u_prev, _f32p), _ptr(u_cur, _f32p),
+                              _ptr(out_prev, _f32p), _ptr(out_cur, _f32p), int(threads))
+    if rc != 0:
+        raise RuntimeError(f"oracle wave_stored failed with status {rc}")
     return out_prev, out_cur
 
 

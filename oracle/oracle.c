@@ -32,6 +32,10 @@
  *   SAXPY: z_i = fma(a, x_i, y_i) in float, the data-parallel kernel of the
  *   paper's first listing (section 2), used to calibrate bandwidth.
  *
+ *   16-bit storage (oracle_wave_stored): the fields kept in bfloat16 or
+ *   binary16 between passes of `depth` float steps, rounded to nearest
+ *   even when stored (oracle_round_to_format).
+ *
  * Parallelism: an optional OpenMP loop over the slowest axis; each cell's
  * arithmetic is unchanged by it.
  */
@@ -198,6 +202,139 @@ int oracle_wave1d_f64(int64_t n, double r2, int64_t steps, const double *u_prev0
     u_prev_out[i] = prev[i + 1];
     u_cur_out[i] = cur[i + 1];
   }
+  free(prev); free(cur); free(next);
+  return ORACLE_OK;
+}
+
+/* ------------------------------------------- 16-bit storage variants -- */
+
+/* Rounding of a float to a narrower binary floating-point format, by the
+ * definition of round-to-nearest, ties to even: the representable numbers
+ * of a format with `mant` stored fraction bits and smallest normal exponent
+ * `emin` are the integer multiples of 2^(e - mant) around 2^e, where
+ * e = max(floor(log2 |x|), emin) (below 2^emin the spacing stays
+ * 2^(emin - mant): the subnormals).  x / q is exact in double (q is a power
+ * of two in range), nearbyint rounds it to an integer with ties to even
+ * (the default rounding mode), and anything above the largest finite value
+ * `maxfin` after rounding is an infinity.
+ *   bfloat16: mant 7, emin -126, maxfin (2 - 2^-7) 2^127
+ *   binary16: mant 10, emin -14, maxfin 65504 */
+static float round_narrow(float x, int mant, int emin, double maxfin) {
+  if (x == 0.0f || !isfinite(x)) return x;
+  int ex;
+  (void)frexp((double)x, &ex); /* |x| = m 2^ex, m in [1/2, 1) */
+  int e = ex - 1;
+  if (e < emin) e = emin;
+  const double q = ldexp(1.0, e - mant);
+  const double r = nearbyint((double)x / q) * q;
+  if (fabs(r) > maxfin) return x > 0 ? INFINITY : -INFINITY;
+  return (float)r;
+}
+
+#define ORACLE_FMT_BF16 1
+#define ORACLE_FMT_F16 2
+
+static float round_fmt(float x, int fmt) {
+  if (fmt == ORACLE_FMT_BF16) return round_narrow(x, 7, -126, ldexp(2.0 - ldexp(1.0, -7), 127));
+  return round_narrow(x, 10, -14, 65504.0);
+}
+
+/* out[i] = in[i] rounded to format `fmt` (1: bfloat16, 2: binary16), as a
+ * float holding the exact value. */
+int oracle_round_to_format(int64_t n, const float *in, float *out, int fmt) {
+  if (n < 0 || (n > 0 && (!in || !out)) || (fmt != ORACLE_FMT_BF16 && fmt != ORACLE_FMT_F16))
+    return ORACLE_EINVAL;
+  for (int64_t i = 0; i < n; ++i) out[i] = round_fmt(in[i], fmt);
+  return ORACLE_OK;
+}
+
+/* One float step of the canonical expression on zero-padded arrays
+ * (ghost layer included, as in oracle_wave2d_f32 / oracle_wave3d_f32):
+ * next = step(prev, cur) over the interior; nz = 0 selects 2D. */
+static void step_padded_f32(int64_t nz, int64_t ny, int64_t nx, float r2, const float *prev,
+                            const float *cur, float *next, int threads) {
+  if (nz == 0) {
+    _Pragma("omp parallel for num_threads(threads) schedule(static)")
+    for (int64_t i = 0; i < ny; ++i)
+      for (int64_t j = 0; j < nx; ++j) {
+        const float c = cur[P2(i, j)];
+        const float north = cur[P2(i - 1, j)], south = cur[P2(i + 1, j)];
+        const float west = cur[P2(i, j - 1)], east = cur[P2(i, j + 1)];
+        const float sum = (north + south) + (west + east);
+        const float lap = sum - 4.0f * c;
+        next[P2(i, j)] = fmaf(r2, lap, 2.0f * c - prev[P2(i, j)]);
+      }
+    return;
+  }
+  _Pragma("omp parallel for num_threads(threads) schedule(static)")
+  for (int64_t z = 0; z < nz; ++z)
+    for (int64_t y = 0; y < ny; ++y)
+      for (int64_t x = 0; x < nx; ++x) {
+        const float c = cur[P3(z, y, x)];
+        const float below = cur[P3(z - 1, y, x)], above = cur[P3(z + 1, y, x)];
+        const float north = cur[P3(z, y - 1, x)], south = cur[P3(z, y + 1, x)];
+        const float west = cur[P3(z, y, x - 1)], east = cur[P3(z, y, x + 1)];
+        const float sum = ((below + above) + (north + south)) + (west + east);
+        const float lap = sum - 6.0f * c;
+        next[P3(z, y, x)] = fmaf(r2, lap, 2.0f * c - prev[P3(z, y, x)]);
+      }
+}
+
+/* Leapfrog with the fields stored in a 16-bit format and float arithmetic,
+ * `depth` steps per pass over the stored fields: the inputs are rounded to
+ * the format; each pass takes the stored (u^{n-1}, u^n), applies
+ * tb = min(depth, steps left) float steps of the canonical expression
+ * (unrounded in between), and stores u^{n+tb-1} and u^{n+tb} rounded to
+ * the format.  nz = 0 selects 2D (ny x nx), else 3D (nz x ny x nx). */
+int oracle_wave_stored(int64_t nz, int64_t ny, int64_t nx, float r2, int64_t steps,
+                       int64_t depth, int fmt, const float *u_prev0, const float *u_cur0,
+                       float *u_prev_out, float *u_cur_out, int threads) {
+  if (nz < 0 || ny < 1 || nx < 1 || steps < 0 || depth < 1 || !u_prev0 || !u_cur0 ||
+      !u_prev_out || !u_cur_out || (fmt != ORACLE_FMT_BF16 && fmt != ORACLE_FMT_F16))
+    return ORACLE_EINVAL;
+  if (threads < 1) threads = 1;
+  const int64_t zz = nz > 0 ? nz : 1;
+  const size_t npad = (size_t)(nz > 0 ? nz + 2 : 1) * (size_t)(ny + 2) * (size_t)(nx + 2);
+  float *prev = (float *)calloc(npad, sizeof(float));
+  float *cur = (float *)calloc(npad, sizeof(float));
+  float *next = (float *)calloc(npad, sizeof(float));
+  if (!prev || !cur || !next) {
+    free(prev); free(cur); free(next);
+    return ORACLE_ENOMEM;
+  }
+  /* interior cell q of the unpadded array <-> padded index */
+#define PADDED(z, y, x) (nz > 0 ? P3(z, y, x) : P2(y, x))
+  for (int64_t z = 0; z < zz; ++z)
+    for (int64_t y = 0; y < ny; ++y)
+      for (int64_t x = 0; x < nx; ++x) {
+        const size_t q = ((size_t)z * (size_t)ny + (size_t)y) * (size_t)nx + (size_t)x;
+        prev[PADDED(z, y, x)] = round_fmt(u_prev0[q], fmt);
+        cur[PADDED(z, y, x)] = round_fmt(u_cur0[q], fmt);
+      }
+  for (int64_t done = 0; done < steps;) {
+    const int64_t tb = steps - done < depth ? steps - done : depth;
+    for (int64_t s = 0; s < tb; ++s) {
+      step_padded_f32(nz, ny, nx, r2, prev, cur, next, threads);
+      float *t = prev; prev = cur; cur = next; next = t;
+    }
+    _Pragma("omp parallel for num_threads(threads) schedule(static)")
+    for (int64_t zy = 0; zy < zz * ny; ++zy) {
+      const int64_t z = zy / ny, y = zy % ny;
+      for (int64_t x = 0; x < nx; ++x) {
+        prev[PADDED(z, y, x)] = round_fmt(prev[PADDED(z, y, x)], fmt);
+        cur[PADDED(z, y, x)] = round_fmt(cur[PADDED(z, y, x)], fmt);
+      }
+    }
+    done += tb;
+  }
+  for (int64_t z = 0; z < zz; ++z)
+    for (int64_t y = 0; y < ny; ++y)
+      for (int64_t x = 0; x < nx; ++x) {
+        const size_t q = ((size_t)z * (size_t)ny + (size_t)y) * (size_t)nx + (size_t)x;
+        u_prev_out[q] = prev[PADDED(z, y, x)];
+        u_cur_out[q] = cur[PADDED(z, y, x)];
+      }
+#undef PADDED
   free(prev); free(cur); free(next);
   return ORACLE_OK;
 }
