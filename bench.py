@@ -12,8 +12,10 @@ measured, of the learned cost model's three best candidates when a trained
 model is present, else the best of a quick autotuner sweep; ``--depth``
 (with ``--tile-rows``, 0 = automatic) overrides both.  Besides the
 headline ("tuned") form the line reports the plain form (T = 1), device
-energy per step, and the 64-grid batched workload run as one graph launch
-against a per-grid loop of plain calls.
+energy per step, the 64-grid batched workload run as one graph launch
+against per-grid loops, the 768^3 workload (swept vs learned), and the
+headline share with float64 and 16-bit fields (roofline fraction on each
+type's own bytes).
 
 Prints one JSON line; value = Mcells/s (cell updates per second / 1e6).
 """
@@ -358,6 +360,50 @@ def wave3d_forms(with_energy=False):
     return out
 
 
+def precision_forms(w, u0, depths=(1, 2, 4, 6, 8)):
+    """The headline share (8192 x 8192, 1000 steps, 4 chunks) with the
+    fields in float64, bfloat16 and binary16 (the last two with float32
+    arithmetic), at each temporal depth in `depths` (automatic tile rows);
+    per element type the fastest depth, with its roofline fraction on its
+    own bytes: 3 elements per cell per launch at T = 1 (in place), 4 at
+    T > 1."""
+    import numpy as np
+    import torch
+
+    import paper_2505_06022_amd as ccl
+    from paper_2505_06022_amd.fields import ChunkedWave
+    cells = int(np.prod(w["shape"]))
+    out = {}
+    for dt in ("f64", "bf16", "f16"):
+        esize = ccl.DTYPE_BYTES[ccl.DTYPES[dt]]
+        host = u0.astype(np.float64) if dt == "f64" else u0
+        rows = []
+        for T in depths:
+            cw = ChunkedWave(w["share_offset"], w["shape"], w["chunks"], w["r2"], depth=T,
+                             buffer_range=w["global_shape"], dtype=dt)
+            cw.scatter(host, host)
+            cw.step(w["steps"])
+            ccl.ccl_timing_enable(True)
+            t = time_runs(cw, w["steps"], 2) / 2
+            n, ms = ccl.ccl_timing_query(ccl.CCL_KERNEL_STENCIL)
+            ccl.ccl_timing_enable(False)
+            per_cell = (3 if T == 1 else 4) * esize
+            gbs = per_cell * cells / (ms / n * 1e-3) / 1e9
+            rows.append({"depth": T, "mcells": round(cells * w["steps"] / t / 1e6, 1),
+                         "ms_per_run": round(t * 1e3, 3),
+                         "stencil_launch_ms": round(ms / n, 4),
+                         "bytes_per_cell_launch": per_cell,
+                         "achieved_gbs": round(gbs, 1),
+                         "roofline_frac": round(gbs / HBM_PEAK_GBS, 4)})
+            del cw
+            torch.cuda.empty_cache()
+        best = max(rows, key=lambda r: r["mcells"])
+        out[dt] = {"best": best, "depths": rows}
+        log(f"{dt}: best T={best['depth']} {best['mcells']} Mcells/s, "
+            f"frac {best['roofline_frac']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -469,6 +515,8 @@ def main():
         out["batched"] = batched_forms(log_energy=out.get("j_per_step") is not None)
         log("3D workload")
         out["wave3d"] = wave3d_forms(with_energy=out.get("j_per_step") is not None)
+        log("float64 and 16-bit storage")
+        out["precisions"] = precision_forms(w, u0)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(w)

@@ -120,13 +120,28 @@ typedef struct {
   ccl_subrange box;
 } ccl_transfer;
 
+/* Element types of the wave fields.  F32 and F64 compute in their own
+ * precision.  BF16 (bfloat16) and F16 (IEEE binary16) store the fields in
+ * 16 bits and compute in float32: a launch widens what it loads, applies its
+ * T steps in float32 and rounds the two levels it stores to nearest, ties
+ * to even, so their results depend on T (not on chunking or tiling). */
+enum {
+  CCL_DTYPE_F32 = 0,
+  CCL_DTYPE_F64 = 1,
+  CCL_DTYPE_BF16 = 2,
+  CCL_DTYPE_F16 = 3
+};
+
 /* Wave-stencil parameters. */
 typedef struct {
   int32_t dims;              /* 2 or 3                                       */
-  float r2;                  /* (c dt / dx)^2; stable for r2 <= 1/dims       */
+  double r2;                 /* (c dt / dx)^2; stable for r2 <= 1/dims; used
+                                as given for F64, rounded once to float32
+                                for the other element types                  */
   int32_t temporal_depth;    /* T in 1..CCL_MAX_DEPTH steps per HBM pass     */
   int32_t tile_rows;         /* rows (2D) / planes (3D) per wave tile, 0=auto*/
   int32_t flags;             /* reserved, must be 0                          */
+  int32_t dtype;             /* CCL_DTYPE_*: element type of every buffer    */
 } ccl_wave_params;
 
 /* ----------------------------------------------------------------------- */
@@ -189,7 +204,9 @@ ccl_status ccl_transfers(int32_t nchunks, const ccl_chunk *chunks,
  * bufs[reader], all boxes in one kernel launch on `hip_stream`.
  *   bufs       : one buffer per chunk; bufs[k].region must contain chunk k
  *                and every box chunk k reads
- *   elem_bytes : element size, a multiple of 4 (4 = float, 8 = double)
+ *   elem_bytes : element size, a multiple of 2 (2 = bfloat16 / binary16,
+ *                4 = float, 8 = double); bases aligned to 4 bytes (2 for
+ *                2-byte elements)
  * Errors: INVALID, RANGE (a box outside a buffer's region), HIP. */
 ccl_status ccl_halo_exchange(int32_t nchunks, const ccl_chunk *chunks,
                              const ccl_range_mapper *mapper,
@@ -214,8 +231,9 @@ ccl_status ccl_halo_unpack(int32_t nboxes, const ccl_subrange *boxes,
  *   2D: s = (u[i-1][j] + u[i+1][j]) + (u[i][j-1] + u[i][j+1]); lap = s - 4u
  *   3D: s = ((u[z-1] + u[z+1]) + (u[y-1] + u[y+1])) + (u[x-1] + u[x+1]);
  *       lap = s - 6u
- *   u_next = fma(r2, lap, 2u - u_prev)            (float32, round-to-nearest)
- * with zero outside the domain.  Work proceeds in blocks of T =
+ *   u_next = fma(r2, lap, 2u - u_prev)    (round-to-nearest, in float64 for
+ *                                          F64 and float32 otherwise)
+ * with zero outside the domain; the buffers hold elements of p->dtype.  Work proceeds in blocks of T =
  * temporal_depth steps (the last block may be shorter): before each block
  * the halos are exchanged as ccl_halo_exchange does with NEIGHBORHOOD(T) for
  * u_cur and NEIGHBORHOOD(T-1) for u_prev, then one launch advances every
@@ -232,9 +250,10 @@ ccl_status ccl_halo_unpack(int32_t nboxes, const ccl_subrange *boxes,
  *   On return the four descriptor arrays have been rotated so that u_cur
  *   describes u^{n+nsteps} and u_prev u^{n+nsteps-1}; buffer contents in the
  *   other pair are unspecified.  Results are bitwise independent of the
- *   chunking, T and tile_rows.
- * Alignment: every base 16-byte aligned, pitch[0] (and pitch[1] in 3D) a
- * multiple of 4 elements.
+ *   chunking and tile_rows, and for F32 and F64 of T too (BF16 and F16
+ *   round what each block stores, so their results depend on T).
+ * Alignment: every base 16-byte aligned (8-byte for BF16 and F16), pitch[0]
+ * (and pitch[1] in 3D) a multiple of 4 elements (2 for F64).
  * Errors: INVALID, RANGE, HIP. */
 ccl_status ccl_wave_step(const ccl_wave_params *p, int32_t nchunks,
                          const ccl_chunk *chunks, ccl_chunk_buffer *u_prev,

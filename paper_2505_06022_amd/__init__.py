@@ -78,9 +78,15 @@ class ccl_transfer(ctypes.Structure):
 
 
 class ccl_wave_params(ctypes.Structure):
-    _fields_ = [("dims", ctypes.c_int32), ("r2", ctypes.c_float),
+    _fields_ = [("dims", ctypes.c_int32), ("r2", ctypes.c_double),
                 ("temporal_depth", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("dtype", ctypes.c_int32)]
+
+
+CCL_DTYPE_F32, CCL_DTYPE_F64, CCL_DTYPE_BF16, CCL_DTYPE_F16 = 0, 1, 2, 3
+DTYPES = {"f32": CCL_DTYPE_F32, "f64": CCL_DTYPE_F64, "bf16": CCL_DTYPE_BF16,
+          "f16": CCL_DTYPE_F16}
+DTYPE_BYTES = {CCL_DTYPE_F32: 4, CCL_DTYPE_F64: 8, CCL_DTYPE_BF16: 2, CCL_DTYPE_F16: 2}
 
 
 class ccl_batch_grid(ctypes.Structure):
@@ -327,9 +333,12 @@ def ccl_halo_unpack(boxes, dsts, elem_bytes: int, staging_ptr: int, stream=None)
                                                     _stream(stream)))
 
 
-def make_wave_params(dims: int, r2: float, temporal_depth: int = 1, tile_rows: int = 0):
+def make_wave_params(dims: int, r2: float, temporal_depth: int = 1, tile_rows: int = 0,
+                     dtype: str = "f32"):
+    """dtype: "f32", "f64", "bf16" or "f16" (the buffers' element type)."""
     p = ccl_wave_params()
     p.dims, p.r2, p.temporal_depth, p.tile_rows, p.flags = dims, r2, temporal_depth, tile_rows, 0
+    p.dtype = DTYPES[dtype]
     return p
 
 

@@ -114,7 +114,7 @@ __device__ __forceinline__ void dispatch_depth(int tb, const w2::Chunk &C, const
                                                float r2, int tile_rows, int seg, int strip,
                                                int lane, int A) {
   if (tb == T || T == TMAX) {
-    w2::tile<T, false>(C, D, r2, tile_rows, seg, strip, lane, A);
+    w2::tile<P32, T, false>(C, D, r2, tile_rows, seg, strip, lane, A);
   } else if constexpr (T < TMAX) {
     dispatch_depth<TMAX, T + 1>(tb, C, D, r2, tile_rows, seg, strip, lane, A);
   }

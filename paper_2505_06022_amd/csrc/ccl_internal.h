@@ -12,6 +12,16 @@
 
 namespace ccl {
 
+// Bytes of one stored element of a ccl dtype (0 if unknown).
+constexpr int dtype_bytes(int32_t dtype) {
+  return dtype == CCL_DTYPE_F32 ? 4 : dtype == CCL_DTYPE_F64 ? 8
+       : (dtype == CCL_DTYPE_BF16 || dtype == CCL_DTYPE_F16) ? 2 : 0;
+}
+
+// Elements a lane loads as one vector access (16 bytes of registers: four
+// floats or two doubles; four 16-bit values widen to four floats).
+constexpr int dtype_group(int32_t dtype) { return dtype == CCL_DTYPE_F64 ? 2 : 4; }
+
 // Records a message for ccl_last_error() and returns `st`.
 ccl_status fail(ccl_status st, const char *fmt, ...);
 void clear_error();
@@ -69,13 +79,15 @@ class TimedLaunch {
 };
 
 // ---- halo copies (halo.hip) ----------------------------------------------
-// One copy job: a box of 4-byte words from src to dst.  Strides in words.
+// One copy job: a box of units from src to dst, a unit being 4 bytes (or 2
+// for 2-byte elements).  Strides and the contiguous extent in units.
 struct CopyJob {
-  const uint32_t *src;
-  uint32_t *dst;
-  int64_t src_pitch0, src_pitch1;  // words per step of dim 0 / dim 1
+  const void *src;
+  void *dst;
+  int64_t src_pitch0, src_pitch1;  // units per step of dim 0 / dim 1
   int64_t dst_pitch0, dst_pitch1;
-  int32_t n0, n1, n2;              // extents (dim 2 in words, contiguous)
+  int32_t n0, n1, n2;              // extents (dim 2 in units, contiguous)
+  int32_t unit;                    // bytes per unit: 4 or 2
 };
 // Enqueues all jobs (any count; split into launches internally).
 ccl_status launch_copies(const CopyJob *jobs, int32_t njobs, hipStream_t stream);
@@ -87,7 +99,7 @@ ccl_status exchange_jobs(int32_t nchunks, const ccl_chunk *chunks, const ccl_ran
 
 // ---- wave kernels --------------------------------------------------------
 struct WaveField {      // one chunk buffer as the kernels see it
-  float *base;
+  void *base;
   int64_t off[CCL_MAX_DIMS];
   int64_t pitch[CCL_MAX_DIMS];
 };
@@ -146,12 +158,16 @@ int32_t wave3d_tb_plan_planes(int64_t nz, int64_t ny, int64_t nx, int32_t K, int
 // depth-T (2..8) 3D kernel.
 void wave3d_tb_geometry(int32_t T, int32_t *out_cols, int32_t *out_rows, int32_t *waves);
 
-ccl_status launch_wave2d(int32_t depth, bool in_place, float r2, int32_t tile_rows,
-                         const WaveChunkPlan *plans, int32_t nplans, hipStream_t stream);
-ccl_status launch_wave3d(int32_t depth, bool in_place, float r2, int32_t tile_rows,
-                         const WaveChunkPlan *plans, int32_t nplans, hipStream_t stream);
+// dtype: CCL_DTYPE_* of every buffer; r2 as given (rounded to float for
+// float arithmetic).
+ccl_status launch_wave2d(int32_t dtype, int32_t depth, bool in_place, double r2,
+                         int32_t tile_rows, const WaveChunkPlan *plans, int32_t nplans,
+                         hipStream_t stream);
+ccl_status launch_wave3d(int32_t dtype, int32_t depth, bool in_place, double r2,
+                         int32_t tile_rows, const WaveChunkPlan *plans, int32_t nplans,
+                         hipStream_t stream);
 // Depth T in 2..8, out of place (u^{n+T-1}, u^{n+T} to out_prev, out_cur).
-ccl_status launch_wave3d_tb(int32_t T, float r2, int32_t tile_planes, const WaveChunkPlan *plans,
-                            int32_t nplans, hipStream_t stream);
+ccl_status launch_wave3d_tb(int32_t dtype, int32_t T, double r2, int32_t tile_planes,
+                            const WaveChunkPlan *plans, int32_t nplans, hipStream_t stream);
 
 }  // namespace ccl

@@ -2,11 +2,12 @@
 // chunk needs but does not own are copied in before it runs), plus packing
 // of such boxes into a contiguous staging buffer and back.
 //
-// Every copy is a list of jobs; a job is a 3-level box of 4-byte words
-// (n0 x n1 rows of n2 contiguous words).  One launch serves up to
-// kJobsPerLaunch jobs: the rows of all jobs are cut into segments of at most
-// kSegWords words and each wave copies one segment at a time, with 16-byte
-// accesses when both row addresses allow it.
+// Every copy is a list of jobs; a job is a 3-level box of units (n0 x n1
+// rows of n2 contiguous units; a unit is 4 bytes, or 2 for 2-byte
+// elements).  One launch serves up to kJobsPerLaunch jobs: the rows of all
+// jobs are cut into segments of at most kSegUnits units and each wave copies
+// one segment at a time, with 16-byte accesses when both row addresses
+// allow it.
 #include <cstring>
 #include <vector>
 
@@ -16,7 +17,7 @@ namespace ccl {
 namespace {
 
 constexpr int kJobsPerLaunch = 32;
-constexpr int kSegWords = 2048;
+constexpr int kSegUnits = 512;
 constexpr int kThreads = 256;
 
 struct CopyArgs {
@@ -24,6 +25,23 @@ struct CopyArgs {
   int64_t task_begin[kJobsPerLaunch + 1];
   CopyJob jobs[kJobsPerLaunch];
 };
+
+// One row segment of `len` units of type U (16-byte words where both ends
+// are aligned and the length allows it).
+template <class U>
+__device__ __forceinline__ void copy_row(const U *src, U *dst, int64_t len, int lane) {
+  constexpr int per16 = 16 / sizeof(U);
+  const bool vec = ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15u) == 0 &&
+                   (len % per16) == 0;
+  if (vec) {
+    const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
+    uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+    const int64_t n4 = len / per16;
+    for (int64_t q = lane; q < n4; q += 64) d4[q] = s4[q];
+  } else {
+    for (int64_t q = lane; q < len; q += 64) dst[q] = src[q];
+  }
+}
 
 __global__ __launch_bounds__(kThreads) void copy_boxes_kernel(CopyArgs a) {
   const int lane = threadIdx.x & 63;
@@ -36,25 +54,21 @@ __global__ __launch_bounds__(kThreads) void copy_boxes_kernel(CopyArgs a) {
     while (j + 1 < a.njobs && t >= a.task_begin[j + 1]) ++j;
     const CopyJob &J = a.jobs[j];
     const int64_t local = t - a.task_begin[j];
-    const int64_t segs = (J.n2 + kSegWords - 1) / kSegWords;
+    const int64_t segs = (J.n2 + kSegUnits - 1) / kSegUnits;
     const int64_t row = local / segs;
     const int64_t seg = local - row * segs;
     const int64_t i0 = row / J.n1;
     const int64_t i1 = row - i0 * J.n1;
-    const int64_t w0 = seg * kSegWords;
-    const int64_t len = (J.n2 - w0) < kSegWords ? (J.n2 - w0) : kSegWords;
-    const uint32_t *src = J.src + i0 * J.src_pitch0 + i1 * J.src_pitch1 + w0;
-    uint32_t *dst = J.dst + i0 * J.dst_pitch0 + i1 * J.dst_pitch1 + w0;
-    const bool vec = ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15u) == 0 &&
-                     (len & 3) == 0;
-    if (vec) {
-      const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
-      uint4 *d4 = reinterpret_cast<uint4 *>(dst);
-      const int64_t n4 = len >> 2;
-      for (int64_t q = lane; q < n4; q += 64) d4[q] = s4[q];
-    } else {
-      for (int64_t q = lane; q < len; q += 64) dst[q] = src[q];
-    }
+    const int64_t w0 = seg * kSegUnits;
+    const int64_t len = (J.n2 - w0) < kSegUnits ? (J.n2 - w0) : kSegUnits;
+    const int64_t so = i0 * J.src_pitch0 + i1 * J.src_pitch1 + w0;
+    const int64_t dof = i0 * J.dst_pitch0 + i1 * J.dst_pitch1 + w0;
+    if (J.unit == 4)
+      copy_row(static_cast<const uint32_t *>(J.src) + so, static_cast<uint32_t *>(J.dst) + dof,
+               len, lane);
+    else
+      copy_row(static_cast<const uint16_t *>(J.src) + so, static_cast<uint16_t *>(J.dst) + dof,
+               len, lane);
   }
 }
 
@@ -71,7 +85,7 @@ ccl_status launch_copies(const CopyJob *jobs, int32_t njobs, hipStream_t stream)
       const CopyJob &J = jobs[done];
       if (J.n0 <= 0 || J.n1 <= 0 || J.n2 <= 0) continue;
       a.jobs[a.njobs] = J;
-      tasks += static_cast<int64_t>(J.n0) * J.n1 * ((J.n2 + kSegWords - 1) / kSegWords);
+      tasks += static_cast<int64_t>(J.n0) * J.n1 * ((J.n2 + kSegUnits - 1) / kSegUnits);
       a.task_begin[++a.njobs] = tasks;
     }
     if (a.njobs == 0) continue;
@@ -90,10 +104,15 @@ ccl_status launch_copies(const CopyJob *jobs, int32_t njobs, hipStream_t stream)
   return CCL_OK;
 }
 
-// Builds the job that copies `box` (global indices) from src to dst buffers.
+// Units of a box copy for elements of `elem_bytes` bytes: 4 bytes when
+// the element size allows, else 2.
+static int32_t unit_of(int32_t elem_bytes) { return (elem_bytes % 4) == 0 ? 4 : 2; }
+
+// Builds the job that copies `box` (global indices) from src to dst buffers,
+// upe units per element of `unit` bytes.
 static ccl_status box_job(const Box &box, const void *src_base, const Box &src_reg,
                           const int64_t *src_pitch, void *dst_base, const Box &dst_reg,
-                          const int64_t *dst_pitch, int32_t wpe, CopyJob *job) {
+                          const int64_t *dst_pitch, int32_t unit, int32_t upe, CopyJob *job) {
   const int dims = box.dims;
   int64_t soff = 0, doff = 0;
   for (int d = 0; d < dims; ++d) {
@@ -101,17 +120,18 @@ static ccl_status box_job(const Box &box, const void *src_base, const Box &src_r
     doff += (box.lo[d] - dst_reg.lo[d]) * dst_pitch[d];
   }
   CopyJob J;
-  J.src = static_cast<const uint32_t *>(src_base) + soff * wpe;
-  J.dst = static_cast<uint32_t *>(dst_base) + doff * wpe;
+  J.unit = unit;
+  J.src = static_cast<const char *>(src_base) + soff * upe * unit;
+  J.dst = static_cast<char *>(dst_base) + doff * upe * unit;
   int64_t ext[3] = {1, 1, 1}, sp[3] = {0, 0, 0}, dp[3] = {0, 0, 0};
   // right-align the box into a 3-level (n0, n1, n2) shape
   for (int d = 0; d < dims; ++d) {
     const int k = 3 - dims + d;
     ext[k] = box.hi[d] - box.lo[d];
-    sp[k] = src_pitch[d] * wpe;
-    dp[k] = dst_pitch[d] * wpe;
+    sp[k] = src_pitch[d] * upe;
+    dp[k] = dst_pitch[d] * upe;
   }
-  ext[2] *= wpe;
+  ext[2] *= upe;
   if (ext[0] > INT32_MAX || ext[1] > INT32_MAX || ext[2] > INT32_MAX)
     return fail(CCL_E_RANGE, "box too large");
   J.n0 = static_cast<int32_t>(ext[0]);
@@ -131,11 +151,11 @@ static ccl_status pack_like(int32_t nboxes, const ccl_subrange *boxes,
   clear_error();
   if (nboxes < 0 || (nboxes > 0 && (!boxes || !bufs || !staging)))
     return fail(CCL_E_INVALID, "NULL argument or negative count");
-  if (elem_bytes <= 0 || (elem_bytes % 4) != 0)
-    return fail(CCL_E_INVALID, "elem_bytes=%d must be a positive multiple of 4", elem_bytes);
-  if ((reinterpret_cast<uintptr_t>(staging) & 3u) != 0)
-    return fail(CCL_E_INVALID, "staging must be 4-byte aligned");
-  const int32_t wpe = elem_bytes / 4;
+  if (elem_bytes <= 0 || (elem_bytes % 2) != 0)
+    return fail(CCL_E_INVALID, "elem_bytes=%d must be a positive multiple of 2", elem_bytes);
+  const int32_t unit = unit_of(elem_bytes), upe = elem_bytes / unit;
+  if ((reinterpret_cast<uintptr_t>(staging) & static_cast<uintptr_t>(unit - 1)) != 0)
+    return fail(CCL_E_INVALID, "staging must be %d-byte aligned", unit);
   std::vector<CopyJob> jobs;
   int64_t cursor = 0;  // in elements
   for (int b = 0; b < nboxes; ++b) {
@@ -144,6 +164,8 @@ static ccl_status pack_like(int32_t nboxes, const ccl_subrange *boxes,
     if (dims < 1 || dims > CCL_MAX_DIMS) return fail(CCL_E_INVALID, "box %d dims=%d", b, dims);
     ccl_status st = check_buffer(B, dims, pack ? "pack source" : "unpack target", false);
     if (st != CCL_OK) return st;
+    if ((reinterpret_cast<uintptr_t>(B.base) & static_cast<uintptr_t>(unit - 1)) != 0)
+      return fail(CCL_E_INVALID, "buffer %d not %d-byte aligned", b, unit);
     Box box = box_of(boxes[b]);
     Box reg = box_of(B.region);
     if (!contains(reg, box)) return fail(CCL_E_RANGE, "box %d outside its buffer's region", b);
@@ -156,9 +178,9 @@ static ccl_status pack_like(int32_t nboxes, const ccl_subrange *boxes,
     char *stg = static_cast<char *>(staging) + cursor * elem_bytes;
     CopyJob J;
     if (pack)
-      st = box_job(box, B.base, reg, B.pitch, stg, box, spitch, wpe, &J);
+      st = box_job(box, B.base, reg, B.pitch, stg, box, spitch, unit, upe, &J);
     else
-      st = box_job(box, stg, box, spitch, B.base, reg, B.pitch, wpe, &J);
+      st = box_job(box, stg, box, spitch, B.base, reg, B.pitch, unit, upe, &J);
     if (st != CCL_OK) return st;
     jobs.push_back(J);
     cursor += vol;
@@ -173,7 +195,7 @@ ccl_status exchange_jobs(int32_t nchunks, const ccl_chunk *chunks, const ccl_ran
                          const ccl_chunk_buffer *bufs, int32_t elem_bytes,
                          std::vector<CopyJob> *jobs) {
   const int dims = chunks[0].dims;
-  const int32_t wpe = elem_bytes / 4;
+  const int32_t unit = unit_of(elem_bytes), upe = elem_bytes / unit;
   // buffer range: the chunks' regions are clipped to the domain, which
   // already lies inside the buffer; clipping to the domain gives the same
   // boxes because a transfer box always lies inside the owner chunk.
@@ -196,7 +218,7 @@ ccl_status exchange_jobs(int32_t nchunks, const ccl_chunk *chunks, const ccl_ran
         return fail(CCL_E_RANGE, "reader buffer %d region lacks the halo its mapper needs", j);
       CopyJob J;
       ccl_status st = box_job(b, bufs[k].base, rk, bufs[k].pitch, bufs[j].base, rj,
-                              bufs[j].pitch, wpe, &J);
+                              bufs[j].pitch, unit, upe, &J);
       if (st != CCL_OK) return st;
       jobs->push_back(J);
     }
@@ -215,16 +237,17 @@ ccl_status ccl_halo_exchange(int32_t nchunks, const ccl_chunk *chunks,
                              int32_t elem_bytes, void *hip_stream) {
   clear_error();
   if (!mapper || !bufs) return fail(CCL_E_INVALID, "NULL argument");
-  if (elem_bytes <= 0 || (elem_bytes % 4) != 0)
-    return fail(CCL_E_INVALID, "elem_bytes=%d must be a positive multiple of 4", elem_bytes);
+  if (elem_bytes <= 0 || (elem_bytes % 2) != 0)
+    return fail(CCL_E_INVALID, "elem_bytes=%d must be a positive multiple of 2", elem_bytes);
   ccl_status st = check_chunks(nchunks, chunks, 0);
   if (st != CCL_OK) return st;
   const int dims = chunks[0].dims;
+  const uintptr_t amask = (elem_bytes % 4) == 0 ? 3u : 1u;
   for (int k = 0; k < nchunks; ++k) {
     st = check_buffer(bufs[k], dims, "halo buffer", false);
     if (st != CCL_OK) return st;
-    if ((reinterpret_cast<uintptr_t>(bufs[k].base) & 3u) != 0)
-      return fail(CCL_E_INVALID, "buffer %d not 4-byte aligned", k);
+    if ((reinterpret_cast<uintptr_t>(bufs[k].base) & amask) != 0)
+      return fail(CCL_E_INVALID, "buffer %d not %d-byte aligned", k, static_cast<int>(amask + 1));
     if (!contains(box_of(bufs[k].region), chunk_box(chunks[k])))
       return fail(CCL_E_RANGE, "buffer %d does not hold its chunk", k);
   }

@@ -20,11 +20,19 @@ struct W2Args {
   int32_t total_tiles;
   int32_t tile_rows;
   w2::Domain dom;
-  float r2;
+  float r2f;   // r2 rounded to float (float arithmetic)
+  double r2d;  // r2 as given (double arithmetic)
   w2::Chunk ch[kMaxChunksPerLaunch];
 };
 
-template <int T, bool IN_PLACE>
+template <class F>
+__device__ __forceinline__ F r2_of(const W2Args &a);
+template <>
+__device__ __forceinline__ float r2_of<float>(const W2Args &a) { return a.r2f; }
+template <>
+__device__ __forceinline__ double r2_of<double>(const W2Args &a) { return a.r2d; }
+
+template <class PR, int T, bool IN_PLACE>
 __global__ __launch_bounds__(kThreads) void wave2d_kernel(const W2Args a) {
   const int lane = threadIdx.x & 63;
   const int tile = __builtin_amdgcn_readfirstlane(
@@ -36,31 +44,68 @@ __global__ __launch_bounds__(kThreads) void wave2d_kernel(const W2Args a) {
   const int local = tile - C.tile_begin;
   const int seg = local / C.nstrips;
   const int strip = local - seg * C.nstrips;
-  w2::tile<T, IN_PLACE>(C, a.dom, a.r2, a.tile_rows, seg, strip, lane, w2::overlap(T));
+  w2::tile<PR, T, IN_PLACE>(C, a.dom, r2_of<typename PR::F>(a), a.tile_rows, seg, strip, lane,
+                            w2::overlap(T, PR::NV));
 }
 
-template <int T, bool IP>
+template <class PR, int T, bool IP>
 ccl_status launch_t(const W2Args &a, int blocks, hipStream_t s) {
   TimedLaunch tl(CCL_KERNEL_STENCIL, s);
-  hipLaunchKernelGGL((wave2d_kernel<T, IP>), dim3(blocks), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL((wave2d_kernel<PR, T, IP>), dim3(blocks), dim3(kThreads), 0, s, a);
   return hip_check(hipGetLastError(), "wave2d_kernel launch");
 }
 
+template <class PR>
 ccl_status launch_depth(int T, bool in_place, const W2Args &a, int blocks, hipStream_t s) {
   if (in_place) {
     if (T != 1) return fail(CCL_E_INVALID, "in-place update needs T == 1");
-    return launch_t<1, true>(a, blocks, s);
+    return launch_t<PR, 1, true>(a, blocks, s);
   }
   switch (T) {
-    case 1: return launch_t<1, false>(a, blocks, s);
-    case 2: return launch_t<2, false>(a, blocks, s);
-    case 3: return launch_t<3, false>(a, blocks, s);
-    case 4: return launch_t<4, false>(a, blocks, s);
-    case 5: return launch_t<5, false>(a, blocks, s);
-    case 6: return launch_t<6, false>(a, blocks, s);
-    case 7: return launch_t<7, false>(a, blocks, s);
-    case 8: return launch_t<8, false>(a, blocks, s);
+    case 1: return launch_t<PR, 1, false>(a, blocks, s);
+    case 2: return launch_t<PR, 2, false>(a, blocks, s);
+    case 3: return launch_t<PR, 3, false>(a, blocks, s);
+    case 4: return launch_t<PR, 4, false>(a, blocks, s);
+    case 5: return launch_t<PR, 5, false>(a, blocks, s);
+    case 6: return launch_t<PR, 6, false>(a, blocks, s);
+    case 7: return launch_t<PR, 7, false>(a, blocks, s);
+    case 8: return launch_t<PR, 8, false>(a, blocks, s);
     default: return fail(CCL_E_INVALID, "temporal depth %d not in 1..8", T);
+  }
+}
+
+ccl_status launch_dtype(int32_t dtype, int T, bool in_place, const W2Args &a, int blocks,
+                        hipStream_t s) {
+  switch (dtype) {
+    case CCL_DTYPE_F32: return launch_depth<P32>(T, in_place, a, blocks, s);
+    case CCL_DTYPE_F64: return launch_depth<P64>(T, in_place, a, blocks, s);
+    case CCL_DTYPE_BF16: return launch_depth<PB16>(T, in_place, a, blocks, s);
+    case CCL_DTYPE_F16: return launch_depth<PH16>(T, in_place, a, blocks, s);
+    default: return fail(CCL_E_INVALID, "unknown dtype %d", dtype);
+  }
+}
+
+template <class PR>
+const void *kernel_ptr(int T, bool in_place) {
+  if (in_place) return reinterpret_cast<const void *>(&wave2d_kernel<PR, 1, true>);
+  switch (T) {
+    case 1: return reinterpret_cast<const void *>(&wave2d_kernel<PR, 1, false>);
+    case 2: return reinterpret_cast<const void *>(&wave2d_kernel<PR, 2, false>);
+    case 3: return reinterpret_cast<const void *>(&wave2d_kernel<PR, 3, false>);
+    case 4: return reinterpret_cast<const void *>(&wave2d_kernel<PR, 4, false>);
+    case 5: return reinterpret_cast<const void *>(&wave2d_kernel<PR, 5, false>);
+    case 6: return reinterpret_cast<const void *>(&wave2d_kernel<PR, 6, false>);
+    case 7: return reinterpret_cast<const void *>(&wave2d_kernel<PR, 7, false>);
+    default: return reinterpret_cast<const void *>(&wave2d_kernel<PR, 8, false>);
+  }
+}
+
+const void *kernel_for(int32_t dtype, int T, bool in_place) {
+  switch (dtype) {
+    case CCL_DTYPE_F64: return kernel_ptr<P64>(T, in_place);
+    case CCL_DTYPE_BF16: return kernel_ptr<PB16>(T, in_place);
+    case CCL_DTYPE_F16: return kernel_ptr<PH16>(T, in_place);
+    default: return kernel_ptr<P32>(T, in_place);
   }
 }
 
@@ -69,22 +114,12 @@ bool fits_i32(int64_t v) { return v >= INT32_MIN && v <= INT32_MAX; }
 }  // namespace
 
 // Concurrent waves the device holds for the depth-T kernel (cached).
-static int64_t wave_slots(int T, bool in_place) {
-  static int64_t cache[2][CCL_MAX_DEPTH + 1] = {};
-  int64_t &c = cache[in_place ? 1 : 0][T];
+static int64_t wave_slots(int T, bool in_place, int32_t dtype = CCL_DTYPE_F32) {
+  static int64_t cache[4][2][CCL_MAX_DEPTH + 1] = {};
+  if (dtype < 0 || dtype > 3) dtype = CCL_DTYPE_F32;
+  int64_t &c = cache[dtype][in_place ? 1 : 0][T];
   if (c > 0) return c;
-  const void *fn = nullptr;
-  switch (in_place ? 0 : T) {
-    case 0: fn = reinterpret_cast<const void *>(&wave2d_kernel<1, true>); break;
-    case 1: fn = reinterpret_cast<const void *>(&wave2d_kernel<1, false>); break;
-    case 2: fn = reinterpret_cast<const void *>(&wave2d_kernel<2, false>); break;
-    case 3: fn = reinterpret_cast<const void *>(&wave2d_kernel<3, false>); break;
-    case 4: fn = reinterpret_cast<const void *>(&wave2d_kernel<4, false>); break;
-    case 5: fn = reinterpret_cast<const void *>(&wave2d_kernel<5, false>); break;
-    case 6: fn = reinterpret_cast<const void *>(&wave2d_kernel<6, false>); break;
-    case 7: fn = reinterpret_cast<const void *>(&wave2d_kernel<7, false>); break;
-    default: fn = reinterpret_cast<const void *>(&wave2d_kernel<8, false>); break;
-  }
+  const void *fn = kernel_for(dtype, T, in_place);
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -117,16 +152,21 @@ int32_t wave2d_plan_rows(int64_t ny, int64_t nx, int32_t K, int32_t T) {
                         static_cast<int32_t>(std::max<int64_t>(rows_max, 8)), waves_of);
 }
 
-ccl_status launch_wave2d(int32_t depth, bool in_place, float r2, int32_t tile_rows,
-                         const WaveChunkPlan *plans, int32_t nplans, hipStream_t stream) {
-  const int A = w2::overlap(depth);
-  const int SW = w2::strip_width(depth);
+ccl_status launch_wave2d(int32_t dtype, int32_t depth, bool in_place, double r2,
+                         int32_t tile_rows, const WaveChunkPlan *plans, int32_t nplans,
+                         hipStream_t stream) {
+  const int NV = dtype_group(dtype);
+  const int esize = dtype_bytes(dtype);
+  if (esize == 0) return fail(CCL_E_INVALID, "unknown dtype %d", dtype);
+  const int A = w2::overlap(depth, NV);
+  const int SW = w2::strip_width(depth, NV);
   for (int first = 0; first < nplans; first += kMaxChunksPerLaunch) {
     const int n = std::min(kMaxChunksPerLaunch, nplans - first);
     W2Args a;
     memset(&a, 0, sizeof(a));
     a.nchunks = n;
-    a.r2 = r2;
+    a.r2f = static_cast<float>(r2);
+    a.r2d = r2;
     const Box &dom = plans[first].domain;
     if (!fits_i32(dom.lo[0] - 64) || !fits_i32(dom.hi[0] + 64) || !fits_i32(dom.lo[1] - 512) ||
         !fits_i32(dom.hi[1] + 512))
@@ -169,21 +209,23 @@ ccl_status launch_wave2d(int32_t depth, bool in_place, float r2, int32_t tile_ro
       C.cx0 = static_cast<int32_t>(P.chunk.lo[1]);
       C.cx1 = static_cast<int32_t>(P.chunk.hi[1]);
       // strip 0 starts A columns left of the chunk, aligned down to a
-      // multiple of 4 relative to the u^n buffer so its loads are 16-byte
+      // multiple of NV relative to the u^n buffer so each lane's group is
+      // one aligned vector access
       int64_t xs0 = P.chunk.lo[1] - A;
       int64_t rel = xs0 - P.in_cur.off[1];
-      int64_t mis = ((rel % 4) + 4) % 4;
+      int64_t mis = ((rel % NV) + NV) % NV;
       xs0 -= mis;
       C.xs0 = static_cast<int32_t>(xs0);
       const int64_t width = P.chunk.hi[1] - (xs0 + A);
       C.nstrips = static_cast<int32_t>((width + SW - 1) / SW);
+      const uintptr_t amask = static_cast<uintptr_t>(NV * esize - 1);
       for (int b = 0; b < 4; ++b) {
         const int64_t r = xs0 - f[b]->off[1];
-        if ((((r % 4) + 4) % 4) != 0 || (f[b]->pitch[0] % 4) != 0 ||
-            (reinterpret_cast<uintptr_t>(f[b]->base) & 15u) != 0)
+        if ((((r % NV) + NV) % NV) != 0 || (f[b]->pitch[0] % NV) != 0 ||
+            (reinterpret_cast<uintptr_t>(f[b]->base) & amask) != 0)
           return fail(CCL_E_INVALID,
-                      "chunk %d: buffers must be 16-byte aligned, with pitch a multiple of 4 and "
-                      "the same region column offset modulo 4", first + k);
+                      "chunk %d: buffers must be %d-byte aligned, with pitch a multiple of %d and "
+                      "the same region column offset modulo %d", first + k, NV * esize, NV, NV);
       }
     }
     auto waves_of = [&](int32_t r) {
@@ -194,7 +236,7 @@ ccl_status launch_wave2d(int32_t depth, bool in_place, float r2, int32_t tile_ro
     };
     a.tile_rows = tile_rows > 0
                       ? tile_rows
-                      : plan_tile_rows(wave_slots(depth, in_place), depth, std::max(8, depth),
+                      : plan_tile_rows(wave_slots(depth, in_place, dtype), depth, std::max(8, depth),
                                        static_cast<int32_t>(std::max<int64_t>(rows_max, 8)),
                                        waves_of);
     int64_t tiles = 0;
@@ -209,7 +251,7 @@ ccl_status launch_wave2d(int32_t depth, bool in_place, float r2, int32_t tile_ro
     a.total_tiles = static_cast<int32_t>(tiles);
     const int blocks = static_cast<int>((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
     if (blocks == 0) continue;
-    ccl_status st = launch_depth(depth, in_place, a, blocks, stream);
+    ccl_status st = launch_dtype(dtype, depth, in_place, a, blocks, stream);
     if (st != CCL_OK) return st;
   }
   return CCL_OK;

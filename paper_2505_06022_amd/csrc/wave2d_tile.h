@@ -1,18 +1,20 @@
 // Device code of one 2D wave tile, shared by the chunked launch (wave2d.hip)
 // and the batched persistent launch (batch.hip).
 //
-// Work unit: one wave (64 lanes) owns a tile = a strip of 256 columns (four
-// consecutive floats per lane, 16-byte loads) and a segment of output rows.
+// Work unit: one wave (64 lanes) owns a tile = a strip of 64*NV columns (NV
+// consecutive elements per lane: four floats, two doubles or four 16-bit
+// values, one vector load each; see prec.h) and a segment of output rows.
 // The wave streams down the rows: at iteration i it loads row i of u^n and
 // row i-1 of u^{n-1}, then computes level 2 at row i-1, level 3 at row i-2,
 // ..., level T+1 at row i-T, keeping the last three rows of every level in
 // registers (rotating slots, so no row is moved between iterations).  North/south neighbours come from that register ring; west/east
 // neighbours from the adjacent lane through DPP wave shifts (no LDS, no
 // barriers).  A level-(k+1) value is only valid where its whole dependency
-// cone was loaded, so strips overlap by 4*ceil(T/4) columns on each side and
+// cone was loaded, so strips overlap by NV*ceil(T/NV) columns on each side and
 // segments re-read T rows above and below; outputs are written only for the
-// valid interior.  Every cell value is produced by the same float32
-// expression, so results are bitwise independent of T, tiling and chunking.
+// valid interior.  Every cell value is produced by the same expression in
+// the arithmetic type, so results are bitwise independent of tiling and
+// chunking (and of T, where storage and arithmetic types agree).
 //
 // In place (T == 1 only): u^{n+1} overwrites u^{n-1}; each lane then reads
 // u^{n-1} only at the cells it writes.  Otherwise u^{n+T-1} and u^{n+T} go to
@@ -23,6 +25,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+
+#include "prec.h"
 
 namespace ccl {
 namespace w2 {
@@ -38,15 +42,18 @@ constexpr int kUnroll = CCL_W2_UNROLL;
 static_assert(kUnroll % kPrefetch == 0, "the unrolled body must be whole ring turns");
 
 
-// Overlap columns per side and output columns per strip for depth T.
-__host__ __device__ constexpr int overlap(int T) { return 4 * ((T + 3) / 4); }
-__host__ __device__ constexpr int strip_width(int T) { return 256 - 2 * overlap(T); }
+// Overlap columns per side and output columns per strip for depth T, with
+// NV columns per lane.
+__host__ __device__ constexpr int overlap(int T, int NV = 4) { return NV * ((T + NV - 1) / NV); }
+__host__ __device__ constexpr int strip_width(int T, int NV = 4) {
+  return 64 * NV - 2 * overlap(T, NV);
+}
 
 struct Chunk {
-  const float *in_prev;
-  const float *in_cur;
-  float *out_prev;
-  float *out_cur;
+  const void *in_prev;
+  const void *in_cur;
+  void *out_prev;
+  void *out_cur;
   int32_t ip_y0, ip_x0, ip_pitch;
   int32_t ic_y0, ic_x0, ic_pitch;
   int32_t op_y0, op_x0, op_pitch;
@@ -63,178 +70,211 @@ struct Domain {
   int32_t gy0, gy1, gx0, gx1;  // zero outside
 };
 
-__device__ __forceinline__ float dpp_from_left(float v) {
-  // lane l receives lane l-1's value (wave_shr:1); lane 0 receives 0
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
-}
-__device__ __forceinline__ float dpp_from_right(float v) {
-  // lane l receives lane l+1's value (wave_shl:1); lane 63 receives 0
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
-}
+__device__ __forceinline__ float fma_(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return fma(a, b, c); }
 
 // One cell: s = (N + S) + (W + E); lap = s - 4C; u+ = fma(r2, lap, 2C - P).
 // 4C and 2C are exact in binary floating point, so s - 4C and 2C - P are
 // each the exact value rounded once, which is what the fma forms below
 // compute: the result is bitwise the same as the separate multiply and
 // subtract, with two fewer instructions.
-__device__ __forceinline__ float cell(float n, float s, float w, float e, float c, float p,
-                                      float r2) {
-  const float sum = (n + s) + (w + e);
-  const float lap = fmaf(-4.0f, c, sum);
-  return fmaf(r2, lap, fmaf(2.0f, c, -p));
+template <class F>
+__device__ __forceinline__ F cell(F n, F s, F w, F e, F c, F p, F r2) {
+  const F sum = (n + s) + (w + e);
+  const F lap = fma_(F(-4), c, sum);
+  return fma_(r2, lap, fma_(F(2), c, -p));
 }
 
-__device__ __forceinline__ float4 step4(const float4 &n, const float4 &c, const float4 &s,
-                                        const float4 &p, float r2) {
-  const float left = dpp_from_left(c.w);
-  const float right = dpp_from_right(c.x);
-  float4 o;
-  o.x = cell(n.x, s.x, left, c.y, c.x, p.x, r2);
-  o.y = cell(n.y, s.y, c.x, c.z, c.y, p.y, r2);
-  o.z = cell(n.z, s.z, c.y, c.w, c.z, p.z, r2);
-  o.w = cell(n.w, s.w, c.z, right, c.w, p.w, r2);
+// One lane group's update; west / east neighbours of the group's outer
+// columns come from the adjacent lanes.
+template <class PR>
+__device__ __forceinline__ Vec<typename PR::F, PR::NV> step_group(
+    const Vec<typename PR::F, PR::NV> &n, const Vec<typename PR::F, PR::NV> &c,
+    const Vec<typename PR::F, PR::NV> &s, const Vec<typename PR::F, PR::NV> &p,
+    typename PR::F r2) {
+  constexpr int NV = PR::NV;
+  using F = typename PR::F;
+  const F left = dpp_move<0x138>(c.v[NV - 1]);   // wave_shr:1
+  const F right = dpp_move<0x130>(c.v[0]);       // wave_shl:1
+  Vec<F, NV> o;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const F w = i == 0 ? left : c.v[i > 0 ? i - 1 : 0];
+    const F e = i == NV - 1 ? right : c.v[i < NV - 1 ? i + 1 : 0];
+    o.v[i] = cell(n.v[i], s.v[i], w, e, c.v[i], p.v[i], r2);
+  }
   return o;
 }
 
-__device__ __forceinline__ float4 zero4() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+template <class F, int NV>
+__device__ __forceinline__ Vec<F, NV> zero_vec() {
+  Vec<F, NV> z;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) z.v[i] = F(0);
+  return z;
+}
 
-// Which of the lane's four columns [xl, xl+4) lie in [x0, x1).  Columns are
-// grouped in aligned fours relative to the buffer, and a buffer's pitch is a
-// multiple of 4 that covers its extent, so a group that meets [x0, x1) is
-// always inside the allocated row.
+// Which of the lane's NV columns [xl, xl+NV) lie in [x0, x1).  Columns are
+// grouped in aligned NV-tuples relative to the buffer, and a buffer's pitch
+// is a multiple of NV that covers its extent, so a group that meets
+// [x0, x1) is always inside the allocated row.
 struct Cols {
-  bool any, m0, m1, m2, m3;
+  bool any;
+  bool m[4];
 };
 
+template <int NV = 4>
 __device__ __forceinline__ Cols cols_of(int xl, int x0, int x1) {
   Cols c;
-  c.m0 = xl + 0 >= x0 && xl + 0 < x1;
-  c.m1 = xl + 1 >= x0 && xl + 1 < x1;
-  c.m2 = xl + 2 >= x0 && xl + 2 < x1;
-  c.m3 = xl + 3 >= x0 && xl + 3 < x1;
-  c.any = c.m0 || c.m1 || c.m2 || c.m3;
+  c.any = false;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    c.m[i] = i < NV && xl + i >= x0 && xl + i < x1;
+    c.any = c.any || c.m[i];
+  }
   return c;
+}
+
+template <int NV>
+__device__ __forceinline__ bool all_of(const Cols &c) {
+  bool a = true;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) a = a && c.m[i];
+  return a;
 }
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 
-// The first and the last aligned group of four columns (aligned relative to
+// The first and the last aligned group of NV columns (aligned relative to
 // the buffer's first column bx0) that meet [x0, x1), a non-empty range of
 // the buffer's columns; such groups lie inside the allocated row.
+template <int NV = 4>
 __device__ __forceinline__ int clamp_group(int xl, int x0, int x1, int bx0) {
-  const int g0 = x0 - ((x0 - bx0) & 3);
-  const int g1 = (x1 - 1) - ((x1 - 1 - bx0) & 3);
+  const int g0 = x0 - ((x0 - bx0) & (NV - 1));
+  const int g1 = (x1 - 1) - ((x1 - 1 - bx0) & (NV - 1));
   return min(max(xl, g0), g1);
 }
 
 // Loads a group unconditionally: the caller passes a row and a group that
 // the buffer holds (clamped into the loadable box), so the load needs no
 // branch and stays in flight until its value is used; cells outside the box
-// are zeroed later by mask4, where the value is consumed.  STREAM marks
-// data read once: u^{n-1} in the in-place T = 1 update, where a
+// are zeroed later by mask_group, where the value is consumed.  STREAM
+// marks data read once: u^{n-1} in the in-place T = 1 update, where a
 // nontemporal load keeps it from displacing the u^n rows that neighbouring
 // tiles re-read from cache (15% faster than a cached load).  For T > 1 the
 // u^{n-1} rows in the overlap of vertically adjacent segments are read
 // twice too, and a cached load is 1-2% faster at T = 7, 8.
-template <bool STREAM>
-__device__ __forceinline__ float4 load4(const float *base, int32_t by0, int32_t bx0,
-                                        int32_t pitch, int row, int xg) {
-  const f4v *p = reinterpret_cast<const f4v *>(base + static_cast<int64_t>(row - by0) * pitch +
+template <class PR, bool STREAM>
+__device__ __forceinline__ typename PR::Raw load_group(const void *base, int32_t by0, int32_t bx0,
+                                                       int32_t pitch, int row, int xg) {
+  using Raw = typename PR::Raw;
+  const Raw *p = reinterpret_cast<const Raw *>(static_cast<const typename PR::E *>(base) +
+                                               static_cast<int64_t>(row - by0) * pitch +
                                                (xg - bx0));
-  const f4v r = STREAM ? __builtin_nontemporal_load(p) : *p;
-  return make_float4(r.x, r.y, r.z, r.w);
+  return STREAM ? __builtin_nontemporal_load(p) : *p;
 }
 
-// Zero outside the loadable box: the row (wave-uniform) and the lane's
-// columns.
-__device__ __forceinline__ float4 mask4(float4 v, bool row_ok, const Cols &c) {
-  v.x = (row_ok && c.m0) ? v.x : 0.0f;
-  v.y = (row_ok && c.m1) ? v.y : 0.0f;
-  v.z = (row_ok && c.m2) ? v.z : 0.0f;
-  v.w = (row_ok && c.m3) ? v.w : 0.0f;
+// Widens a loaded group, zero outside the loadable box: the row
+// (wave-uniform) and the lane's columns.
+template <class PR>
+__device__ __forceinline__ Vec<typename PR::F, PR::NV> mask_group(const typename PR::Raw &r,
+                                                                  bool row_ok, const Cols &c) {
+  Vec<typename PR::F, PR::NV> v;
+#pragma unroll
+  for (int i = 0; i < PR::NV; ++i)
+    v.v[i] = (row_ok && c.m[i]) ? PR::widen(r[i]) : typename PR::F(0);
   return v;
 }
 
-// Stores the lane's group of `row` where the output mask allows (nontemporal:
-// nothing in this launch reads it back).  Partial groups occur only at a
-// chunk's left or right edge; their other columns are halo cells of this
-// chunk's own buffer that no wave writes during the launch, so they are read
-// and written back unchanged (one 16-byte store).
-__device__ __forceinline__ void store4(float *base, int32_t by0, int32_t bx0, int32_t pitch,
-                                       int row, int xl, const Cols &c, const float4 &v) {
+// Stores the lane's group of `row` where the output mask allows, narrowed
+// to the storage type (nontemporal: nothing in this launch reads it back).
+// Partial groups occur only at a chunk's left or right edge; their other
+// columns are halo cells of this chunk's own buffer that no wave writes
+// during the launch, so they are read and written back unchanged (one
+// vector store).
+template <class PR>
+__device__ __forceinline__ void store_group(void *base, int32_t by0, int32_t bx0, int32_t pitch,
+                                            int row, int xl, const Cols &c,
+                                            const Vec<typename PR::F, PR::NV> &v) {
+  using Raw = typename PR::Raw;
   if (!c.any) return;
-  f4v *p = reinterpret_cast<f4v *>(base + static_cast<int64_t>(row - by0) * pitch + (xl - bx0));
-  f4v w = {v.x, v.y, v.z, v.w};
-  if (!(c.m0 && c.m1 && c.m2 && c.m3)) {
-    const f4v o = *p;
-    w.x = c.m0 ? v.x : o.x;
-    w.y = c.m1 ? v.y : o.y;
-    w.z = c.m2 ? v.z : o.z;
-    w.w = c.m3 ? v.w : o.w;
+  Raw *p = reinterpret_cast<Raw *>(static_cast<typename PR::E *>(base) +
+                                   static_cast<int64_t>(row - by0) * pitch + (xl - bx0));
+  Raw w;
+#pragma unroll
+  for (int i = 0; i < PR::NV; ++i) w[i] = PR::narrow(v.v[i]);
+  if (!all_of<PR::NV>(c)) {
+    const Raw o = *p;
+#pragma unroll
+    for (int i = 0; i < PR::NV; ++i) w[i] = c.m[i] ? w[i] : o[i];
   }
   __builtin_nontemporal_store(w, p);
 }
 
-__device__ __forceinline__ float4 force_zero(float4 v, bool row_in, const Cols &d) {
-  v.x = (row_in && d.m0) ? v.x : 0.0f;
-  v.y = (row_in && d.m1) ? v.y : 0.0f;
-  v.z = (row_in && d.m2) ? v.z : 0.0f;
-  v.w = (row_in && d.m3) ? v.w : 0.0f;
+template <class F, int NV>
+__device__ __forceinline__ Vec<F, NV> force_zero(Vec<F, NV> v, bool row_in, const Cols &d) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v.v[i] = (row_in && d.m[i]) ? v.v[i] : F(0);
   return v;
 }
 
 // Advances one tile (segment `seg`, strip `strip` of chunk C) by T steps.
-// Strips are 256 columns wide and overlap their neighbours by A columns on
-// each side (A >= T, a multiple of 4); each writes SW = 256 - 2A columns.
+// Strips are 64*NV columns wide and overlap their neighbours by A columns on
+// each side (A >= T, a multiple of NV); each writes SW = 64*NV - 2A columns.
 // The descriptors are copied into registers once: read through a reference
 // inside the loop, they would be reloaded after every store (the compiler
 // cannot rule out that a store aliases them).
-template <int T, bool IN_PLACE>
-__device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, float r2,
+template <class PR, int T, bool IN_PLACE>
+__device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, typename PR::F r2,
                                      int tile_rows, int seg, int strip, int lane, int A) {
+  constexpr int NV = PR::NV;
+  using F = typename PR::F;
+  using V = Vec<F, NV>;
+  using Raw = typename PR::Raw;
   const Chunk C = Cref;
   const Domain D = Dref;
-  const int SW = 256 - 2 * A;
+  const int SW = 64 * NV - 2 * A;
   const int y0 = C.cy0 + seg * tile_rows;
   const int y1 = min(C.cy1, y0 + tile_rows);
   const int xs = C.xs0 + strip * SW;
-  const int xl = xs + 4 * lane;
+  const int xl = xs + NV * lane;
   const int vx0 = max(C.cx0, xs + A);
   const int vx1 = min(C.cx1, xs + A + SW);
 
-  const Cols dom = cols_of(xl, D.gx0, D.gx1);
-  const Cols out = cols_of(xl, vx0, vx1);
-  const Cols lc = cols_of(xl, C.lc_x0, C.lc_x1);
+  const Cols dom = cols_of<NV>(xl, D.gx0, D.gx1);
+  const Cols out = cols_of<NV>(xl, vx0, vx1);
+  const Cols lc = cols_of<NV>(xl, C.lc_x0, C.lc_x1);
   // In place, u^{n-1} is read only where this lane writes.
   const int lpy0 = IN_PLACE ? max(C.lp_y0, y0) : C.lp_y0;
   const int lpy1 = IN_PLACE ? min(C.lp_y1, y1) : C.lp_y1;
-  const Cols lp = cols_of(xl, IN_PLACE ? max(C.lp_x0, vx0) : C.lp_x0,
-                          IN_PLACE ? min(C.lp_x1, vx1) : C.lp_x1);
+  const Cols lp = cols_of<NV>(xl, IN_PLACE ? max(C.lp_x0, vx0) : C.lp_x0,
+                              IN_PLACE ? min(C.lp_x1, vx1) : C.lp_x1);
 
-  // a strip whose 256 columns all lie in the domain needs no column mask
-  const bool interior_cols = xs >= D.gx0 && xs + 256 <= D.gx1;
+  // a strip whose columns all lie in the domain needs no column mask
+  const bool interior_cols = xs >= D.gx0 && xs + 64 * NV <= D.gx1;
 
   // ring[k][s]: the last three rows of level k in rotating slots; at the
   // unrolled copy u the newest row goes to slot u, the middle one is in
   // (u+2)%3 and the oldest in (u+1)%3
-  float4 ring[T][3];
+  V ring[T][3];
 #pragma unroll
-  for (int k = 0; k < T; ++k) ring[k][0] = ring[k][1] = ring[k][2] = zero4();
+  for (int k = 0; k < T; ++k) ring[k][0] = ring[k][1] = ring[k][2] = zero_vec<F, NV>();
 
   const int first = y0 - T;
   const int nrows = (y1 - y0) + 2 * T;
   // loads go to rows and groups clamped into the loadable box (never empty:
   // it holds the chunk's rows and columns), masks apply on use
-  const int xgc = clamp_group(xl, C.lc_x0, C.lc_x1, C.ic_x0);
-  const int xgp = clamp_group(xl, IN_PLACE ? max(C.lp_x0, vx0) : C.lp_x0,
-                              IN_PLACE ? min(C.lp_x1, vx1) : C.lp_x1, C.ip_x0);
+  const int xgc = clamp_group<NV>(xl, C.lc_x0, C.lc_x1, C.ic_x0);
+  const int xgp = clamp_group<NV>(xl, IN_PLACE ? max(C.lp_x0, vx0) : C.lp_x0,
+                                  IN_PLACE ? min(C.lp_x1, vx1) : C.lp_x1, C.ip_x0);
   auto row_c = [&](int r) { return min(max(r, C.lc_y0), C.lc_y1 - 1); };
   auto row_p = [&](int r) { return min(max(r, lpy0), lpy1 - 1); };
-  float4 q1[kPrefetch], q0[kPrefetch];
+  Raw q1[kPrefetch], q0[kPrefetch];
 #pragma unroll
   for (int u = 0; u < kPrefetch; ++u) {
-    q1[u] = load4<false>(C.in_cur, C.ic_y0, C.ic_x0, C.ic_pitch, row_c(first + u), xgc);
-    q0[u] = load4<IN_PLACE>(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch, row_p(first + u - 1), xgp);
+    q1[u] = load_group<PR, false>(C.in_cur, C.ic_y0, C.ic_x0, C.ic_pitch, row_c(first + u), xgc);
+    q0[u] = load_group<PR, IN_PLACE>(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch,
+                                     row_p(first + u - 1), xgp);
   }
 
   // Stores are issued one loop iteration late.  One counter tracks both
@@ -248,7 +288,7 @@ __device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, floa
   constexpr bool DEFER = !IN_PLACE;
   // level-T rows of the previous iteration (u^{n+T}, u^{n+T-1}) and whether
   // each lies in the tile's output rows (wave-uniform)
-  float4 d1[kUnroll], d0[kUnroll];
+  V d1[kUnroll], d0[kUnroll];
   bool dok[kUnroll];
 #pragma unroll
   for (int uu = 0; uu < kUnroll; ++uu) dok[uu] = false;
@@ -264,8 +304,8 @@ __device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, floa
       for (int uu = 0; uu < kUnroll; ++uu) {
         if (dok[uu]) {
           const int r = first + jb - kUnroll + uu - T;
-          store4(C.out_cur, C.oc_y0, C.oc_x0, C.oc_pitch, r, xl, out, d1[uu]);
-          store4(C.out_prev, C.op_y0, C.op_x0, C.op_pitch, r, xl, out, d0[uu]);
+          store_group<PR>(C.out_cur, C.oc_y0, C.oc_x0, C.oc_pitch, r, xl, out, d1[uu]);
+          store_group<PR>(C.out_prev, C.op_y0, C.op_x0, C.op_pitch, r, xl, out, d0[uu]);
         }
       }
     }
@@ -274,15 +314,16 @@ __device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, floa
       const int u = uu % kPrefetch;
       const int NEW = u, MID = (u + 2) % 3, OLD = (u + 1) % 3;
       const int i = first + jb + uu;  // row of level 0 arriving now
-      ring[0][NEW] = mask4(q1[u], i >= C.lc_y0 && i < C.lc_y1, lc);
-      float4 pv = mask4(q0[u], i - 1 >= lpy0 && i - 1 < lpy1, lp);
-      q1[u] = load4<false>(C.in_cur, C.ic_y0, C.ic_x0, C.ic_pitch, row_c(i + kPrefetch), xgc);
-      q0[u] = load4<IN_PLACE>(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch, row_p(i + kPrefetch - 1),
-                          xgp);
+      ring[0][NEW] = mask_group<PR>(q1[u], i >= C.lc_y0 && i < C.lc_y1, lc);
+      V pv = mask_group<PR>(q0[u], i - 1 >= lpy0 && i - 1 < lpy1, lp);
+      q1[u] = load_group<PR, false>(C.in_cur, C.ic_y0, C.ic_x0, C.ic_pitch,
+                                    row_c(i + kPrefetch), xgc);
+      q0[u] = load_group<PR, IN_PLACE>(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch,
+                                       row_p(i + kPrefetch - 1), xgp);
 #pragma unroll
       for (int k = 1; k <= T; ++k) {
         const int r = i - k;  // row of level k computed now
-        float4 nv = step4(ring[k - 1][OLD], ring[k - 1][MID], ring[k - 1][NEW], pv, r2);
+        V nv = step_group<PR>(ring[k - 1][OLD], ring[k - 1][MID], ring[k - 1][NEW], pv, r2);
         const bool row_in = r >= D.gy0 && r < D.gy1;  // wave-uniform
         if (!(row_in && interior_cols)) nv = force_zero(nv, row_in, dom);
         if (k < T) {
@@ -293,9 +334,10 @@ __device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, floa
           d1[uu] = nv;
           d0[uu] = ring[T - 1][MID];
         } else if (r >= y0 && r < y1) {
-          store4(C.out_cur, C.oc_y0, C.oc_x0, C.oc_pitch, r, xl, out, nv);
+          store_group<PR>(C.out_cur, C.oc_y0, C.oc_x0, C.oc_pitch, r, xl, out, nv);
           if (!IN_PLACE)
-            store4(C.out_prev, C.op_y0, C.op_x0, C.op_pitch, r, xl, out, ring[T - 1][MID]);
+            store_group<PR>(C.out_prev, C.op_y0, C.op_x0, C.op_pitch, r, xl, out,
+                            ring[T - 1][MID]);
         }
       }
     }
@@ -306,8 +348,8 @@ __device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, floa
     for (int uu = 0; uu < kUnroll; ++uu) {
       if (dok[uu]) {
         const int r = first + jlast + uu - T;
-        store4(C.out_cur, C.oc_y0, C.oc_x0, C.oc_pitch, r, xl, out, d1[uu]);
-        store4(C.out_prev, C.op_y0, C.op_x0, C.op_pitch, r, xl, out, d0[uu]);
+        store_group<PR>(C.out_cur, C.oc_y0, C.oc_x0, C.oc_pitch, r, xl, out, d1[uu]);
+        store_group<PR>(C.out_prev, C.op_y0, C.op_x0, C.op_pitch, r, xl, out, d0[uu]);
       }
     }
   }

@@ -13,6 +13,7 @@
 #include <cstring>
 
 #include "ccl_internal.h"
+#include "prec.h"
 #include "wave3d_cell.h"
 
 namespace ccl {
@@ -27,8 +28,8 @@ constexpr int kMaxChunksPerLaunch = 16;
 constexpr int kRows = CCL_W3_ROWS;  // rows per wave tile
 
 struct W3Chunk {
-  const float *in_cur;
-  float *io_prev;  // u^{n-1} in, u^{n+1} out
+  const void *in_cur;
+  void *io_prev;  // u^{n-1} in, u^{n+1} out
   int32_t ic_z0, ic_y0, ic_x0;
   int32_t ip_z0, ip_y0, ip_x0;
   int64_t ic_pz, ic_py;  // element strides of dims 0 and 1
@@ -44,53 +45,75 @@ struct W3Args {
   int32_t nchunks;
   int32_t total_tiles;
   int32_t tile_planes;
-  float r2;
+  float r2f;   // r2 rounded to float (float arithmetic)
+  double r2d;  // r2 as given (double arithmetic)
   W3Chunk ch[kMaxChunksPerLaunch];
 };
 
-__device__ __forceinline__ float dpp_from_left(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
-}
-__device__ __forceinline__ float dpp_from_right(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
-}
+template <class F>
+__device__ __forceinline__ F r2_of(const W3Args &a);
+template <>
+__device__ __forceinline__ float r2_of<float>(const W3Args &a) { return a.r2f; }
+template <>
+__device__ __forceinline__ double r2_of<double>(const W3Args &a) { return a.r2d; }
 
-__device__ __forceinline__ float4 zero4() { return make_float4(0.f, 0.f, 0.f, 0.f); }
-
+template <class PR>
 struct Plane {
-  float4 v[kRows];
+  Vec<typename PR::F, PR::NV> v[kRows];
 };
 
-// Which of the lane's four columns [xl, xl+4) lie in [x0, x1).  Groups are
-// aligned fours relative to the buffer and pitches are multiples of 4 that
-// cover the extent, so a group meeting [x0, x1) lies inside its row.
+// Which of the lane's NV columns [xl, xl+NV) lie in [x0, x1).  Groups are
+// aligned NV-tuples relative to the buffer and pitches are multiples of NV
+// that cover the extent, so a group meeting [x0, x1) lies inside its row.
 struct Cols {
-  bool any, m0, m1, m2, m3;
+  bool any;
+  bool m[4];
 };
 
+template <int NV>
 __device__ __forceinline__ Cols cols_of(int xl, int x0, int x1) {
   Cols c;
-  c.m0 = xl + 0 >= x0 && xl + 0 < x1;
-  c.m1 = xl + 1 >= x0 && xl + 1 < x1;
-  c.m2 = xl + 2 >= x0 && xl + 2 < x1;
-  c.m3 = xl + 3 >= x0 && xl + 3 < x1;
-  c.any = c.m0 || c.m1 || c.m2 || c.m3;
+  c.any = false;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    c.m[i] = i < NV && xl + i >= x0 && xl + i < x1;
+    c.any = c.any || c.m[i];
+  }
   return c;
 }
 
-__device__ __forceinline__ float4 ld4(const float *base, int64_t pz, int64_t py, int z0, int y0,
-                                      int x0, int z, int y, int xl, int lz0, int lz1, int ly0,
-                                      int ly1, const Cols &c) {
-  float4 v = zero4();
+template <int NV>
+__device__ __forceinline__ bool all_of(const Cols &c) {
+  bool a = true;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) a = a && c.m[i];
+  return a;
+}
+
+template <class PR>
+__device__ __forceinline__ Vec<typename PR::F, PR::NV> zero_v() {
+  Vec<typename PR::F, PR::NV> z;
+#pragma unroll
+  for (int i = 0; i < PR::NV; ++i) z.v[i] = typename PR::F(0);
+  return z;
+}
+
+template <class PR>
+__device__ __forceinline__ Vec<typename PR::F, PR::NV> ld_group(
+    const void *base, int64_t pz, int64_t py, int z0, int y0, int x0, int z, int y, int xl,
+    int lz0, int lz1, int ly0, int ly1, const Cols &c) {
+  using Raw = typename PR::Raw;
+  Vec<typename PR::F, PR::NV> v = zero_v<PR>();
   if (z < lz0 || z >= lz1 || y < ly0 || y >= ly1) return v;  // wave-uniform
+  Raw r;
+#pragma unroll
+  for (int i = 0; i < PR::NV; ++i) r[i] = typename PR::E(0);
   if (c.any)
-    v = *reinterpret_cast<const float4 *>(base + static_cast<int64_t>(z - z0) * pz +
-                                          static_cast<int64_t>(y - y0) * py + (xl - x0));
-  if (c.m0 && c.m1 && c.m2 && c.m3) return v;  // folds away when all are known true
-  v.x = c.m0 ? v.x : 0.0f;
-  v.y = c.m1 ? v.y : 0.0f;
-  v.z = c.m2 ? v.z : 0.0f;
-  v.w = c.m3 ? v.w : 0.0f;
+    r = *reinterpret_cast<const Raw *>(static_cast<const typename PR::E *>(base) +
+                                       static_cast<int64_t>(z - z0) * pz +
+                                       static_cast<int64_t>(y - y0) * py + (xl - x0));
+#pragma unroll
+  for (int i = 0; i < PR::NV; ++i) v.v[i] = c.m[i] ? PR::widen(r[i]) : typename PR::F(0);
   return v;
 }
 
@@ -100,11 +123,17 @@ __device__ __forceinline__ int xcd_block(int bid, int nblocks) {
   return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + idx;
 }
 
-// XIN: the strip's 256 columns lie inside the loadable and the output
-// column ranges (every strip of a domain whose width is a multiple of 256),
-// so loads and stores need no per-element column masks.
-template <bool XIN>
+// XIN: the strip's 64*NV columns lie inside the loadable and the output
+// column ranges (every strip of a domain whose width is a multiple of the
+// strip width), so loads and stores need no per-element column masks.
+template <class PR, bool XIN>
 __global__ __launch_bounds__(kThreads) void wave3d_kernel(const W3Args a) {
+  constexpr int NV = PR::NV;
+  constexpr int SWD = 64 * NV;  // strip width
+  using F = typename PR::F;
+  using V = Vec<F, NV>;
+  using E = typename PR::E;
+  using Raw = typename PR::Raw;
   const int lane = threadIdx.x & 63;
   const int tile = __builtin_amdgcn_readfirstlane(
       xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
@@ -123,64 +152,69 @@ __global__ __launch_bounds__(kThreads) void wave3d_kernel(const W3Args a) {
   const int z0 = C.cz0 + seg * a.tile_planes;
   const int z1 = min(C.cz1, z0 + a.tile_planes);
   const int yb = C.cy0 + rb * kRows;
-  const int xs = C.xs0 + strip * 256;
-  const int xl = xs + 4 * lane;
-  const float r2 = a.r2;
+  const int xs = C.xs0 + strip * SWD;
+  const int xl = xs + NV * lane;
+  const F r2 = r2_of<F>(a);
 
+  Cols all;
+  all.any = true;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) all.m[i] = i < NV;
   // u^{n-1} is read (and written) only inside this tile's own output cells
   const int oy1 = min(C.cy1, yb + kRows);
-  const Cols out = XIN ? Cols{true, true, true, true, true} : cols_of(xl, C.cx0, C.cx1);
-  const Cols lc = XIN ? Cols{true, true, true, true, true} : cols_of(xl, C.lc_x0, C.lc_x1);
-  const int edge_x = lane == 0 ? xs - 1 : xs + 256;
+  const Cols out = XIN ? all : cols_of<NV>(xl, C.cx0, C.cx1);
+  const Cols lc = XIN ? all : cols_of<NV>(xl, C.lc_x0, C.lc_x1);
+  const int edge_x = lane == 0 ? xs - 1 : xs + SWD;
   const bool edge_lane = lane == 0 || lane == 63;
 
-  Plane zm, zc, zp;  // ring: planes r-1, r, r+1 (r = centre)
-  float4 hlo_c, hhi_c, hlo_n, hhi_n;  // halo rows of the centre / newest plane
-  float ed_c[kRows], ed_n[kRows];     // outer columns of the centre / newest plane
+  Plane<PR> zm, zc, zp;  // ring: planes r-1, r, r+1 (r = centre)
+  V hlo_c, hhi_c, hlo_n, hhi_n;  // halo rows of the centre / newest plane
+  F ed_c[kRows], ed_n[kRows];    // outer columns of the centre / newest plane
 #pragma unroll
   for (int j = 0; j < kRows; ++j) {
-    zm.v[j] = zc.v[j] = zp.v[j] = zero4();
-    ed_c[j] = ed_n[j] = 0.0f;
+    zm.v[j] = zc.v[j] = zp.v[j] = zero_v<PR>();
+    ed_c[j] = ed_n[j] = F(0);
   }
-  hlo_c = hhi_c = hlo_n = hhi_n = zero4();
+  hlo_c = hhi_c = hlo_n = hhi_n = zero_v<PR>();
 
-  auto load_plane = [&](int z, Plane &pl, float4 &hlo, float4 &hhi, float *ed) {
+  auto load_plane = [&](int z, Plane<PR> &pl, V &hlo, V &hhi, F *ed) {
 #pragma unroll
     for (int j = 0; j < kRows; ++j)
-      pl.v[j] = ld4(C.in_cur, C.ic_pz, C.ic_py, C.ic_z0, C.ic_y0, C.ic_x0, z, yb + j, xl, C.lc_z0,
-                    C.lc_z1, C.lc_y0, C.lc_y1, lc);
-    hlo = ld4(C.in_cur, C.ic_pz, C.ic_py, C.ic_z0, C.ic_y0, C.ic_x0, z, yb - 1, xl, C.lc_z0, C.lc_z1,
-              C.lc_y0, C.lc_y1, lc);
-    hhi = ld4(C.in_cur, C.ic_pz, C.ic_py, C.ic_z0, C.ic_y0, C.ic_x0, z, yb + kRows, xl, C.lc_z0,
-              C.lc_z1, C.lc_y0, C.lc_y1, lc);
+      pl.v[j] = ld_group<PR>(C.in_cur, C.ic_pz, C.ic_py, C.ic_z0, C.ic_y0, C.ic_x0, z, yb + j, xl,
+                             C.lc_z0, C.lc_z1, C.lc_y0, C.lc_y1, lc);
+    hlo = ld_group<PR>(C.in_cur, C.ic_pz, C.ic_py, C.ic_z0, C.ic_y0, C.ic_x0, z, yb - 1, xl,
+                       C.lc_z0, C.lc_z1, C.lc_y0, C.lc_y1, lc);
+    hhi = ld_group<PR>(C.in_cur, C.ic_pz, C.ic_py, C.ic_z0, C.ic_y0, C.ic_x0, z, yb + kRows, xl,
+                       C.lc_z0, C.lc_z1, C.lc_y0, C.lc_y1, lc);
     const bool zin = z >= C.lc_z0 && z < C.lc_z1;
     const bool xin = edge_x >= C.lc_x0 && edge_x < C.lc_x1;
 #pragma unroll
     for (int j = 0; j < kRows; ++j) {
       const int y = yb + j;
-      float e = 0.0f;
+      F e = F(0);
       if (edge_lane && zin && xin && y >= C.lc_y0 && y < C.lc_y1)
-        e = C.in_cur[static_cast<int64_t>(z - C.ic_z0) * C.ic_pz +
-                     static_cast<int64_t>(y - C.ic_y0) * C.ic_py + (edge_x - C.ic_x0)];
+        e = PR::widen(static_cast<const E *>(C.in_cur)[static_cast<int64_t>(z - C.ic_z0) * C.ic_pz +
+                                                       static_cast<int64_t>(y - C.ic_y0) * C.ic_py +
+                                                       (edge_x - C.ic_x0)]);
       ed[j] = e;
     }
   };
 
-  auto load_prev = [&](int z, float4 *pv) {
+  auto load_prev = [&](int z, V *pv) {
 #pragma unroll
     for (int j = 0; j < kRows; ++j)
-      pv[j] = ld4(C.io_prev, C.ip_pz, C.ip_py, C.ip_z0, C.ip_y0, C.ip_x0, z, yb + j, xl, z0, z1,
-                  yb, oy1, out);
+      pv[j] = ld_group<PR>(C.io_prev, C.ip_pz, C.ip_py, C.ip_z0, C.ip_y0, C.ip_x0, z, yb + j, xl,
+                           z0, z1, yb, oy1, out);
   };
 
   const int i0 = z0 - 1;
   // prime: plane z0-1 becomes the centre plane after the first shift
   load_plane(i0, zp, hlo_n, hhi_n, ed_n);
-  Plane pn;
-  float4 plo, phi;
-  float ped[kRows];
+  Plane<PR> pn;
+  V plo, phi;
+  F ped[kRows];
   load_plane(i0 + 1, pn, plo, phi, ped);
-  float4 pv[kRows], pvn[kRows];
+  V pv[kRows], pvn[kRows];
   load_prev(i0, pvn);
 
   for (int i = i0 + 1; i <= z1; ++i) {
@@ -208,31 +242,32 @@ __global__ __launch_bounds__(kThreads) void wave3d_kernel(const W3Args a) {
       for (int j = 0; j < kRows; ++j) {
         const int y = yb + j;
         if (y >= oy1) continue;  // wave-uniform
-        const float4 cc = zc.v[j];
-        const float4 ym = j == 0 ? hlo_c : zc.v[j - 1];
-        const float4 yp = j == kRows - 1 ? hhi_c : zc.v[j + 1];
-        const float4 zmv = zm.v[j], zpv = zp.v[j];
-        const float left_n = dpp_from_left(cc.w);
-        const float right_n = dpp_from_right(cc.x);
-        const float xm0 = lane == 0 ? ed_c[j] : left_n;
-        const float xp3 = lane == 63 ? ed_c[j] : right_n;
-        float4 o;
-        o.x = cell3(zmv.x, zpv.x, ym.x, yp.x, xm0, cc.y, cc.x, pv[j].x, r2);
-        o.y = cell3(zmv.y, zpv.y, ym.y, yp.y, cc.x, cc.z, cc.y, pv[j].y, r2);
-        o.z = cell3(zmv.z, zpv.z, ym.z, yp.z, cc.y, cc.w, cc.z, pv[j].z, r2);
-        o.w = cell3(zmv.w, zpv.w, ym.w, yp.w, cc.z, xp3, cc.w, pv[j].w, r2);
+        const V cc = zc.v[j];
+        const V ym = j == 0 ? hlo_c : zc.v[j - 1];
+        const V yp = j == kRows - 1 ? hhi_c : zc.v[j + 1];
+        const V zmv = zm.v[j], zpv = zp.v[j];
+        const F left_n = dpp_move<0x138>(cc.v[NV - 1]);   // wave_shr:1
+        const F right_n = dpp_move<0x130>(cc.v[0]);       // wave_shl:1
+        const F xm0 = lane == 0 ? ed_c[j] : left_n;
+        const F xpl = lane == 63 ? ed_c[j] : right_n;
+        Raw o;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+          const F xm = q == 0 ? xm0 : cc.v[q > 0 ? q - 1 : 0];
+          const F xp = q == NV - 1 ? xpl : cc.v[q < NV - 1 ? q + 1 : 0];
+          o[q] = PR::narrow(cell3(zmv.v[q], zpv.v[q], ym.v[q], yp.v[q], xm, xp, cc.v[q],
+                                  pv[j].v[q], r2));
+        }
         if (out.any) {
           // partial groups only at the chunk's x edges: merge with the
-          // unchanged halo cells of this buffer, one 16-byte store
-          float4 *p = reinterpret_cast<float4 *>(
-              C.io_prev + static_cast<int64_t>(r - C.ip_z0) * C.ip_pz +
+          // unchanged halo cells of this buffer, one vector store
+          Raw *p = reinterpret_cast<Raw *>(
+              static_cast<E *>(C.io_prev) + static_cast<int64_t>(r - C.ip_z0) * C.ip_pz +
               static_cast<int64_t>(y - C.ip_y0) * C.ip_py + (xl - C.ip_x0));
-          if (!(out.m0 && out.m1 && out.m2 && out.m3)) {
-            const float4 q = *p;
-            o.x = out.m0 ? o.x : q.x;
-            o.y = out.m1 ? o.y : q.y;
-            o.z = out.m2 ? o.z : q.z;
-            o.w = out.m3 ? o.w : q.w;
+          if (!all_of<NV>(out)) {
+            const Raw q = *p;
+#pragma unroll
+            for (int e = 0; e < NV; ++e) o[e] = out.m[e] ? o[e] : q[e];
           }
           *p = o;
         }
@@ -241,21 +276,36 @@ __global__ __launch_bounds__(kThreads) void wave3d_kernel(const W3Args a) {
   }
 }
 
+template <class PR>
+const void *kernel_of(bool xin) {
+  return xin ? reinterpret_cast<const void *>(&wave3d_kernel<PR, true>)
+             : reinterpret_cast<const void *>(&wave3d_kernel<PR, false>);
+}
+
+const void *kernel_for(int32_t dtype, bool xin) {
+  switch (dtype) {
+    case CCL_DTYPE_F64: return kernel_of<P64>(xin);
+    case CCL_DTYPE_BF16: return kernel_of<PB16>(xin);
+    case CCL_DTYPE_F16: return kernel_of<PH16>(xin);
+    default: return kernel_of<P32>(xin);
+  }
+}
+
 bool fits_i32(int64_t v) { return v >= INT32_MIN && v <= INT32_MAX; }
 
-int64_t wave_slots3d() {
-  static int64_t cached = 0;
-  if (cached > 0) return cached;
+int64_t wave_slots3d(int32_t dtype = CCL_DTYPE_F32) {
+  static int64_t cached[4] = {};
+  if (dtype < 0 || dtype > 3) dtype = CCL_DTYPE_F32;
+  if (cached[dtype] > 0) return cached[dtype];
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void *>(&wave3d_kernel<false>), kThreads, 0) !=
-              hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_for(dtype, false), kThreads,
+                                                    0) != hipSuccess ||
       per_cu < 1)
     return 1024;
-  cached = static_cast<int64_t>(cus) * per_cu * kWavesPerBlock;
-  return cached;
+  cached[dtype] = static_cast<int64_t>(cus) * per_cu * kWavesPerBlock;
+  return cached[dtype];
 }
 
 }  // namespace
@@ -280,19 +330,26 @@ int32_t wave3d_plan_planes(int64_t nz, int64_t ny, int64_t nx, int32_t K, int32_
                         waves_of);
 }
 
-ccl_status launch_wave3d(int32_t depth, bool in_place, float r2, int32_t tile_planes,
-                         const WaveChunkPlan *plans, int32_t nplans, hipStream_t stream) {
+ccl_status launch_wave3d(int32_t dtype, int32_t depth, bool in_place, double r2,
+                         int32_t tile_planes, const WaveChunkPlan *plans, int32_t nplans,
+                         hipStream_t stream) {
   if (depth > 1) {
     if (in_place) return fail(CCL_E_INVALID, "in-place update needs T == 1");
-    return launch_wave3d_tb(depth, r2, tile_planes, plans, nplans, stream);
+    return launch_wave3d_tb(dtype, depth, r2, tile_planes, plans, nplans, stream);
   }
+  const int NV = dtype_group(dtype);
+  const int esize = dtype_bytes(dtype);
+  if (esize == 0) return fail(CCL_E_INVALID, "unknown dtype %d", dtype);
+  const int SWD = 64 * NV;
+  const uintptr_t amask = static_cast<uintptr_t>(NV * esize - 1);
   if (!in_place) return fail(CCL_E_INVALID, "the one-step 3D kernel updates in place");
   for (int first = 0; first < nplans; first += kMaxChunksPerLaunch) {
     const int n = std::min(kMaxChunksPerLaunch, nplans - first);
     W3Args a;
     memset(&a, 0, sizeof(a));
     a.nchunks = n;
-    a.r2 = r2;
+    a.r2f = static_cast<float>(r2);
+    a.r2d = r2;
     if (tile_planes > 0) {
       a.tile_planes = tile_planes;
     } else {
@@ -303,12 +360,12 @@ ccl_status launch_wave3d(int32_t depth, bool in_place, float r2, int32_t tile_pl
         int64_t w = 0;
         for (int k = 0; k < n; ++k) {
           const Box &cb = plans[first + k].chunk;
-          w += ((cb.hi[0] - cb.lo[0] + p - 1) / p) * ((cb.hi[2] - cb.lo[2] + 255) / 256) *
+          w += ((cb.hi[0] - cb.lo[0] + p - 1) / p) * ((cb.hi[2] - cb.lo[2] + SWD - 1) / SWD) *
                ((cb.hi[1] - cb.lo[1] + kRows - 1) / kRows);
         }
         return w;
       };
-      a.tile_planes = plan_tile_rows(wave_slots3d(), 1, 4,
+      a.tile_planes = plan_tile_rows(wave_slots3d(dtype), 1, 4,
                                      static_cast<int32_t>(std::max<int64_t>(zmax, 4)), waves_of);
     }
     int64_t tiles = 0;
@@ -344,30 +401,30 @@ ccl_status launch_wave3d(int32_t depth, bool in_place, float r2, int32_t tile_pl
       C.cx0 = static_cast<int32_t>(P.chunk.lo[2]);
       C.cx1 = static_cast<int32_t>(P.chunk.hi[2]);
       // strip 0 starts at the chunk's first column aligned down to a
-      // multiple of 4 relative to the u^n buffer, so every lane's group of
-      // four columns is one 16-byte access; the output mask keeps the
+      // multiple of NV relative to the u^n buffer, so every lane's group of
+      // NV columns is one aligned vector access; the output mask keeps the
       // columns left of the chunk unchanged
-      const int64_t mis = (((P.chunk.lo[2] - P.in_cur.off[2]) % 4) + 4) % 4;
+      const int64_t mis = (((P.chunk.lo[2] - P.in_cur.off[2]) % NV) + NV) % NV;
       const int64_t xs0 = P.chunk.lo[2] - mis;
       C.xs0 = static_cast<int32_t>(xs0);
       const int64_t nx = P.chunk.hi[2] - xs0;
       const int64_t ny = P.chunk.hi[1] - P.chunk.lo[1];
       const int64_t nz = P.chunk.hi[0] - P.chunk.lo[0];
-      C.nstrips = static_cast<int32_t>((nx + 255) / 256);
+      C.nstrips = static_cast<int32_t>((nx + SWD - 1) / SWD);
       C.nrowblk = static_cast<int32_t>((ny + kRows - 1) / kRows);
       const int64_t segs = (nz + a.tile_planes - 1) / a.tile_planes;
       {
-        // both buffers must hold the strips' groups at 16-byte boundaries
+        // both buffers must hold the strips' groups at aligned boundaries
         const int64_t rp = xs0 - P.in_prev.off[2];
-        if ((((rp % 4) + 4) % 4) != 0 || P.in_cur.pitch[0] % 4 != 0 ||
-            P.in_cur.pitch[1] % 4 != 0 || P.in_prev.pitch[0] % 4 != 0 ||
-            P.in_prev.pitch[1] % 4 != 0 ||
-            (reinterpret_cast<uintptr_t>(P.in_cur.base) & 15u) != 0 ||
-            (reinterpret_cast<uintptr_t>(P.in_prev.base) & 15u) != 0)
+        if ((((rp % NV) + NV) % NV) != 0 || P.in_cur.pitch[0] % NV != 0 ||
+            P.in_cur.pitch[1] % NV != 0 || P.in_prev.pitch[0] % NV != 0 ||
+            P.in_prev.pitch[1] % NV != 0 ||
+            (reinterpret_cast<uintptr_t>(P.in_cur.base) & amask) != 0 ||
+            (reinterpret_cast<uintptr_t>(P.in_prev.base) & amask) != 0)
           return fail(CCL_E_INVALID,
-                      "chunk %d: 3D buffers must be 16-byte aligned with pitches a multiple of 4 "
-                      "and the same region column offset modulo 4",
-                      first + k);
+                      "chunk %d: 3D buffers must be %d-byte aligned with pitches a multiple of "
+                      "%d and the same region column offset modulo %d",
+                      first + k, NV * esize, NV, NV);
       }
       C.tile_begin = static_cast<int32_t>(tiles);
       tiles += segs * C.nstrips * C.nrowblk;
@@ -379,16 +436,17 @@ ccl_status launch_wave3d(int32_t depth, bool in_place, float r2, int32_t tile_pl
     bool xin = true;  // every strip of every chunk fully interior in x
     for (int k = 0; k < n; ++k) {
       const W3Chunk &C = a.ch[k];
-      xin = xin && C.xs0 == C.cx0 && (C.cx1 - C.cx0) % 256 == 0 && C.cx0 >= C.lc_x0 &&
+      xin = xin && C.xs0 == C.cx0 && (C.cx1 - C.cx0) % SWD == 0 && C.cx0 >= C.lc_x0 &&
             C.cx1 <= C.lc_x1;
     }
     ccl_status st;
     {
       TimedLaunch tl(CCL_KERNEL_STENCIL, stream);
-      if (xin)
-        hipLaunchKernelGGL(wave3d_kernel<true>, dim3(blocks), dim3(kThreads), 0, stream, a);
-      else
-        hipLaunchKernelGGL(wave3d_kernel<false>, dim3(blocks), dim3(kThreads), 0, stream, a);
+      void *args[] = {&a};
+      st = hip_check(hipLaunchKernel(kernel_for(dtype, xin), dim3(blocks), dim3(kThreads), args, 0,
+                                     stream),
+                     "wave3d_kernel launch");
+      if (st != CCL_OK) return st;
     }
     st = hip_check(hipGetLastError(), "wave3d_kernel launch");
     if (st != CCL_OK) return st;

@@ -13,11 +13,15 @@ namespace ccl {
 // s = ((Z- + Z+) + (Y- + Y+)) + (X- + X+); lap = s - 6C; u+ = fma(r2, lap, 2C - P).
 // 6C is rounded (6 needs two significant bits), so it stays a separate
 // multiply; 2C is exact, so fma(2, C, -P) equals the rounded 2C - P.
-__device__ __forceinline__ float cell3(float zm, float zp, float ym, float yp, float xm, float xp,
-                                       float c, float p, float r2) {
-  const float sum = ((zm + zp) + (ym + yp)) + (xm + xp);
-  const float lap = sum - 6.0f * c;
-  return fmaf(r2, lap, fmaf(2.0f, c, -p));
+// F is float or double (the arithmetic type).
+__device__ __forceinline__ float fma3(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma3(double a, double b, double c) { return fma(a, b, c); }
+
+template <class F>
+__device__ __forceinline__ F cell3(F zm, F zp, F ym, F yp, F xm, F xp, F c, F p, F r2) {
+  const F sum = ((zm + zp) + (ym + yp)) + (xm + xp);
+  const F lap = sum - F(6) * c;
+  return fma3(r2, lap, fma3(F(2), c, -p));
 }
 
 }  // namespace ccl

@@ -1,10 +1,10 @@
 // 3D seven-point leapfrog stencil, T = 2..8 steps per pass over HBM.
 //
-// Work unit: one 512-thread block owns a patch of 64 columns by 32*P rows
-// and streams along z through a segment of planes.  Thread (ly, lx) holds
-// four consecutive columns (one 16-byte group) of P consecutive rows; the
-// 16 threads of a patch row are one DPP row, so x-neighbours come from DPP
-// row shifts.  A taller patch re-computes less of its overlap with the
+// Work unit: one 512-thread block owns a patch of 16*NV columns by 32*P
+// rows and streams along z through a segment of planes.  Thread (ly, lx)
+// holds NV consecutive columns (one vector group: four floats, two doubles
+// or four 16-bit values; see prec.h) of P consecutive rows; the 16 threads
+// of a patch row are one DPP row, so x-neighbours come from DPP row shifts.  A taller patch re-computes less of its overlap with the
 // neighbouring patches (at T = 6 a 64 x 64 patch stores 48 x 52 cells, a
 // 64 x 32 patch 48 x 20), at the same registers per thread.  For every level l < T the thread keeps the last three planes
 // of u^{n+l} over its cells in registers (a rotating three-slot ring), so
@@ -17,15 +17,17 @@
 // level, computes plane i-l of u^{n+l}; level T gives u^{n+T} at plane i-T,
 // stored with u^{n+T-1} of the same plane.  A level-l value is valid only
 // where its whole dependency cone was loaded, so patches overlap their
-// neighbours by A = 4*ceil(T/4) columns and T rows on each side and
+// neighbours by A = NV*ceil(T/NV) columns and T rows on each side and
 // segments re-read T planes above and below; only the valid interior is
-// stored.  Every cell is produced by the same float32 expression as the
-// one-step kernel, so results are bitwise independent of T and tiling.
+// stored.  Every cell is produced by the same expression as the one-step
+// kernel, so results are bitwise independent of tiling (and of T where
+// storage and arithmetic types agree).
 #include <algorithm>
 #include <cstring>
 #include <type_traits>
 
 #include "ccl_internal.h"
+#include "prec.h"
 #include "wave2d_tile.h"
 #include "wave3d_cell.h"
 
@@ -33,7 +35,7 @@ namespace ccl {
 namespace {
 
 // Block shape: kThreads threads in rows of kLX; a patch row is kLX groups
-// of four columns and the patch has kThreads / kLX thread rows.
+// of NV columns and the patch has kThreads / kLX thread rows.
 #ifndef CCL_W3T_THREADS
 #define CCL_W3T_THREADS 512
 #endif
@@ -43,7 +45,6 @@ namespace {
 constexpr int kThreads = CCL_W3T_THREADS;
 constexpr int kLX = CCL_W3T_LX;
 constexpr int kLY = kThreads / kLX;
-constexpr int kPatchCols = 4 * kLX;
 static_assert(kLX == 16 || kLX == 32 || kLX == 64, "a patch row is 16, 32 or 64 lanes");
 static_assert(kThreads % 64 == 0 && kThreads % kLX == 0, "whole waves and thread rows");
 static_assert((kThreads & (kThreads - 1)) == 0, "row neighbours wrap with a power-of-two mask");
@@ -60,10 +61,13 @@ __host__ __device__ constexpr int tb_prefetch(int) { return 1; }
 #else
 __host__ __device__ constexpr int tb_prefetch(int) { return CCL_W3T_PF; }
 #endif
-__host__ __device__ constexpr int tb_overlap(int T) { return 4 * ((T + 3) / 4); }
-__host__ __device__ constexpr int tb_out_cols(int T) { return kPatchCols - 2 * tb_overlap(T); }
+__host__ __device__ constexpr int tb_patch_cols(int NV) { return NV * kLX; }
+__host__ __device__ constexpr int tb_overlap(int T, int NV = 4) { return NV * ((T + NV - 1) / NV); }
+__host__ __device__ constexpr int tb_out_cols(int T, int NV = 4) {
+  return tb_patch_cols(NV) - 2 * tb_overlap(T, NV);
+}
 __host__ __device__ constexpr int tb_out_rows(int T) { return kLY * tb_rows(T) - 2 * T; }
-static_assert(tb_out_cols(CCL_MAX_DEPTH) > 0 && tb_out_rows(CCL_MAX_DEPTH) > 0,
+static_assert(tb_out_cols(CCL_MAX_DEPTH, 2) > 0 && tb_out_rows(CCL_MAX_DEPTH) > 0,
               "every depth leaves an interior to store");
 #ifndef CCL_W3T_NB
 __host__ __device__ constexpr int tb_lds_buffers(int T) { return T <= 4 ? 2 : 1; }
@@ -77,10 +81,10 @@ struct Field3 {  // a chunk buffer: global index of its first element, strides
 };
 
 struct W3TChunk {
-  const float *in_prev;
-  const float *in_cur;
-  float *out_prev;
-  float *out_cur;
+  const void *in_prev;
+  const void *in_cur;
+  void *out_prev;
+  void *out_cur;
   Field3 ip, ic, op, oc;
   int32_t lp[6];  // loadable box of in_prev: z0, z1, y0, y1, x0, x1
   int32_t lc[6];  // loadable box of in_cur
@@ -94,22 +98,30 @@ struct W3TArgs {
   int32_t nchunks;
   int32_t total_tiles;
   int32_t tile_planes;
-  float r2;
+  float r2f;   // r2 rounded to float (float arithmetic)
+  double r2d;  // r2 as given (double arithmetic)
   int32_t gz0, gz1, gy0, gy1, gx0, gx1;  // domain: zero outside
   W3TChunk ch[kMaxChunksPerLaunch];
 };
+
+template <class F>
+__device__ __forceinline__ F r2_of(const W3TArgs &a);
+template <>
+__device__ __forceinline__ float r2_of<float>(const W3TArgs &a) { return a.r2f; }
+template <>
+__device__ __forceinline__ double r2_of<double>(const W3TArgs &a) { return a.r2d; }
 
 // x-neighbours across the lanes of a patch row.  16-lane rows are DPP rows
 // (row_shr:1 / row_shl:1); wider rows use the wave shifts (wave_shr:1 /
 // wave_shl:1), where the first lane of the second row of a wave receives
 // the last lane of the first: a patch-edge cell, never valid, so harmless.
-__device__ __forceinline__ float row_from_left(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kLX == 16 ? 0x111 : 0x138,
-                                                    0xf, 0xf, false));
+template <class F>
+__device__ __forceinline__ F row_from_left(F v) {
+  return dpp_move<kLX == 16 ? 0x111 : 0x138>(v);
 }
-__device__ __forceinline__ float row_from_right(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kLX == 16 ? 0x101 : 0x130,
-                                                    0xf, 0xf, false));
+template <class F>
+__device__ __forceinline__ F row_from_right(F v) {
+  return dpp_move<kLX == 16 ? 0x101 : 0x130>(v);
 }
 
 // One buffer as the streaming loop sees it: its base, the plane index of
@@ -117,18 +129,18 @@ __device__ __forceinline__ float row_from_right(float v) {
 // element offset, within a plane, of each of the thread's rows (32 bits:
 // strides are checked to fit in int32 on the host).  A row that the
 // buffer does not hold has an offset that is never used.
-template <int P>
+template <class E, int P>
 struct Rows {
-  const float *base;
+  const E *base;
   int32_t z0;
   int32_t pz;
   uint32_t off[P];
 };
 
-template <int P>
-__device__ __forceinline__ Rows<P> rows_of(const float *base, const Field3 &f, int yl, int xl) {
-  Rows<P> r;
-  r.base = base;
+template <class E, int P>
+__device__ __forceinline__ Rows<E, P> rows_of(const void *base, const Field3 &f, int yl, int xl) {
+  Rows<E, P> r;
+  r.base = static_cast<const E *>(base);
   r.z0 = f.z0;
   r.pz = f.pz;
 #pragma unroll
@@ -137,57 +149,63 @@ __device__ __forceinline__ Rows<P> rows_of(const float *base, const Field3 &f, i
   return r;
 }
 
-template <int P>
-__device__ __forceinline__ const float *plane_of(const Rows<P> &b, int z) {
+template <class E, int P>
+__device__ __forceinline__ const E *plane_of(const Rows<E, P> &b, int z) {
   return b.base + static_cast<int64_t>(z - b.z0) * b.pz;
 }
 
-// The thread's P rows of plane z: zero outside the loadable box (planes
-// [lz0, lz1), rows where ok[j], columns in cx).  STREAM marks data read
-// once (u^{n-1}).
-template <bool STREAM, int P>
-__device__ __forceinline__ void load_rows(float4 (&v)[P], const Rows<P> &b, int z, int lz0,
+// The thread's P rows of plane z, widened: zero outside the loadable box
+// (planes [lz0, lz1), rows where ok[j], columns in cx).  STREAM marks data
+// read once (u^{n-1}).
+template <class PR, bool STREAM, int P>
+__device__ __forceinline__ void load_rows(Vec<typename PR::F, PR::NV> (&v)[P],
+                                          const Rows<typename PR::E, P> &b, int z, int lz0,
                                           int lz1, const bool (&ok)[P], const w2::Cols &cx) {
+  using Raw = typename PR::Raw;
+  using F = typename PR::F;
   const bool zin = z >= lz0 && z < lz1;  // block-uniform
-  const float *plane = plane_of(b, z);
+  const typename PR::E *plane = plane_of(b, z);
 #pragma unroll
   for (int j = 0; j < P; ++j) {
-    float4 r = w2::zero4();
+    Raw q;
+#pragma unroll
+    for (int i = 0; i < PR::NV; ++i) q[i] = typename PR::E(0);
     if (zin && ok[j] && cx.any) {
-      const w2::f4v *p = reinterpret_cast<const w2::f4v *>(plane + b.off[j]);
-      const w2::f4v q = STREAM ? __builtin_nontemporal_load(p) : *p;
-      r = make_float4(q.x, q.y, q.z, q.w);
+      const Raw *p = reinterpret_cast<const Raw *>(plane + b.off[j]);
+      q = STREAM ? __builtin_nontemporal_load(p) : *p;
     }
-    r.x = cx.m0 ? r.x : 0.0f;
-    r.y = cx.m1 ? r.y : 0.0f;
-    r.z = cx.m2 ? r.z : 0.0f;
-    r.w = cx.m3 ? r.w : 0.0f;
-    v[j] = r;
+#pragma unroll
+    for (int i = 0; i < PR::NV; ++i) v[j].v[i] = cx.m[i] ? PR::widen(q[i]) : F(0);
   }
 }
 
-// Stores a group where the output mask allows.  Partial groups occur only
-// at a chunk's x edges; their other columns are halo cells of this chunk's
-// own output buffer that nothing writes during the launch, so they are read
-// and written back unchanged (one 16-byte store).
-__device__ __forceinline__ void store_group(float *p_, const w2::Cols &c, const float4 &v) {
-  w2::f4v *p = reinterpret_cast<w2::f4v *>(p_);
-  w2::f4v w = {v.x, v.y, v.z, v.w};
-  if (!(c.m0 && c.m1 && c.m2 && c.m3)) {
-    const w2::f4v o = *p;
-    w.x = c.m0 ? v.x : o.x;
-    w.y = c.m1 ? v.y : o.y;
-    w.z = c.m2 ? v.z : o.z;
-    w.w = c.m3 ? v.w : o.w;
+// Stores a group where the output mask allows, narrowed to the storage
+// type.  Partial groups occur only at a chunk's x edges; their other
+// columns are halo cells of this chunk's own output buffer that nothing
+// writes during the launch, so they are read and written back unchanged
+// (one vector store).
+template <class PR>
+__device__ __forceinline__ void store_group(typename PR::E *p_, const w2::Cols &c,
+                                            const Vec<typename PR::F, PR::NV> &v) {
+  using Raw = typename PR::Raw;
+  Raw *p = reinterpret_cast<Raw *>(p_);
+  Raw w;
+#pragma unroll
+  for (int i = 0; i < PR::NV; ++i) w[i] = PR::narrow(v.v[i]);
+  if (!w2::all_of<PR::NV>(c)) {
+    const Raw o = *p;
+#pragma unroll
+    for (int i = 0; i < PR::NV; ++i) w[i] = c.m[i] ? w[i] : o[i];
   }
   __builtin_nontemporal_store(w, p);
 }
 
 // What the streaming loop of one block needs, gathered once (in registers,
 // so nothing is reloaded from the kernel arguments after a store).
-template <int P>
+template <class PR, int P>
 struct Patch {
-  Rows<P> ic, ip, oc, op;
+  using E = typename PR::E;
+  Rows<E, P> ic, ip, oc, op;
   int32_t lc_z0, lc_z1, lp_z0, lp_z1;  // loadable planes of u^n, u^{n-1}
   int32_t gz0, gz1;                     // domain planes
   int32_t zo0, zo1;                     // output planes of this segment
@@ -196,33 +214,40 @@ struct Patch {
   bool xy_in;                           // patch inside the domain in x and y
 };
 
-// xch: the block's LDS words, [buffer][level][first row / last row][thread].
-template <int T>
-__device__ __forceinline__ void stream_patch(const Patch<tb_rows(T)> &S, float r2, int tid,
-                                             float4 (*xch)[T][2][kThreads]) {
+// xch: the block's LDS words, [buffer][level][first row / last row][thread];
+// each word is one thread's group of NV arithmetic values (16 bytes).
+template <class PR, int T>
+__device__ __forceinline__ void stream_patch(const Patch<PR, tb_rows(T)> &S, typename PR::F r2,
+                                             int tid,
+                                             Vec<typename PR::F, PR::NV> (*xch)[T][2][kThreads]) {
   constexpr int P = tb_rows(T);
   constexpr int NB = tb_lds_buffers(T);
   constexpr int PF = tb_prefetch(T);
+  constexpr int NV = PR::NV;
+  using F = typename PR::F;
+  using V = Vec<F, NV>;
   static_assert(PF == 1 || PF == 3, "prefetch depth is 1 or 3 planes");
 
-  float4 ring[T][3][P];  // level l: planes i-l-2, i-l-1, i-l in rotating slots
+  V ring[T][3][P];  // level l: planes i-l-2, i-l-1, i-l in rotating slots
 #pragma unroll
   for (int l = 0; l < T; ++l)
 #pragma unroll
     for (int s = 0; s < 3; ++s)
 #pragma unroll
-      for (int j = 0; j < P; ++j) ring[l][s][j] = w2::zero4();
+      for (int j = 0; j < P; ++j)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) ring[l][s][j].v[q] = F(0);
 
   const int i0 = S.zo0 - T;
   const int n_iter = (S.zo1 - S.zo0) + 2 * T;
   // planes loaded ahead: u^n of planes i..i+PF-1 and u^{n-1} of the plane
   // before each; with PF = 3 plane i sits in slot i - i0 mod 3, the
   // iteration's phase, so the slots rotate without moves
-  float4 qs[PF][P], ps[PF][P];
+  V qs[PF][P], ps[PF][P];
 #pragma unroll
   for (int f = 0; f < PF; ++f) {
-    load_rows<false>(qs[f], S.ic, i0 + f, S.lc_z0, S.lc_z1, S.ok_c, S.lcx);
-    load_rows<true>(ps[f], S.ip, i0 + f - 1, S.lp_z0, S.lp_z1, S.ok_p, S.lpx);
+    load_rows<PR, false>(qs[f], S.ic, i0 + f, S.lc_z0, S.lc_z1, S.ok_c, S.lcx);
+    load_rows<PR, true>(ps[f], S.ip, i0 + f - 1, S.lp_z0, S.lp_z1, S.ok_p, S.lpx);
   }
 
   // One iteration; PH = iteration count mod 3 names the ring slots: before
@@ -244,11 +269,11 @@ __device__ __forceinline__ void stream_patch(const Patch<tb_rows(T)> &S, float r
     constexpr int QS = PF == 3 ? PH : 0;
 #pragma unroll
     for (int j = 0; j < P; ++j) ring[0][NEW][j] = qs[QS][j];
-    float4 pc[P];
+    V pc[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) pc[j] = ps[QS][j];
-    load_rows<false>(qs[QS], S.ic, i + PF, S.lc_z0, S.lc_z1, S.ok_c, S.lcx);
-    load_rows<true>(ps[QS], S.ip, i + PF - 1, S.lp_z0, S.lp_z1, S.ok_p, S.lpx);
+    load_rows<PR, false>(qs[QS], S.ic, i + PF, S.lc_z0, S.lc_z1, S.ok_c, S.lcx);
+    load_rows<PR, true>(ps[QS], S.ip, i + PF - 1, S.lp_z0, S.lp_z1, S.ok_p, S.lpx);
 
 #pragma unroll
     for (int t = 1; t <= T; ++t) {
@@ -257,30 +282,30 @@ __device__ __forceinline__ void stream_patch(const Patch<tb_rows(T)> &S, float r
       // outer y-neighbours of this thread's rows in plane r of u^{n+t-1}
       // (the top thread row reads the bottom one's words: patch-edge cells
       // are never valid, so any value there is harmless)
-      const float4 up = xch[b][t - 1][1][(tid - kLX) & (kThreads - 1)];
-      const float4 dn = xch[b][t - 1][0][(tid + kLX) & (kThreads - 1)];
-      float4 o[P];
+      const V up = xch[b][t - 1][1][(tid - kLX) & (kThreads - 1)];
+      const V dn = xch[b][t - 1][0][(tid + kLX) & (kThreads - 1)];
+      V o[P];
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        const float4 cc = ring[t - 1][MID][j];
-        const float4 zm = ring[t - 1][OLD][j];
-        const float4 zp = ring[t - 1][NEW][j];
-        const float4 ym = j == 0 ? up : ring[t - 1][MID][j - 1];
-        const float4 yp = j == P - 1 ? dn : ring[t - 1][MID][j + 1];
-        const float4 pv = t == 1 ? pc[j] : ring[t >= 2 ? t - 2 : 0][OLD][j];
-        const float xm0 = row_from_left(cc.w);
-        const float xp3 = row_from_right(cc.x);
-        float4 v;
-        v.x = cell3(zm.x, zp.x, ym.x, yp.x, xm0, cc.y, cc.x, pv.x, r2);
-        v.y = cell3(zm.y, zp.y, ym.y, yp.y, cc.x, cc.z, cc.y, pv.y, r2);
-        v.z = cell3(zm.z, zp.z, ym.z, yp.z, cc.y, cc.w, cc.z, pv.z, r2);
-        v.w = cell3(zm.w, zp.w, ym.w, yp.w, cc.z, xp3, cc.w, pv.w, r2);
+        const V cc = ring[t - 1][MID][j];
+        const V zm = ring[t - 1][OLD][j];
+        const V zp = ring[t - 1][NEW][j];
+        const V ym = j == 0 ? up : ring[t - 1][MID][j > 0 ? j - 1 : 0];
+        const V yp = j == P - 1 ? dn : ring[t - 1][MID][j < P - 1 ? j + 1 : 0];
+        const V pv = t == 1 ? pc[j] : ring[t >= 2 ? t - 2 : 0][OLD][j];
+        const F xm0 = row_from_left(cc.v[NV - 1]);
+        const F xpl = row_from_right(cc.v[0]);
+        V v;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+          const F xm = q == 0 ? xm0 : cc.v[q > 0 ? q - 1 : 0];
+          const F xp = q == NV - 1 ? xpl : cc.v[q < NV - 1 ? q + 1 : 0];
+          v.v[q] = cell3(zm.v[q], zp.v[q], ym.v[q], yp.v[q], xm, xp, cc.v[q], pv.v[q], r2);
+        }
         if (!(S.xy_in && z_in)) {
           const bool in = z_in && S.dom_row[j];
-          v.x = (in && S.dom.m0) ? v.x : 0.0f;
-          v.y = (in && S.dom.m1) ? v.y : 0.0f;
-          v.z = (in && S.dom.m2) ? v.z : 0.0f;
-          v.w = (in && S.dom.m3) ? v.w : 0.0f;
+#pragma unroll
+          for (int q = 0; q < NV; ++q) v.v[q] = (in && S.dom.m[q]) ? v.v[q] : F(0);
         }
         o[j] = v;
       }
@@ -288,13 +313,13 @@ __device__ __forceinline__ void stream_patch(const Patch<tb_rows(T)> &S, float r
 #pragma unroll
         for (int j = 0; j < P; ++j) ring[t < T ? t : 0][NEW][j] = o[j];
       } else if (r >= S.zo0 && r < S.zo1 && S.out.any) {
-        float *pcur = const_cast<float *>(plane_of(S.oc, r));
-        float *pprev = const_cast<float *>(plane_of(S.op, r));
+        typename PR::E *pcur = const_cast<typename PR::E *>(plane_of(S.oc, r));
+        typename PR::E *pprev = const_cast<typename PR::E *>(plane_of(S.op, r));
 #pragma unroll
         for (int j = 0; j < P; ++j) {
           if (!S.out_row[j]) continue;
-          store_group(pcur + S.oc.off[j], S.out, o[j]);
-          store_group(pprev + S.op.off[j], S.out, ring[T - 1][MID][j]);
+          store_group<PR>(pcur + S.oc.off[j], S.out, o[j]);
+          store_group<PR>(pprev + S.op.off[j], S.out, ring[T - 1][MID][j]);
         }
       }
     }
@@ -307,12 +332,15 @@ __device__ __forceinline__ void stream_patch(const Patch<tb_rows(T)> &S, float r
   }
 }
 
-template <int T>
+template <class PR, int T>
 __global__ __launch_bounds__(kThreads) void wave3d_tb_kernel(const W3TArgs a) {
+  constexpr int NV = PR::NV;
   constexpr int P = tb_rows(T);
-  constexpr int A = tb_overlap(T);
-  constexpr int OW = tb_out_cols(T);
+  constexpr int A = tb_overlap(T, NV);
+  constexpr int OW = tb_out_cols(T, NV);
   constexpr int OH = tb_out_rows(T);
+  using E = typename PR::E;
+  using F = typename PR::F;
 
   const int blk = w2::xcd_block(blockIdx.x, gridDim.x);
   if (blk >= a.total_tiles) return;  // the whole block leaves together
@@ -332,15 +360,15 @@ __global__ __launch_bounds__(kThreads) void wave3d_tb_kernel(const W3TArgs a) {
   const int lx = tid % kLX, ly = tid / kLX;
   const int px = C.xs0 + strip * OW;  // patch origin
   const int py = C.cy0 - T + rb * OH;
-  const int xl = px + 4 * lx;
+  const int xl = px + NV * lx;
   const int yl = py + ly * P;
   const int oy0 = max(C.cy0, py + T), oy1 = min(C.cy1, py + T + OH);
 
-  Patch<P> S;
-  S.ic = rows_of<P>(C.in_cur, C.ic, yl, xl);
-  S.ip = rows_of<P>(C.in_prev, C.ip, yl, xl);
-  S.oc = rows_of<P>(C.out_cur, C.oc, yl, xl);
-  S.op = rows_of<P>(C.out_prev, C.op, yl, xl);
+  Patch<PR, P> S;
+  S.ic = rows_of<E, P>(C.in_cur, C.ic, yl, xl);
+  S.ip = rows_of<E, P>(C.in_prev, C.ip, yl, xl);
+  S.oc = rows_of<E, P>(C.out_cur, C.oc, yl, xl);
+  S.op = rows_of<E, P>(C.out_prev, C.op, yl, xl);
   S.lc_z0 = C.lc[0];
   S.lc_z1 = C.lc[1];
   S.lp_z0 = C.lp[0];
@@ -357,52 +385,64 @@ __global__ __launch_bounds__(kThreads) void wave3d_tb_kernel(const W3TArgs a) {
     S.out_row[j] = y >= oy0 && y < oy1;
     S.dom_row[j] = y >= a.gy0 && y < a.gy1;
   }
-  S.lcx = w2::cols_of(xl, C.lc[4], C.lc[5]);
-  S.lpx = w2::cols_of(xl, C.lp[4], C.lp[5]);
-  S.dom = w2::cols_of(xl, a.gx0, a.gx1);
-  S.out = w2::cols_of(xl, max(C.cx0, px + A), min(C.cx1, px + A + OW));
-  S.xy_in = px >= a.gx0 && px + kPatchCols <= a.gx1 && py >= a.gy0 && py + kLY * P <= a.gy1;
-  __shared__ float4 xch[tb_lds_buffers(T)][T][2][kThreads];
-  stream_patch<T>(S, a.r2, tid, xch);
+  S.lcx = w2::cols_of<NV>(xl, C.lc[4], C.lc[5]);
+  S.lpx = w2::cols_of<NV>(xl, C.lp[4], C.lp[5]);
+  S.dom = w2::cols_of<NV>(xl, a.gx0, a.gx1);
+  S.out = w2::cols_of<NV>(xl, max(C.cx0, px + A), min(C.cx1, px + A + OW));
+  S.xy_in = px >= a.gx0 && px + tb_patch_cols(NV) <= a.gx1 && py >= a.gy0 &&
+            py + kLY * P <= a.gy1;
+  __shared__ Vec<F, NV> xch[tb_lds_buffers(T)][T][2][kThreads];
+  stream_patch<PR, T>(S, r2_of<F>(a), tid, xch);
 }
 
-template <int T>
+template <class PR, int T>
 const void *kernel_of() {
-  return reinterpret_cast<const void *>(&wave3d_tb_kernel<T>);
+  return reinterpret_cast<const void *>(&wave3d_tb_kernel<PR, T>);
 }
 
-const void *kernel_for(int T) {
+template <class PR>
+const void *kernel_depth(int T) {
   switch (T) {
-    case 2: return kernel_of<2>();
-    case 3: return kernel_of<3>();
-    case 4: return kernel_of<4>();
-    case 5: return kernel_of<5>();
-    case 6: return kernel_of<6>();
-    case 7: return kernel_of<7>();
-    case 8: return kernel_of<8>();
+    case 2: return kernel_of<PR, 2>();
+    case 3: return kernel_of<PR, 3>();
+    case 4: return kernel_of<PR, 4>();
+    case 5: return kernel_of<PR, 5>();
+    case 6: return kernel_of<PR, 6>();
+    case 7: return kernel_of<PR, 7>();
+    case 8: return kernel_of<PR, 8>();
+    default: return nullptr;
+  }
+}
+
+const void *kernel_for(int32_t dtype, int T) {
+  switch (dtype) {
+    case CCL_DTYPE_F32: return kernel_depth<P32>(T);
+    case CCL_DTYPE_F64: return kernel_depth<P64>(T);
+    case CCL_DTYPE_BF16: return kernel_depth<PB16>(T);
+    case CCL_DTYPE_F16: return kernel_depth<PH16>(T);
     default: return nullptr;
   }
 }
 
 // Concurrently resident blocks of the depth-T kernel on the device (cached).
-int64_t block_slots(int T) {
-  static int64_t cache[CCL_MAX_DEPTH + 1] = {};
-  if (T < 2 || T > CCL_MAX_DEPTH) return 256;
-  if (cache[T] > 0) return cache[T];
+int64_t block_slots(int T, int32_t dtype = CCL_DTYPE_F32) {
+  static int64_t cache[4][CCL_MAX_DEPTH + 1] = {};
+  if (T < 2 || T > CCL_MAX_DEPTH || dtype < 0 || dtype > 3) return 256;
+  if (cache[dtype][T] > 0) return cache[dtype][T];
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_for(T), kThreads, 0) !=
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_for(dtype, T), kThreads, 0) !=
           hipSuccess ||
       per_cu < 1)
     return 256;
-  cache[T] = static_cast<int64_t>(cus) * per_cu;
-  return cache[T];
+  cache[dtype][T] = static_cast<int64_t>(cus) * per_cu;
+  return cache[dtype][T];
 }
 
-int64_t tiles_of(int64_t nz, int64_t ny, int64_t nx, int T, int32_t planes) {
+int64_t tiles_of(int64_t nz, int64_t ny, int64_t nx, int T, int32_t planes, int NV = 4) {
   return ((nz + planes - 1) / planes) * ((ny + tb_out_rows(T) - 1) / tb_out_rows(T)) *
-         ((nx + tb_out_cols(T) - 1) / tb_out_cols(T));
+         ((nx + tb_out_cols(T, NV) - 1) / tb_out_cols(T, NV));
 }
 
 bool fits_i32(int64_t v) { return v >= INT32_MIN && v <= INT32_MAX; }
@@ -427,11 +467,12 @@ void box6(const Box &b, int32_t *o) {
   }
 }
 
-template <int T>
-ccl_status launch_t(const W3TArgs &a, int blocks, hipStream_t s) {
+ccl_status launch_k(const void *fn, const W3TArgs &a, int blocks, hipStream_t s) {
+  if (!fn) return fail(CCL_E_INVALID, "no 3D blocked kernel for this dtype and depth");
   TimedLaunch tl(CCL_KERNEL_STENCIL, s);
-  hipLaunchKernelGGL(wave3d_tb_kernel<T>, dim3(blocks), dim3(kThreads), 0, s, a);
-  return hip_check(hipGetLastError(), "wave3d_tb_kernel launch");
+  void *args[] = {const_cast<W3TArgs *>(&a)};
+  return hip_check(hipLaunchKernel(fn, dim3(blocks), dim3(kThreads), args, 0, s),
+                   "wave3d_tb_kernel launch");
 }
 
 }  // namespace
@@ -458,10 +499,14 @@ int32_t wave3d_tb_plan_planes(int64_t nz, int64_t ny, int64_t nx, int32_t K, int
                         blocks_of);
 }
 
-ccl_status launch_wave3d_tb(int32_t T, float r2, int32_t tile_planes, const WaveChunkPlan *plans,
-                            int32_t nplans, hipStream_t stream) {
+ccl_status launch_wave3d_tb(int32_t dtype, int32_t T, double r2, int32_t tile_planes,
+                            const WaveChunkPlan *plans, int32_t nplans, hipStream_t stream) {
   if (T < 2 || T > CCL_MAX_DEPTH)
     return fail(CCL_E_INVALID, "temporally blocked 3D stencil needs T in 2..%d", CCL_MAX_DEPTH);
+  const int NV = dtype_group(dtype);
+  const int esize = dtype_bytes(dtype);
+  if (esize == 0) return fail(CCL_E_INVALID, "unknown dtype %d", dtype);
+  const uintptr_t amask = static_cast<uintptr_t>(NV * esize - 1);
   if (nplans < 1) return CCL_OK;
   const Box &D = plans[0].domain;
   for (int k = 0; k < nplans; ++k)
@@ -476,7 +521,8 @@ ccl_status launch_wave3d_tb(int32_t T, float r2, int32_t tile_planes, const Wave
     W3TArgs a;
     memset(&a, 0, sizeof(a));
     a.nchunks = n;
-    a.r2 = r2;
+    a.r2f = static_cast<float>(r2);
+    a.r2d = r2;
     a.gz0 = static_cast<int32_t>(D.lo[0]);
     a.gz1 = static_cast<int32_t>(D.hi[0]);
     a.gy0 = static_cast<int32_t>(D.lo[1]);
@@ -493,11 +539,11 @@ ccl_status launch_wave3d_tb(int32_t T, float r2, int32_t tile_planes, const Wave
         int64_t w = 0;
         for (int k = 0; k < n; ++k) {
           const Box &cb = plans[first + k].chunk;
-          w += tiles_of(cb.hi[0] - cb.lo[0], cb.hi[1] - cb.lo[1], cb.hi[2] - cb.lo[2], T, p);
+          w += tiles_of(cb.hi[0] - cb.lo[0], cb.hi[1] - cb.lo[1], cb.hi[2] - cb.lo[2], T, p, NV);
         }
         return w;
       };
-      a.tile_planes = plan_tile_rows(block_slots(T), T, 4,
+      a.tile_planes = plan_tile_rows(block_slots(T, dtype), T, 4,
                                      static_cast<int32_t>(std::max<int64_t>(zmax, 4)), blocks_of);
     }
     int64_t tiles = 0;
@@ -511,22 +557,22 @@ ccl_status launch_wave3d_tb(int32_t T, float r2, int32_t tile_planes, const Wave
       const WaveField *fs[4] = {&P.in_prev, &P.in_cur, &P.out_prev, &P.out_cur};
       Field3 *gs[4] = {&C.ip, &C.ic, &C.op, &C.oc};
       // strip 0's patches start A columns left of the chunk, aligned down
-      // to a multiple of 4 relative to the u^n buffer so that every
-      // thread's group of four columns is one 16-byte access
-      const int64_t A = tb_overlap(T);
-      const int64_t mis = (((P.chunk.lo[2] - A - P.in_cur.off[2]) % 4) + 4) % 4;
+      // to a multiple of NV relative to the u^n buffer so that every
+      // thread's group of NV columns is one aligned vector access
+      const int64_t A = tb_overlap(T, NV);
+      const int64_t mis = (((P.chunk.lo[2] - A - P.in_cur.off[2]) % NV) + NV) % NV;
       const int64_t xs0 = P.chunk.lo[2] - A - mis;
       if (!fits_i32(xs0)) return fail(CCL_E_RANGE, "3D indices must fit in int32");
       C.xs0 = static_cast<int32_t>(xs0);
       for (int b = 0; b < 4; ++b) {
         ccl_status st = field3_of(*fs[b], gs[b]);
         if (st != CCL_OK) return st;
-        if ((((xs0 - fs[b]->off[2]) % 4) + 4) % 4 != 0 || fs[b]->pitch[0] % 4 != 0 ||
-            fs[b]->pitch[1] % 4 != 0 || (reinterpret_cast<uintptr_t>(fs[b]->base) & 15u) != 0)
+        if ((((xs0 - fs[b]->off[2]) % NV) + NV) % NV != 0 || fs[b]->pitch[0] % NV != 0 ||
+            fs[b]->pitch[1] % NV != 0 || (reinterpret_cast<uintptr_t>(fs[b]->base) & amask) != 0)
           return fail(CCL_E_INVALID,
-                      "chunk %d: 3D buffers must be 16-byte aligned with strides a multiple of 4 "
-                      "and the same region column offset modulo 4",
-                      first + k);
+                      "chunk %d: 3D buffers must be %d-byte aligned with strides a multiple of "
+                      "%d and the same region column offset modulo %d",
+                      first + k, NV * esize, NV, NV);
       }
       box6(P.load_prev, C.lp);
       box6(P.load_cur, C.lc);
@@ -539,24 +585,15 @@ ccl_status launch_wave3d_tb(int32_t T, float r2, int32_t tile_planes, const Wave
       const int64_t nz = P.chunk.hi[0] - P.chunk.lo[0];
       const int64_t ny = P.chunk.hi[1] - P.chunk.lo[1];
       const int64_t nx = P.chunk.hi[2] - (xs0 + A);  // output columns from strip 0's first
-      C.nstrips = static_cast<int32_t>((nx + tb_out_cols(T) - 1) / tb_out_cols(T));
+      C.nstrips = static_cast<int32_t>((nx + tb_out_cols(T, NV) - 1) / tb_out_cols(T, NV));
       C.nrowblk = static_cast<int32_t>((ny + tb_out_rows(T) - 1) / tb_out_rows(T));
       C.tile_begin = static_cast<int32_t>(tiles);
-      tiles += tiles_of(nz, ny, nx, T, a.tile_planes);
+      tiles += tiles_of(nz, ny, nx, T, a.tile_planes, NV);
       if (tiles > INT32_MAX / 2) return fail(CCL_E_RANGE, "too many tiles");
     }
     a.total_tiles = static_cast<int32_t>(tiles);
     if (tiles == 0) continue;
-    ccl_status st;
-    switch (T) {
-      case 2: st = launch_t<2>(a, static_cast<int>(tiles), stream); break;
-      case 3: st = launch_t<3>(a, static_cast<int>(tiles), stream); break;
-      case 4: st = launch_t<4>(a, static_cast<int>(tiles), stream); break;
-      case 5: st = launch_t<5>(a, static_cast<int>(tiles), stream); break;
-      case 6: st = launch_t<6>(a, static_cast<int>(tiles), stream); break;
-      case 7: st = launch_t<7>(a, static_cast<int>(tiles), stream); break;
-      default: st = launch_t<8>(a, static_cast<int>(tiles), stream); break;
-    }
+    ccl_status st = launch_k(kernel_for(dtype, T), a, static_cast<int>(tiles), stream);
     if (st != CCL_OK) return st;
   }
   return CCL_OK;

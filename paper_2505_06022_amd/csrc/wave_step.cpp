@@ -18,7 +18,7 @@ namespace {
 
 WaveField field_of(const ccl_chunk_buffer &b) {
   WaveField f;
-  f.base = static_cast<float *>(b.base);
+  f.base = b.base;
   for (int d = 0; d < CCL_MAX_DIMS; ++d) {
     f.off[d] = d < b.region.dims ? b.region.offset[d] : 0;
     f.pitch[d] = d < b.region.dims ? b.pitch[d] : 0;
@@ -45,7 +45,12 @@ extern "C" ccl_status ccl_wave_step(const ccl_wave_params *p, int32_t nchunks,
   if (!p || !u_prev || !u_cur) return fail(CCL_E_INVALID, "NULL argument");
   const int dims = p->dims;
   if (dims != 2 && dims != 3) return fail(CCL_E_INVALID, "wave dims=%d must be 2 or 3", dims);
-  if (!std::isfinite(p->r2) || p->r2 < 0.0f) return fail(CCL_E_INVALID, "r2 must be finite, >= 0");
+  if (!std::isfinite(p->r2) || p->r2 < 0.0) return fail(CCL_E_INVALID, "r2 must be finite, >= 0");
+  const int32_t dtype = p->dtype;
+  const int esize = dtype_bytes(dtype);
+  if (esize == 0) return fail(CCL_E_INVALID, "dtype=%d unknown", dtype);
+  if (dtype != CCL_DTYPE_F64 && !std::isfinite(static_cast<float>(p->r2)))
+    return fail(CCL_E_INVALID, "r2 overflows float");
   const int T = p->temporal_depth;
   if (T < 1 || T > CCL_MAX_DEPTH)
     return fail(CCL_E_INVALID, "temporal_depth=%d not in 1..%d", T, CCL_MAX_DEPTH);
@@ -61,10 +66,20 @@ extern "C" ccl_status ccl_wave_step(const ccl_wave_params *p, int32_t nchunks,
     ccl_chunk_buffer *sets[4] = {u_prev, u_cur, need_w ? w_prev : nullptr,
                                  need_w ? w_cur : nullptr};
     const char *names[4] = {"u_prev", "u_cur", "w_prev", "w_cur"};
+    // each lane group (dtype_group elements) must be one aligned access
+    const int group = dtype_group(dtype);
+    const uintptr_t amask = static_cast<uintptr_t>(group * esize - 1);
     for (int b = 0; b < 4; ++b) {
       if (!sets[b]) continue;
-      st = check_buffer(sets[b][k], dims, names[b], true);
+      st = check_buffer(sets[b][k], dims, names[b], false);
       if (st != CCL_OK) return st;
+      for (int d = 0; d + 1 < dims; ++d)
+        if (sets[b][k].pitch[d] % group != 0)
+          return fail(CCL_E_INVALID, "%s: pitch[%d] must be a multiple of %d elements", names[b],
+                      d, group);
+      if ((reinterpret_cast<uintptr_t>(sets[b][k].base) & amask) != 0)
+        return fail(CCL_E_INVALID, "%s: base must be %d-byte aligned", names[b],
+                    static_cast<int>(amask + 1));
     }
   }
   if (nsteps == 0) return CCL_OK;
@@ -113,11 +128,11 @@ extern "C" ccl_status ccl_wave_step(const ccl_wave_params *p, int32_t nchunks,
       memset(&m, 0, sizeof(m));
       m.kind = CCL_MAP_NEIGHBORHOOD;
       for (int d = 0; d < dims; ++d) m.extent[d] = tb;
-      st = exchange_jobs(nchunks, chunks, m, u_cur, 4, &jobs);
+      st = exchange_jobs(nchunks, chunks, m, u_cur, esize, &jobs);
       if (st != CCL_OK) return st;
       if (tb > 1) {
         for (int d = 0; d < dims; ++d) m.extent[d] = tb - 1;
-        st = exchange_jobs(nchunks, chunks, m, u_prev, 4, &jobs);
+        st = exchange_jobs(nchunks, chunks, m, u_prev, esize, &jobs);
         if (st != CCL_OK) return st;
       }
       if (!jobs.empty()) {
@@ -138,9 +153,11 @@ extern "C" ccl_status ccl_wave_step(const ccl_wave_params *p, int32_t nchunks,
       P.load_cur = intersect(box_of(u_cur[k].region), P.domain);
     }
     if (dims == 2)
-      st = launch_wave2d(tb, in_place, p->r2, p->tile_rows, plans.data(), nchunks, stream);
+      st = launch_wave2d(dtype, tb, in_place, p->r2, p->tile_rows, plans.data(), nchunks,
+                         stream);
     else
-      st = launch_wave3d(tb, in_place, p->r2, p->tile_rows, plans.data(), nchunks, stream);
+      st = launch_wave3d(dtype, tb, in_place, p->r2, p->tile_rows, plans.data(), nchunks,
+                         stream);
     if (st != CCL_OK) return st;
     // 3. rotate roles so u_cur names the newest level
     for (int k = 0; k < nchunks; ++k) {

@@ -21,15 +21,22 @@ def _round_up(v: int, a: int) -> int:
     return (v + a - 1) // a * a
 
 
-def alloc_buffer(region, device="cuda", fill=0.0, pitch_align=PITCH_ALIGN):
+def torch_dtype(dtype: str):
+    import torch
+    return {"f32": torch.float32, "f64": torch.float64, "bf16": torch.bfloat16,
+            "f16": torch.float16}[dtype]
+
+
+def alloc_buffer(region, device="cuda", fill=0.0, pitch_align=PITCH_ALIGN, dtype="f32"):
     """A torch tensor holding `region` (offset, range) row-major with a padded
-    innermost pitch, and its ccl_chunk_buffer descriptor."""
+    innermost pitch, and its ccl_chunk_buffer descriptor.  `dtype`: the
+    element type ("f32", "f64", "bf16", "f16")."""
     import torch
     off, rng = region
     dims = len(rng)
     pitch_last = _round_up(int(rng[-1]), pitch_align)
     shape = tuple(int(r) for r in rng[:-1]) + (pitch_last,)
-    t = torch.full(shape, float(fill), dtype=torch.float32, device=device)
+    t = torch.full(shape, float(fill), dtype=torch_dtype(dtype), device=device)
     b = ccl_chunk_buffer()
     b.base = t.data_ptr()
     b.region = make_subrange(off, rng)
@@ -49,18 +56,22 @@ def view_of(t, region, box):
 class ChunkedWave:
     """``nchunks`` chunks along ``split_dim`` (ccl_split_range), or, when
     ``grid`` gives a count per dimension, the block split of ccl_split_grid
-    (``nchunks`` is then ignored)."""
+    (``nchunks`` is then ignored).  ``dtype``: the fields' element type
+    ("f32", "f64", "bf16", "f16"); scatter converts the host arrays to it
+    (round to nearest even) and gather returns float64 for "f64", else
+    float32."""
 
     def __init__(self, domain_offset, domain_shape, nchunks: int, r2: float, depth: int = 1,
                  tile_rows: int = 0, buffer_range=None, split_dim: int = 0, device="cuda",
-                 fill=0.0, grid=None):
+                 fill=0.0, grid=None, dtype="f32"):
         self.dims = len(domain_shape)
         self.domain_offset = tuple(int(v) for v in domain_offset)
         self.domain_shape = tuple(int(v) for v in domain_shape)
         self.buffer_range = tuple(buffer_range) if buffer_range is not None else tuple(
             o + n for o, n in zip(self.domain_offset, self.domain_shape))
         self.depth = depth
-        self.params = make_wave_params(self.dims, r2, depth, tile_rows)
+        self.dtype = dtype
+        self.params = make_wave_params(self.dims, r2, depth, tile_rows, dtype)
         if grid is not None:
             self.chunks = ccl_split_grid(self.domain_offset, self.domain_shape, grid)
         else:
@@ -76,7 +87,7 @@ class ChunkedWave:
         arrays = [(ccl_chunk_buffer * nchunks)() for _ in range(4)]
         for k, reg in enumerate(self.regions):
             for which in range(nbuf):
-                t, b = alloc_buffer(reg, device=device, fill=fill)
+                t, b = alloc_buffer(reg, device=device, fill=fill, dtype=dtype)
                 arrays[which][k] = b
                 self.tensors[b.base] = (t, reg)
         self.u_prev, self.u_cur, self.w_prev, self.w_cur = arrays
@@ -97,17 +108,23 @@ class ChunkedWave:
             box = self.chunk_box(k)
             for arr, host in ((self.u_prev, u_prev), (self.u_cur, u_cur)):
                 t, reg = self.tensors[arr[k].base]
+                host_dt = np.float64 if self.dtype == "f64" else np.float32
                 src = torch.from_numpy(np.ascontiguousarray(host[self._local(box)],
-                                                            dtype=np.float32))
+                                                            dtype=host_dt))
                 view_of(t, reg, box).copy_(src, non_blocking=False)
 
     def gather(self, which="cur"):
+        import torch
         arr = self.u_cur if which == "cur" else self.u_prev
-        out = np.empty(self.domain_shape, dtype=np.float32)
+        host_dt = np.float64 if self.dtype == "f64" else np.float32
+        out = np.empty(self.domain_shape, dtype=host_dt)
         for k in range(self.nchunks):
             box = self.chunk_box(k)
             t, reg = self.tensors[arr[k].base]
-            out[self._local(box)] = view_of(t, reg, box).cpu().numpy()
+            v = view_of(t, reg, box)
+            if v.dtype in (torch.bfloat16, torch.float16):
+                v = v.float()  # exact widening
+            out[self._local(box)] = v.cpu().numpy()
         return out
 
     def gather_points(self, points, which="cur"):

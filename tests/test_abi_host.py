@@ -240,6 +240,25 @@ def test_wave_step_validation_no_launch():
     bad = _fake_buffers(chunks, regs1)
     bad[1].pitch[0] = 34
     assert call(good, bad, _fake_buffers(chunks, regs1)) == ccl.CCL_E_INVALID
+    # element types: unknown dtype; float64 groups are two elements (pitch 34
+    # is fine, an 8-byte offset is not); 16-bit groups are 8 bytes
+    pbad = ccl.make_wave_params(2, 0.25, 1)
+    pbad.dtype = 7
+    assert call(pbad, _fake_buffers(chunks, regs1), _fake_buffers(chunks, regs1)) == ccl.CCL_E_INVALID
+    p64 = ccl.make_wave_params(2, 0.25, 1, dtype="f64")
+    odd = _fake_buffers(chunks, regs1)
+    odd[1].pitch[0] = 33
+    assert call(p64, odd, _fake_buffers(chunks, regs1)) == ccl.CCL_E_INVALID
+    off8 = _fake_buffers(chunks, regs1)
+    off8[0].base = off8[0].base + 8
+    assert call(p64, off8, _fake_buffers(chunks, regs1)) == ccl.CCL_E_INVALID
+    pb = ccl.make_wave_params(2, 0.25, 1, dtype="bf16")
+    off4 = _fake_buffers(chunks, regs1)
+    off4[0].base = off4[0].base + 4
+    assert call(pb, off4, _fake_buffers(chunks, regs1)) == ccl.CCL_E_INVALID
+    # r2 that overflows float is refused for the float-arithmetic types only
+    assert call(ccl.make_wave_params(2, 1e300, 1), _fake_buffers(chunks, regs1),
+                _fake_buffers(chunks, regs1)) == ccl.CCL_E_INVALID
     # overlapping chunks
     ov = ccl.ccl_split_range((0, 0), shape, 4)
     ov[1].offset[0] -= 1
