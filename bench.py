@@ -383,8 +383,9 @@ def precision_forms(w, u0, depths=(1, 2, 4, 6, 8)):
                              buffer_range=w["global_shape"], dtype=dt)
             cw.scatter(host, host)
             cw.step(w["steps"])
-            ccl.ccl_timing_enable(True)
             t = time_runs(cw, w["steps"], 2) / 2
+            ccl.ccl_timing_enable(True)  # launch durations: a separate run
+            time_runs(cw, w["steps"], 1)
             n, ms = ccl.ccl_timing_query(ccl.CCL_KERNEL_STENCIL)
             ccl.ccl_timing_enable(False)
             per_cell = (3 if T == 1 else 4) * esize
@@ -449,12 +450,17 @@ def main():
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done")
 
-    ccl.ccl_timing_enable(True)
     elapsed = time_runs(cw, w["steps"], args.steps)
+    log(f"timed {args.steps} runs in {elapsed:.3f} s")
+    # per-launch durations for the roofline: the same runs again, each
+    # launch bracketed by HIP events on its own stream (the event records
+    # between launches add gaps, so they stay out of the timed runs above)
+    ccl.ccl_timing_enable(True)
+    elapsed_ev = time_runs(cw, w["steps"], args.steps)
     n_launch, st_ms = ccl.ccl_timing_query(ccl.CCL_KERNEL_STENCIL)
     h_launch, h_ms = ccl.ccl_timing_query(ccl.CCL_KERNEL_HALO)
     ccl.ccl_timing_enable(False)
-    log(f"timed {args.steps} runs in {elapsed:.3f} s")
+    log(f"the same {args.steps} runs with per-launch events: {elapsed_ev:.3f} s")
     sample = cw.gather_points([(w["share_offset"][0] + 4096, 4096)])
     if not np.all(np.isfinite(sample)):
         raise SystemExit("bench: non-finite field")
@@ -482,6 +488,7 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": load_traffic(depth, rows)},
         "hbm_roofline_equiv_pct": round(100.0 * mcells / roof_equiv, 2),
+        "ms_per_step_with_launch_events": round(elapsed_ev / args.steps * 1e3, 3),
         "stencil_launch_ms": round(st_ms / n_launch, 4), "stencil_launches": n_launch,
         "halo_launch_ms": round(h_ms / max(h_launch, 1), 4), "halo_launches": h_launch,
     }

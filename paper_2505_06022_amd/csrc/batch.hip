@@ -13,7 +13,11 @@
 // after its stores; waiters acquire it before reading.
 //
 // Work order: a single queue holds all (block, grid, tile) items sorted by
-// block, then depth class, then grid, then tile.  (Stepping small groups of grids whose
+// block, then depth class, then grid, then tile.  (A queue ordered grid by
+// grid, so that the resident waves would pipeline one grid's blocks while
+// its buffers stay cache-resident, was measured 20x slower: the blocks of
+// one grid depend on each other, so at any time only about one block of
+// one grid can run and the other waves hold queue items they must wait on.)  (Stepping small groups of grids whose
 // buffers fit in the 256 MB Infinity Cache block by block was measured 5x
 // slower: a block of two grids is too little work to hide the hand-off
 // between consecutive blocks.)  Waves pop items with an atomic counter.  An
@@ -114,7 +118,9 @@ __device__ __forceinline__ void dispatch_depth(int tb, const w2::Chunk &C, const
                                                float r2, int tile_rows, int seg, int strip,
                                                int lane, int A) {
   if (tb == T || T == TMAX) {
-    w2::tile<P32, T, false>(C, D, r2, tile_rows, seg, strip, lane, A);
+    // 3 rows per loop body: the kernel holds the code of every depth up to
+    // TMAX, and 12-row bodies would take it to one wave per SIMD
+    w2::tile<P32, T, false, 3>(C, D, r2, tile_rows, seg, strip, lane, A);
   } else if constexpr (T < TMAX) {
     dispatch_depth<TMAX, T + 1>(tb, C, D, r2, tile_rows, seg, strip, lane, A);
   }
@@ -170,6 +176,7 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(const BatchTables t) {
     C.xs0 = -G.A;
     C.nstrips = G.nstrips;
     C.tile_begin = 0;
+    C.push_begin = C.push_end = 0;  // the batch's tiles share no buffers
     const w2::Domain D{0, G.ny, 0, G.nx};
     const int tb = (b == G.nblocks - 1) ? G.last_T : G.T;
     dispatch_depth<TMAX>(tb, C, D, G.r2, G.tile_rows, seg, strip, lane, G.A);

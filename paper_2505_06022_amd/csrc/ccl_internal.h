@@ -104,21 +104,34 @@ struct WaveField {      // one chunk buffer as the kernels see it
   int64_t pitch[CCL_MAX_DIMS];
 };
 
+// Rows of a chunk's output that another chunk's next block reads: stored by
+// the launch into that chunk's output buffers as well (2D, splits along
+// rows).  [cr0, cr1) of u^{n+T} into `cur`, [pr0, pr1) of u^{n+T-1} into
+// `prev` (empty ranges allowed).
+struct PushPlan {
+  WaveField cur, prev;
+  int64_t cr0, cr1, pr0, pr1;
+};
+constexpr int kMaxPushPerChunk = 2;
+
 struct WaveChunkPlan {  // host-side plan of one chunk for one block of steps
   Box chunk;
   Box domain;
   WaveField in_prev, in_cur, out_prev, out_cur;
   Box load_prev, load_cur;  // loadable index boxes (region of the buffer ∩ domain)
+  int32_t npush = 0;
+  PushPlan push[kMaxPushPerChunk];
 };
 
 // Rows (2D) or planes (3D) per tile when the caller leaves it to the
-// library: every wave streams (rows + 2*halo) rows and the launch runs in
+// library: every wave streams (rows + 2*halo) rows, rounded up to a whole
+// number of its loop bodies of `granule` rows, and the launch runs in
 // ceil(waves / slots) rounds of concurrently resident waves, so the rows are
-// chosen to minimise rounds * (rows + 2*halo).  `waves_of(rows)` is the
+// chosen to minimise rounds * streamed rows.  `waves_of(rows)` is the
 // launch's wave count for a given rows value (non-increasing in rows).
 template <class F>
 int32_t plan_tile_rows(int64_t slots, int32_t halo, int32_t min_rows, int32_t max_rows,
-                       F waves_of) {
+                       F waves_of, int32_t granule = 1) {
   if (slots < 1) slots = 1;
   if (max_rows < min_rows) max_rows = min_rows;
   int32_t best = max_rows;
@@ -136,7 +149,8 @@ int32_t plan_tile_rows(int64_t slots, int32_t halo, int32_t min_rows, int32_t ma
     }
     const int64_t w = waves_of(lo);
     const double rounds = static_cast<double>((w + slots - 1) / slots);
-    const double cost = rounds * (lo + 2.0 * halo);
+    const int64_t streamed = (lo + 2 * static_cast<int64_t>(halo) + granule - 1) / granule * granule;
+    const double cost = rounds * static_cast<double>(streamed);
     if (cost < best_cost - 1e-9) {
       best_cost = cost;
       best = lo;
@@ -160,9 +174,11 @@ void wave3d_tb_geometry(int32_t T, int32_t *out_cols, int32_t *out_rows, int32_t
 
 // dtype: CCL_DTYPE_* of every buffer; r2 as given (rounded to float for
 // float arithmetic).
+// `pushed` (may be NULL): set to whether every push the plans ask for was
+// made; if any cannot be (count, alignment), none is and it is false.
 ccl_status launch_wave2d(int32_t dtype, int32_t depth, bool in_place, double r2,
                          int32_t tile_rows, const WaveChunkPlan *plans, int32_t nplans,
-                         hipStream_t stream);
+                         hipStream_t stream, bool *pushed = nullptr);
 ccl_status launch_wave3d(int32_t dtype, int32_t depth, bool in_place, double r2,
                          int32_t tile_rows, const WaveChunkPlan *plans, int32_t nplans,
                          hipStream_t stream);

@@ -27,10 +27,13 @@ struct Vec {
   F v[NV];
 };
 
+// kBody: rows per unrolled loop body of the out-of-place 2D update (see
+// wave2d_tile.h); measured per type on the 8192 x 8192 share.
 struct P32 {
   using E = float;  // stored element
   using F = float;  // arithmetic
   static constexpr int NV = 4;
+  static constexpr int kBody = 12;
   static constexpr int kDtype = CCL_DTYPE_F32;
   typedef float Raw __attribute__((ext_vector_type(4)));
   __device__ static F widen(E e) { return e; }
@@ -41,6 +44,7 @@ struct P64 {
   using E = double;
   using F = double;
   static constexpr int NV = 2;
+  static constexpr int kBody = 3;
   static constexpr int kDtype = CCL_DTYPE_F64;
   typedef double Raw __attribute__((ext_vector_type(2)));
   __device__ static F widen(E e) { return e; }
@@ -51,6 +55,7 @@ struct PB16 {
   using E = uint16_t;  // the upper half of a float's bit pattern
   using F = float;
   static constexpr int NV = 4;
+  static constexpr int kBody = 3;
   static constexpr int kDtype = CCL_DTYPE_BF16;
   typedef uint16_t Raw __attribute__((ext_vector_type(4)));
   __device__ static F widen(E e) { return __uint_as_float(static_cast<uint32_t>(e) << 16); }
@@ -67,6 +72,7 @@ struct PH16 {
   using E = _Float16;
   using F = float;
   static constexpr int NV = 4;
+  static constexpr int kBody = 3;
   static constexpr int kDtype = CCL_DTYPE_F16;
   typedef _Float16 Raw __attribute__((ext_vector_type(4)));
   __device__ static F widen(E e) { return static_cast<float>(e); }

@@ -14,6 +14,7 @@ namespace {
 constexpr int kWavesPerBlock = 4;
 constexpr int kThreads = 64 * kWavesPerBlock;
 constexpr int kMaxChunksPerLaunch = 16;
+constexpr int kMaxPushPerLaunch = 16;
 
 struct W2Args {
   int32_t nchunks;
@@ -23,6 +24,7 @@ struct W2Args {
   float r2f;   // r2 rounded to float (float arithmetic)
   double r2d;  // r2 as given (double arithmetic)
   w2::Chunk ch[kMaxChunksPerLaunch];
+  w2::Push push[kMaxPushPerLaunch];
 };
 
 template <class F>
@@ -44,8 +46,12 @@ __global__ __launch_bounds__(kThreads) void wave2d_kernel(const W2Args a) {
   const int local = tile - C.tile_begin;
   const int seg = local / C.nstrips;
   const int strip = local - seg * C.nstrips;
+  w2::PushSet ps;
+  ps.n = C.push_end - C.push_begin;
+#pragma unroll
+  for (int p = 0; p < w2::kMaxPush; ++p) ps.p[p] = a.push[min(C.push_begin + p, kMaxPushPerLaunch - 1)];
   w2::tile<PR, T, IN_PLACE>(C, a.dom, r2_of<typename PR::F>(a), a.tile_rows, seg, strip, lane,
-                            w2::overlap(T, PR::NV));
+                            w2::overlap(T, PR::NV), ps);
 }
 
 template <class PR, int T, bool IP>
@@ -111,6 +117,16 @@ const void *kernel_for(int32_t dtype, int T, bool in_place) {
 
 bool fits_i32(int64_t v) { return v >= INT32_MIN && v <= INT32_MAX; }
 
+// Rows per loop body of the kernel a launch of this type and mode runs.
+int32_t body_rows(int32_t dtype, bool in_place) {
+  switch (dtype) {
+    case CCL_DTYPE_F64: return w2::unroll_of<P64>(in_place);
+    case CCL_DTYPE_BF16: return w2::unroll_of<PB16>(in_place);
+    case CCL_DTYPE_F16: return w2::unroll_of<PH16>(in_place);
+    default: return w2::unroll_of<P32>(in_place);
+  }
+}
+
 }  // namespace
 
 // Concurrent waves the device holds for the depth-T kernel (cached).
@@ -149,12 +165,14 @@ int32_t wave2d_plan_rows(int64_t ny, int64_t nx, int32_t K, int32_t T) {
     return w;
   };
   return plan_tile_rows(wave_slots(T, T == 1), T, std::max(8, T),
-                        static_cast<int32_t>(std::max<int64_t>(rows_max, 8)), waves_of);
+                        static_cast<int32_t>(std::max<int64_t>(rows_max, 8)), waves_of,
+                        w2::unroll_of<P32>(T == 1));
 }
 
 ccl_status launch_wave2d(int32_t dtype, int32_t depth, bool in_place, double r2,
                          int32_t tile_rows, const WaveChunkPlan *plans, int32_t nplans,
-                         hipStream_t stream) {
+                         hipStream_t stream, bool *pushed) {
+  bool all_pushed = true;  // every push the plans ask for is encoded
   const int NV = dtype_group(dtype);
   const int esize = dtype_bytes(dtype);
   if (esize == 0) return fail(CCL_E_INVALID, "unknown dtype %d", dtype);
@@ -227,7 +245,55 @@ ccl_status launch_wave2d(int32_t dtype, int32_t depth, bool in_place, double r2,
                       "chunk %d: buffers must be %d-byte aligned, with pitch a multiple of %d and "
                       "the same region column offset modulo %d", first + k, NV * esize, NV, NV);
       }
+      // halo pushes: the target buffers must hold the rows and the chunk's
+      // columns and take the strips' groups at aligned boundaries
+      C.push_begin = C.push_end = 0;
+      for (int q = 0; q < P.npush && all_pushed; ++q) {
+        const PushPlan &Q = P.push[q];
+        const WaveField *tf[2] = {&Q.cur, &Q.prev};
+        const int64_t rows[2][2] = {{Q.cr0, Q.cr1}, {Q.pr0, Q.pr1}};
+        for (int b = 0; b < 2; ++b) {
+          if (rows[b][1] <= rows[b][0]) continue;
+          const int64_t r = xs0 - tf[b]->off[1];
+          all_pushed = all_pushed && tf[b]->base && (((r % NV) + NV) % NV) == 0 &&
+                       (tf[b]->pitch[0] % NV) == 0 &&
+                       (reinterpret_cast<uintptr_t>(tf[b]->base) & amask) == 0 &&
+                       fits_i32(tf[b]->off[0]) && fits_i32(tf[b]->off[1]) &&
+                       fits_i32(tf[b]->pitch[0]);
+        }
+      }
     }
+    // encode the pushes of this launch's chunks (all or none)
+    int32_t npush = 0;
+    for (int k = 0; k < n && all_pushed; ++k) {
+      const WaveChunkPlan &P = plans[first + k];
+      w2::Chunk &C = a.ch[k];
+      C.push_begin = npush;
+      if (P.npush > w2::kMaxPush) all_pushed = false;
+      for (int q = 0; q < P.npush && all_pushed; ++q) {
+        if (npush == kMaxPushPerLaunch) {
+          all_pushed = false;
+          break;
+        }
+        const PushPlan &Q = P.push[q];
+        w2::Push &W = a.push[npush++];
+        W.cur = Q.cur.base;
+        W.prev = Q.prev.base;
+        W.cur_y0 = static_cast<int32_t>(Q.cur.off[0]);
+        W.cur_x0 = static_cast<int32_t>(Q.cur.off[1]);
+        W.cur_pitch = static_cast<int32_t>(Q.cur.pitch[0]);
+        W.prev_y0 = static_cast<int32_t>(Q.prev.off[0]);
+        W.prev_x0 = static_cast<int32_t>(Q.prev.off[1]);
+        W.prev_pitch = static_cast<int32_t>(Q.prev.pitch[0]);
+        W.cr0 = static_cast<int32_t>(Q.cr0);
+        W.cr1 = static_cast<int32_t>(std::max(Q.cr0, Q.cr1));
+        W.pr0 = static_cast<int32_t>(Q.pr0);
+        W.pr1 = static_cast<int32_t>(std::max(Q.pr0, Q.pr1));
+      }
+      C.push_end = npush;
+    }
+    if (!all_pushed)
+      for (int k = 0; k < n; ++k) a.ch[k].push_begin = a.ch[k].push_end = 0;
     auto waves_of = [&](int32_t r) {
       int64_t w = 0;
       for (int k = 0; k < n; ++k)
@@ -238,7 +304,7 @@ ccl_status launch_wave2d(int32_t dtype, int32_t depth, bool in_place, double r2,
                       ? tile_rows
                       : plan_tile_rows(wave_slots(depth, in_place, dtype), depth, std::max(8, depth),
                                        static_cast<int32_t>(std::max<int64_t>(rows_max, 8)),
-                                       waves_of);
+                                       waves_of, body_rows(dtype, in_place));
     int64_t tiles = 0;
     for (int k = 0; k < n; ++k) {
       w2::Chunk &C = a.ch[k];
@@ -254,6 +320,7 @@ ccl_status launch_wave2d(int32_t dtype, int32_t depth, bool in_place, double r2,
     ccl_status st = launch_dtype(dtype, depth, in_place, a, blocks, stream);
     if (st != CCL_OK) return st;
   }
+  if (pushed) *pushed = all_pushed;
   return CCL_OK;
 }
 

@@ -31,15 +31,28 @@
 namespace ccl {
 namespace w2 {
 
-// Rows loaded ahead of use.  It equals the ring length, so the unrolled
-// body's copy u finds every level's newest row in ring slot u and nothing
-// is moved between iterations.
-constexpr int kPrefetch = 3;
-#ifndef CCL_W2_UNROLL
-#define CCL_W2_UNROLL 3
+// Rows loaded ahead of use, and rows per unrolled loop body.  The body is
+// a whole number of turns of both the three-row ring and the prefetch
+// slots, so its copy uu finds every level's newest row in ring slot uu % 3
+// and its prefetched rows in slot uu % kPrefetch, and nothing is moved
+// between iterations.  The out-of-place update holds its stores until the
+// next body (see tile()), so within a body only loads are outstanding and
+// each use waits for its own row's loads alone; the wait for everything
+// outstanding comes once per body, at its head.  For float32 a 12-row body
+// makes that wait 4x rarer than a 3-row one (measured on the 8192 x 8192
+// share with 32-row tiles: 28.6 ms per 1000 steps at T = 8 against 30.5,
+// 32.0 against 34.6 at T = 7, 37.0 against 39.6 at T = 6), at 12 held rows
+// per level pair (210 VGPRs at T = 8, two waves per SIMD).  The float64 and
+// 16-bit types keep 3-row bodies (PR::kBody; 12 rows made them slower), as
+// does the in-place T = 1 update, which stores as it goes.
+#ifndef CCL_W2_PREFETCH
+#define CCL_W2_PREFETCH 3
 #endif
-constexpr int kUnroll = CCL_W2_UNROLL;
-static_assert(kUnroll % kPrefetch == 0, "the unrolled body must be whole ring turns");
+constexpr int kPrefetch = CCL_W2_PREFETCH;
+template <class PR>
+__host__ __device__ constexpr int unroll_of(bool in_place) {
+  return in_place ? 3 : PR::kBody;
+}
 
 
 // Overlap columns per side and output columns per strip for depth T, with
@@ -64,6 +77,30 @@ struct Chunk {
   int32_t xs0;                         // first column of strip 0
   int32_t nstrips;
   int32_t tile_begin;
+  int32_t push_begin, push_end;        // this chunk's entries of the launch's pushes
+};
+
+// A halo push: rows of this launch's output that another chunk's next
+// launch reads from its own buffers.  The launch stores them there too, so
+// no separate exchange is needed before the next block of steps.  Rows
+// [cr0, cr1) of u^{n+T} go to `cur`, rows [pr0, pr1) of u^{n+T-1} to `prev`
+// (the other chunk's output buffers of this launch, which nothing reads
+// during it); the columns are the source chunk's, which for a split along
+// rows are the whole domain width.
+struct Push {
+  void *cur;
+  void *prev;
+  int32_t cur_y0, cur_x0, cur_pitch;
+  int32_t prev_y0, prev_x0, prev_pitch;
+  int32_t cr0, cr1, pr0, pr1;
+};
+
+// The pushes of one chunk, passed to the tile by value (kept in scalar
+// registers): a chunk of a split along rows has at most two neighbours.
+constexpr int kMaxPush = 2;
+struct PushSet {
+  int32_t n;
+  Push p[kMaxPush];
 };
 
 struct Domain {
@@ -174,6 +211,28 @@ __device__ __forceinline__ typename PR::Raw load_group(const void *base, int32_t
   return STREAM ? __builtin_nontemporal_load(p) : *p;
 }
 
+// Loads a group as 32-bit words at the device-coherent level (relaxed
+// agent-scope atomic loads, which do not hit the vector L1): used to read
+// back what this lane has just stored.
+template <class PR>
+__device__ __forceinline__ typename PR::Raw load_group_coherent(const void *base, int32_t by0,
+                                                                int32_t bx0, int32_t pitch,
+                                                                int row, int xg) {
+  using Raw = typename PR::Raw;
+  constexpr int kWords = sizeof(Raw) / 4;
+  static_assert(sizeof(Raw) % 4 == 0, "groups are whole 32-bit words");
+  const uint32_t *p = reinterpret_cast<const uint32_t *>(
+      static_cast<const typename PR::E *>(base) + static_cast<int64_t>(row - by0) * pitch +
+      (xg - bx0));
+  uint32_t w[kWords];
+#pragma unroll
+  for (int i = 0; i < kWords; ++i)
+    w[i] = __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  Raw r;
+  __builtin_memcpy(&r, w, sizeof(Raw));
+  return r;
+}
+
 // Widens a loaded group, zero outside the loadable box: the row
 // (wave-uniform) and the lane's columns.
 template <class PR>
@@ -224,9 +283,12 @@ __device__ __forceinline__ Vec<F, NV> force_zero(Vec<F, NV> v, bool row_in, cons
 // The descriptors are copied into registers once: read through a reference
 // inside the loop, they would be reloaded after every store (the compiler
 // cannot rule out that a store aliases them).
-template <class PR, int T, bool IN_PLACE>
+template <class PR, int T, bool IN_PLACE, int U = unroll_of<PR>(IN_PLACE)>
 __device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, typename PR::F r2,
-                                     int tile_rows, int seg, int strip, int lane, int A) {
+                                     int tile_rows, int seg, int strip, int lane, int A,
+                                     const PushSet &PSref = PushSet{0, {}}) {
+  constexpr int kUnroll = U;
+  static_assert(U % kPrefetch == 0 && U % 3 == 0, "whole turns of the ring and the prefetch");
   constexpr int NV = PR::NV;
   using F = typename PR::F;
   using V = Vec<F, NV>;
@@ -253,9 +315,20 @@ __device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, type
   // a strip whose columns all lie in the domain needs no column mask
   const bool interior_cols = xs >= D.gx0 && xs + 64 * NV <= D.gx1;
 
+  // halo pushes that meet this tile's output rows (only tiles at the edges
+  // of a chunk have any; wave-uniform); made after the streaming loop
+  const PushSet PS = PSref;
+  bool has_push = false;
+#pragma unroll
+  for (int p = 0; p < kMaxPush; ++p) {
+    const Push &P = PS.p[p];
+    has_push = has_push ||
+               (p < PS.n && ((P.cr0 < y1 && P.cr1 > y0) || (P.pr0 < y1 && P.pr1 > y0)));
+  }
+
   // ring[k][s]: the last three rows of level k in rotating slots; at the
-  // unrolled copy u the newest row goes to slot u, the middle one is in
-  // (u+2)%3 and the oldest in (u+1)%3
+  // unrolled copy uu the newest row goes to slot uu%3, the middle one is in
+  // (uu+2)%3 and the oldest in (uu+1)%3
   V ring[T][3];
 #pragma unroll
   for (int k = 0; k < T; ++k) ring[k][0] = ring[k][1] = ring[k][2] = zero_vec<F, NV>();
@@ -272,7 +345,8 @@ __device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, type
   Raw q1[kPrefetch], q0[kPrefetch];
 #pragma unroll
   for (int u = 0; u < kPrefetch; ++u) {
-    q1[u] = load_group<PR, false>(C.in_cur, C.ic_y0, C.ic_x0, C.ic_pitch, row_c(first + u), xgc);
+    q1[u] = load_group<PR, false>(C.in_cur, C.ic_y0, C.ic_x0, C.ic_pitch,
+                                  row_c(first + u), xgc);
     q0[u] = load_group<PR, IN_PLACE>(C.in_prev, C.ip_y0, C.ip_x0, C.ip_pitch,
                                      row_p(first + u - 1), xgp);
   }
@@ -311,8 +385,8 @@ __device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, type
     }
 #pragma unroll
     for (int uu = 0; uu < kUnroll; ++uu) {
-      const int u = uu % kPrefetch;
-      const int NEW = u, MID = (u + 2) % 3, OLD = (u + 1) % 3;
+      const int u = uu % kPrefetch;  // prefetch slot
+      const int NEW = uu % 3, MID = (uu + 2) % 3, OLD = (uu + 1) % 3;
       const int i = first + jb + uu;  // row of level 0 arriving now
       ring[0][NEW] = mask_group<PR>(q1[u], i >= C.lc_y0 && i < C.lc_y1, lc);
       V pv = mask_group<PR>(q0[u], i - 1 >= lpy0 && i - 1 < lpy1, lp);
@@ -350,6 +424,46 @@ __device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, type
         const int r = first + jlast + uu - T;
         store_group<PR>(C.out_cur, C.oc_y0, C.oc_x0, C.oc_pitch, r, xl, out, d1[uu]);
         store_group<PR>(C.out_prev, C.op_y0, C.op_x0, C.op_pitch, r, xl, out, d0[uu]);
+      }
+    }
+  }
+  if (has_push) {
+    // the pushed rows are this lane's own groups of its output buffers, just
+    // stored: read them back and store them into the other chunks' buffers
+    // (at most 2T rows per field, in the tiles at the edges of a chunk
+    // only).  A lane reads only what it stored itself, so it is enough to
+    // wait until its stores have completed and to read at the device-coherent
+    // level (an agent-scope fence would also write back the whole L2 of the
+    // XCD: measured 8% slower launches)
+    __builtin_amdgcn_s_waitcnt(0);
+    // all of a push's rows (at most T) are read first and then stored, so
+    // the reads overlap
+    auto copy_rows = [&](const void *src, int32_t sy0, int32_t sx0, int32_t spitch, void *dst,
+                         int32_t dy0, int32_t dx0, int32_t dpitch, int r0, int r1) {
+      Raw buf[T];
+#pragma unroll
+      for (int j = 0; j < T; ++j)
+        if (r0 + j < r1) buf[j] = load_group_coherent<PR>(src, sy0, sx0, spitch, r0 + j, xl);
+#pragma unroll
+      for (int j = 0; j < T; ++j)
+        if (r0 + j < r1)
+          store_group<PR>(dst, dy0, dx0, dpitch, r0 + j, xl, out, mask_group<PR>(buf[j], true, out));
+    };
+    if (out.any) {
+#pragma unroll
+      for (int p = 0; p < kMaxPush; ++p) {
+        const Push &P = PS.p[p];
+        if (p >= PS.n) continue;
+        // a push covers at most T rows of the chunk, and a tile's share of
+        // them is one contiguous range
+        const int c0 = max(y0, P.cr0), c1 = min(y1, P.cr1);
+        if (c0 < c1)
+          copy_rows(C.out_cur, C.oc_y0, C.oc_x0, C.oc_pitch, P.cur, P.cur_y0, P.cur_x0,
+                    P.cur_pitch, c0, min(c1, c0 + T));
+        const int p0 = max(y0, P.pr0), p1 = min(y1, P.pr1);
+        if (!IN_PLACE && p0 < p1)
+          copy_rows(C.out_prev, C.op_y0, C.op_x0, C.op_pitch, P.prev, P.prev_y0, P.prev_x0,
+                    P.prev_pitch, p0, min(p1, p0 + T));
       }
     }
   }

@@ -5,6 +5,7 @@
 // transfers inferred from the mappers), then one launch advances every chunk
 // T steps.  The host only plans and enqueues; the caller's descriptor arrays
 // are rotated to name the newest levels.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <utility>
@@ -30,6 +31,44 @@ WaveField field_of(const ccl_chunk_buffer &b) {
 bool holds(const ccl_chunk_buffer &b, const ccl_chunk &c, int64_t e) {
   Box need = intersect(grow(chunk_box(c), e), domain_box(c));
   return contains(box_of(b.region), need);
+}
+
+// Every chunk spans the domain's full width: a split along rows (2D).
+bool row_split(int32_t nchunks, const ccl_chunk *chunks) {
+  for (int k = 0; k < nchunks; ++k) {
+    const Box c = chunk_box(chunks[k]), d = domain_box(chunks[k]);
+    if (c.lo[1] != d.lo[1] || c.hi[1] != d.hi[1]) return false;
+  }
+  return true;
+}
+
+// The halo rows chunk k's launch can store straight into the other chunks'
+// output buffers for the next block of `next` steps: the rows of chunk k
+// within `next` (u^{n+T}) and `next` - 1 (u^{n+T-1}) rows of chunk j, the
+// boxes the exchange before that block would copy.  False (no pushes) if a
+// chunk has more neighbours than a plan holds.
+bool plan_pushes(int32_t nchunks, const ccl_chunk *chunks, const ccl_chunk_buffer *out_cur,
+                 const ccl_chunk_buffer *out_prev, int next, WaveChunkPlan *plans) {
+  for (int k = 0; k < nchunks; ++k) plans[k].npush = 0;
+  for (int k = 0; k < nchunks; ++k) {
+    const Box ck = chunk_box(chunks[k]);
+    for (int j = 0; j < nchunks; ++j) {
+      if (j == k) continue;
+      const Box cj = chunk_box(chunks[j]);
+      PushPlan Q;
+      Q.cr0 = std::max(ck.lo[0], cj.lo[0] - next);
+      Q.cr1 = std::min(ck.hi[0], cj.hi[0] + next);
+      Q.pr0 = std::max(ck.lo[0], cj.lo[0] - (next - 1));
+      Q.pr1 = std::min(ck.hi[0], cj.hi[0] + (next - 1));
+      if (!out_prev) Q.pr1 = Q.pr0;  // in place: u^{n-1} of the next block needs no halo
+      if (Q.cr1 <= Q.cr0 && Q.pr1 <= Q.pr0) continue;
+      if (plans[k].npush == kMaxPushPerChunk) return false;
+      Q.cur = field_of(out_cur[j]);
+      Q.prev = out_prev ? field_of(out_prev[j]) : Q.cur;
+      plans[k].push[plans[k].npush++] = Q;
+    }
+  }
+  return true;
 }
 
 }  // namespace
@@ -118,12 +157,18 @@ extern "C" ccl_status ccl_wave_step(const ccl_wave_params *p, int32_t nchunks,
   hipStream_t stream = static_cast<hipStream_t>(hip_stream);
   std::vector<WaveChunkPlan> plans(nchunks);
   std::vector<CopyJob> jobs;
+  // 2D splits along rows: each launch also stores the rows the next block's
+  // halos need into the neighbours' output buffers, so only the first block
+  // runs the exchange (the same boxes, the same values)
+  const bool can_push = dims == 2 && nchunks > 1 && row_split(nchunks, chunks);
+  bool halos_ready = false;
   for (int done = 0; done < nsteps;) {
     const int tb = (nsteps - done) < T ? (nsteps - done) : T;
     const bool in_place = tb == 1;
+    const int next = std::min(T, nsteps - done - tb);  // the next block's steps (0: none)
     // 1. inferred transfers: u^n with NEIGHBORHOOD(tb), u^{n-1} with NEIGHBORHOOD(tb-1)
     jobs.clear();
-    if (nchunks > 1) {
+    if (nchunks > 1 && !halos_ready) {
       ccl_range_mapper m;
       memset(&m, 0, sizeof(m));
       m.kind = CCL_MAP_NEIGHBORHOOD;
@@ -152,13 +197,20 @@ extern "C" ccl_status ccl_wave_step(const ccl_wave_params *p, int32_t nchunks,
       P.load_prev = intersect(box_of(u_prev[k].region), P.domain);
       P.load_cur = intersect(box_of(u_cur[k].region), P.domain);
     }
+    bool pushed = false;
+    if (can_push && next > 0)
+      pushed = plan_pushes(nchunks, chunks, in_place ? u_prev : w_cur, in_place ? nullptr : w_prev,
+                           next, plans.data());
+    if (!pushed)
+      for (int k = 0; k < nchunks; ++k) plans[k].npush = 0;
     if (dims == 2)
       st = launch_wave2d(dtype, tb, in_place, p->r2, p->tile_rows, plans.data(), nchunks,
-                         stream);
+                         stream, pushed ? &pushed : nullptr);
     else
       st = launch_wave3d(dtype, tb, in_place, p->r2, p->tile_rows, plans.data(), nchunks,
                          stream);
     if (st != CCL_OK) return st;
+    halos_ready = pushed;
     // 3. rotate roles so u_cur names the newest level
     for (int k = 0; k < nchunks; ++k) {
       if (in_place) {

@@ -5,6 +5,9 @@
     python -m paper_2505_06022_amd.learn remeasure --out DIR [--dims 3 --min-depth 2]
     python -m paper_2505_06022_amd.learn train    --data DIR/samples.json --model MODEL.json
     python -m paper_2505_06022_amd.learn evaluate --model MODEL.json --out DIR [--shapes 200]
+    python -m paper_2505_06022_amd.learn energy-check --model MODEL.json --out DIR [--count 24]
+    python -m paper_2505_06022_amd.learn summarise --out DIR [--model MODEL.json --dims 2]
+    python -m paper_2505_06022_amd.learn report --out DIR --md profiles/costmodel_evaluation.md
 
 collect  : seeded training shapes (2D sides log-uniform on 256..16384, 3D
            sides 64..768), a seeded subset of each shape's candidates, each
@@ -230,13 +233,34 @@ def train(data_path, model_path, epochs=4000, lr=3e-3, seed=0, seeds=1, val_frac
     return m
 
 
+def training_shapes():
+    """Every shape the training samples come from (2D and 3D)."""
+    from . import tune
+    shapes, _ = tune.sample_space(250, TRAIN_SHAPE_SEED, 0, SAMPLE_SEED, 40, 40)
+    return set(tuple(s) for s in shapes)
+
+
 def held_out_shapes(n_shapes, dims=2):
     """Seeded held-out shapes: 2D as the training shapes' distribution, 3D
-    with sides 64..768; seeds that no training set uses."""
+    with sides 64..768, drawn from seeds that no training set uses; a drawn
+    shape that is also a training shape, or was drawn before, is skipped
+    and the next one drawn instead, so the n_shapes are distinct and none
+    was seen in training."""
     import synth
-    if dims == 2:
-        return synth.cost_model_shapes(n_shapes, HELD_OUT_SEED)
-    return synth.cost_model_shapes_3d(n_shapes, HELD_OUT_SEED + 100)
+    train = training_shapes()
+    draw = (lambda k: synth.cost_model_shapes(k, HELD_OUT_SEED)) if dims == 2 else \
+        (lambda k: synth.cost_model_shapes_3d(k, HELD_OUT_SEED + 100))
+    k = n_shapes
+    while True:
+        out, seen = [], set()
+        for sh in draw(k):  # the draws are prefix-stable in k
+            if sh in train or sh in seen:
+                continue
+            seen.add(sh)
+            out.append(sh)
+            if len(out) == n_shapes:
+                return out
+        k *= 2
 
 
 def _tag(dims):
@@ -290,28 +314,34 @@ def evaluate(model_path, out_dir, n_shapes=200, start=0, count=None, budget_s=1e
     return rows
 
 
-def energy_check(model_path, out_dir, n_shapes=200, count=4, window_s=1.0, top=3, repeats=3):
-    """For the first held-out shapes: device energy of the model's energy
-    pick and of the `top` fastest configs of the time sweep (the energy
-    judge is restricted to those, since a full energy sweep would need ~2 s
-    of counter time per candidate).  Each config's energy is the median over
-    `repeats` windows with a valid reading: one window reads the ~1 Hz
-    counter at two updates only, and now and then a window reads a third
-    to two thirds of what the windows around it read; the median of three
-    discards one such reading."""
+def energy_check(model_path, out_dir, n_shapes=200, start=0, count=24, window_s=1.0, top=10,
+                 repeats=3, budget_s=1e9):
+    """For held-out shapes [start, start+count): device energy of the model's
+    energy pick, of its time pick and of the `top` fastest configs of the
+    time sweep (the energy judge is restricted to those, since a full energy
+    sweep would need ~2 s of counter time per candidate).  Each config's
+    energy is the median over `repeats` windows with a valid reading: one
+    window reads the ~1 Hz counter at two updates only, and now and then a
+    window reads a third to two thirds of what the windows around it read;
+    the median of three discards one such reading.  Rows are written to
+    energy_check_part_<start>.json after every shape."""
     from . import tune
-    import synth
-    shapes = synth.cost_model_shapes(n_shapes, HELD_OUT_SEED)[:count]
+    os.makedirs(out_dir, exist_ok=True)
+    shapes = held_out_shapes(n_shapes)[start:start + count]
     model = tune.CostModel.load(model_path)
     out = []
-    for sh in shapes:
+    t0 = time.perf_counter()
+    path = os.path.join(out_dir, f"energy_check_part_{start:04d}.json")
+    for i, sh in enumerate(shapes):
         cfgs = tune.candidates(sh)
         res = tune.measure(cfgs, reps=2, steps=tune.steps_for(sh, target_cell_steps=1.5e9))
         keys = [tune.cfg_key(c) for c in cfgs]
         order = list(np.argsort([r["s_per_step"] for r in res])[:top])
         pick_cfg, _ = model.pick(sh, "energy")
         pick = keys.index(tune.cfg_key(pick_cfg))
-        idx = sorted(set(int(j) for j in order) | {pick})
+        tpick_cfg, _ = model.pick(sh, "time")
+        tpick = keys.index(tune.cfg_key(tpick_cfg))
+        idx = sorted(set(int(j) for j in order) | {pick, tpick})
         reads = {j: [] for j in idx}
         for _ in range(repeats):
             meas = tune.measure([cfgs[j] for j in idx], energy_window_s=window_s)
@@ -320,18 +350,22 @@ def energy_check(model_path, out_dir, n_shapes=200, count=4, window_s=1.0, top=3
                 if v is not None and np.isfinite(v) and v > 0:
                     reads[j].append(v)
         e = {j: float(np.median(v)) for j, v in reads.items() if v}
-        if pick not in e:
-            _log(f"  energy {sh}: no valid energy window for the pick; shape skipped")
+        if pick not in e or tpick not in e:
+            _log(f"  energy {sh}: no valid energy window for a pick; shape skipped")
             continue
         best = min(e, key=e.get)
-        out.append(dict(shape=list(sh), pick=keys[pick], best=keys[best], e_pick=e[pick],
-                        e_best=e[best], ratio=e[pick] / e[best],
+        out.append(dict(index=start + i, shape=list(sh), pick=keys[pick], time_pick=keys[tpick],
+                        best=keys[best], e_pick=e[pick], e_time_pick=e[tpick], e_best=e[best],
+                        ratio=e[pick] / e[best], ratio_time_pick=e[tpick] / e[best],
                         reads={str(keys[j][1:]): v for j, v in reads.items()},
                         time_pick_over_best=res[pick]["s_per_step"] / res[order[0]]["s_per_step"]))
         _log(f"  energy {sh}: pick/best {e[pick] / e[best]:.3f} ({keys[pick][1:]} vs "
-             f"{keys[best][1:]})")
-    with open(os.path.join(out_dir, "energy_check.json"), "w") as f:
-        json.dump(out, f)
+             f"{keys[best][1:]}), time pick/best {e[tpick] / e[best]:.3f} "
+             f"({time.perf_counter() - t0:.0f} s)")
+        with open(path, "w") as f:
+            json.dump(out, f)
+        if time.perf_counter() - t0 > budget_s:
+            break
     model.close()
     return out
 
@@ -360,12 +394,20 @@ def summarise(out_dir, model_path=None, dims=2):
             summary[f"top{k}_verified"] = dict(geomean_over_best=gm(rk),
                                                frac_within_5pct=float(np.mean(rk <= 1.05)),
                                                worst=float(rk.max()))
-    ep = os.path.join(out_dir, "energy_check.json")
-    if dims == 2 and os.path.exists(ep):
-        with open(ep) as f:
-            er = json.load(f)
-        summary["energy"] = dict(shapes=len(er), geomean_pick_over_best=gm([r["ratio"] for r in er]),
-                                 frac_within_5pct=float(np.mean([r["ratio"] <= 1.05 for r in er])))
+    er = []
+    for p in sorted(glob.glob(os.path.join(out_dir, "energy_check_part_*.json"))):
+        with open(p) as f:
+            er.extend(json.load(f))
+    if dims == 2 and er:
+        summary["energy"] = dict(
+            shapes=len(er), judge="median of 3 windows; the 10 fastest of the time sweep, the "
+                                  "energy pick and the time pick",
+            geomean_pick_over_best=gm([r["ratio"] for r in er]),
+            frac_within_5pct=float(np.mean([r["ratio"] <= 1.05 for r in er])),
+            worst=float(max(r["ratio"] for r in er)),
+            geomean_time_pick_over_best=gm([r["ratio_time_pick"] for r in er]))
+        with open(os.path.join(out_dir, "energy_check.json"), "w") as f:
+            json.dump(er, f)
     with open(os.path.join(out_dir, f"evaluation{_tag(dims)}.json"), "w") as f:
         json.dump(dict(summary=summary, rows=rows), f)
     if model_path:
@@ -376,6 +418,46 @@ def summarise(out_dir, model_path=None, dims=2):
             json.dump(doc, f)
     _log(json.dumps(summary))
     return summary
+
+
+def report(out_dir, md_path):
+    """Per-shape rows of the evaluations (2D, 3D) and of the energy check as
+    one markdown file: shape, the sweep's best config, the model's pick and
+    the measured ratios."""
+    lines = ["# Cost-model evaluation on held-out shapes, per shape", "",
+             "Configs are (K chunks, T, tile rows; 0 = automatic). Ratios are measured "
+             "time (or energy) over the best of the judge set, on the same kernels.", ""]
+    for dims in (2, 3):
+        p = os.path.join(out_dir, f"evaluation{_tag(dims)}.json")
+        if not os.path.exists(p):
+            continue
+        with open(p) as f:
+            doc = json.load(f)
+        sm = doc["summary"]
+        lines += [f"## {dims}D time: {sm['shapes']} shapes, every candidate measured", "",
+                  "summary-json: " + json.dumps(sm), "",
+                  "| # | shape | best | pick | pick/best | top-3/best | default/best |",
+                  "|---|---|---|---|---|---|---|"]
+        for r in doc["rows"]:
+            lines.append(f"| {r['index']} | {'x'.join(map(str, r['shape']))} | "
+                         f"{tuple(r['best'][1:])} | {tuple(r['pick'][1:])} | {r['ratio']:.3f} | "
+                         f"{r.get('ratio_top3', float('nan')):.3f} | {r['ratio_default']:.2f} |")
+        lines.append("")
+    p = os.path.join(out_dir, "energy_check.json")
+    if os.path.exists(p):
+        with open(p) as f:
+            er = json.load(f)
+        lines += [f"## 2D energy: {len(er)} shapes, median of 3 windows per config", "",
+                  "| # | shape | least energy | energy pick | pick/least | time pick/least |",
+                  "|---|---|---|---|---|---|"]
+        for r in er:
+            lines.append(f"| {r['index']} | {'x'.join(map(str, r['shape']))} | "
+                         f"{tuple(r['best'][1:])} | {tuple(r['pick'][1:])} | {r['ratio']:.3f} | "
+                         f"{r['ratio_time_pick']:.3f} |")
+        lines.append("")
+    with open(md_path, "w") as f:
+        f.write("\n".join(lines))
+    _log(f"wrote {md_path}")
 
 
 def main(argv=None):
@@ -417,14 +499,20 @@ def main(argv=None):
     ec = sub.add_parser("energy-check")
     ec.add_argument("--model", required=True)
     ec.add_argument("--out", required=True)
-    ec.add_argument("--count", type=int, default=4)
+    ec.add_argument("--start", type=int, default=0)
+    ec.add_argument("--count", type=int, default=24)
+    ec.add_argument("--top", type=int, default=10)
     ec.add_argument("--repeats", type=int, default=3)
+    ec.add_argument("--budget", type=float, default=1e9)
+    rp = sub.add_parser("report")
+    rp.add_argument("--out", required=True)
+    rp.add_argument("--md", required=True)
     sm = sub.add_parser("summarise")
     sm.add_argument("--out", required=True)
     sm.add_argument("--model", default=None)
     sm.add_argument("--dims", type=int, default=2, choices=(2, 3))
     a = ap.parse_args(argv)
-    if a.cmd != "summarise":
+    if a.cmd not in ("summarise", "report"):
         import torch
         torch.cuda.set_device(0)
     if a.cmd == "collect":
@@ -439,7 +527,10 @@ def main(argv=None):
     elif a.cmd == "evaluate":
         evaluate(a.model, a.out, a.shapes, a.start, a.count, a.budget, dims=a.dims)
     elif a.cmd == "energy-check":
-        energy_check(a.model, a.out, count=a.count, repeats=a.repeats)
+        energy_check(a.model, a.out, start=a.start, count=a.count, top=a.top,
+                     repeats=a.repeats, budget_s=a.budget)
+    elif a.cmd == "report":
+        report(a.out, a.md)
     else:
         summarise(a.out, a.model, a.dims)
     return 0

@@ -25,8 +25,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SAXPY_N = 1 << 26
 
 
-SOURCES = {2: ("wave2d_tile.h", "wave2d.hip", "wave_step.cpp", "halo.hip"),
-           3: ("wave3d_cell.h", "wave3d.hip", "wave3d_tb.hip", "wave_step.cpp", "halo.hip")}
+SOURCES = {2: ("prec.h", "wave2d_tile.h", "wave2d.hip", "wave_step.cpp", "halo.hip"),
+           3: ("prec.h", "wave3d_cell.h", "wave3d.hip", "wave3d_tb.hip", "wave_step.cpp",
+               "halo.hip")}
 
 
 def kernel_source_hash(dims: int = 2) -> str:

@@ -235,8 +235,8 @@ def test_batched_workload_full(batch, mode):
     times, bitwise equal to the oracle (u^n and u^{n-1})."""
     import paper_2505_06022_amd as ccl
     from paper_2505_06022_amd.fields import BatchedWaves
-    specs, flags = ((batch["specs"], 0) if mode == "persistent" else
-                    (batch["specs_pg"], ccl.CCL_BATCH_PER_GRID))
+    specs, flags = {"persistent": (batch["specs"], 0),
+                    "per_grid": (batch["specs_pg"], ccl.CCL_BATCH_PER_GRID)}[mode]
     print(f"batch mode {mode}, configs from {batch['how']}: depths "
           f"{sorted(set(s['depth'] for s in specs))}", flush=True)
     bw = BatchedWaves(specs, flags=flags, fill=float("nan"))

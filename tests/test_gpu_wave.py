@@ -262,7 +262,21 @@ def test_timing_counts_launches():
     n, ms = ccl.ccl_timing_query(ccl.CCL_KERNEL_STENCIL)
     nh, _ = ccl.ccl_timing_query(ccl.CCL_KERNEL_HALO)
     ccl.ccl_timing_enable(False)
-    assert n == 3 and ms > 0 and nh == 3
+    # rows split: one exchange before the first block, the stencil launches
+    # store the later halos into the neighbours' buffers themselves
+    assert n == 3 and ms > 0 and nh == 1
+    # columns split: no pushes, an exchange before every block
+    cc = ChunkedWave((0, 0), (256, 256), 2, 0.25, depth=4, split_dim=1)
+    cc.scatter(u0, u0)
+    torch.cuda.synchronize()
+    ccl.ccl_timing_enable(True)
+    cc.step(10)
+    torch.cuda.synchronize()
+    n, _ = ccl.ccl_timing_query(ccl.CCL_KERNEL_STENCIL)
+    nh, _ = ccl.ccl_timing_query(ccl.CCL_KERNEL_HALO)
+    ccl.ccl_timing_enable(False)
+    assert n == 3 and nh == 3
+    assert np.array_equal(cc.gather("cur"), cw.gather("cur"))
 
 
 @pytest.mark.parametrize("shape,K,T", [((1, 300), 1, 1), ((1, 300), 1, 4), ((57, 1), 3, 2),

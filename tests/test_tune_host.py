@@ -167,3 +167,15 @@ def test_summarise_3d_parts(tmp_path):
     meta = json.loads((tmp_path / "m.json").read_text())["meta"]
     assert meta["evaluation"] == dict(shapes=200) and meta["evaluation_3d"]["shapes"] == 4
     assert (tmp_path / "evaluation_3d.json").exists() and not (tmp_path / "evaluation.json").exists()
+
+
+def test_held_out_shapes_disjoint_from_training():
+    """The held-out shapes of the cost-model evaluation are distinct and
+    none of them is a training shape (2D and 3D)."""
+    from paper_2505_06022_amd import learn
+    train = learn.training_shapes()
+    for dims, n in ((2, 200), (3, 40)):
+        h = learn.held_out_shapes(n, dims)
+        assert len(h) == n and len(set(h)) == n
+        assert not set(h) & train
+        assert all(len(s) == dims for s in h)
