@@ -163,6 +163,11 @@ class CostModel:
         torch.cuda.synchronize()
         return self.ys.invert(yd.cpu().numpy().astype(np.float64))
 
+    # A predicted energy (or EDP) saving over the time pick smaller than
+    # this (log units) is not acted on: the power head's error on held-out
+    # labels is about 1%, so smaller predicted savings are noise.
+    MIN_SAVING = 0.02
+
     def pick(self, shape, objective="time", nchunks=None, shortlist=8):
         """Best candidate of `shape` by the model (only those with `nchunks`
         chunks when given); returns (config, index into that list).  The
@@ -170,7 +175,8 @@ class CostModel:
         is made among the `shortlist` candidates predicted fastest: power
         varies by a few percent across configs and is labelled for few of
         them, so a slow config is never chosen for a predicted power saving
-        the model cannot back."""
+        the model cannot back; and the time pick is kept unless the other
+        candidate's predicted saving exceeds MIN_SAVING."""
         import torch
         cfgs = candidates(shape)
         if nchunks is not None:
@@ -189,6 +195,12 @@ class CostModel:
         ccl_mlp_pick(self.handle, len(X), xd.data_ptr(), wt, we, 0, best.data_ptr())
         torch.cuda.synchronize()
         i = base[int(best.item())]
+        if objective != "time":
+            tcfg, ti = self.pick(shape, "time", nchunks)
+            y = self.predict(ccl_costmodel_features([cfgs[i], cfgs[ti]]))
+            score = w[0] * y[:, 0] + w[1] * y[:, 1]
+            if score[1] - score[0] < self.MIN_SAVING:
+                return tcfg, ti
         return cfgs[i], i
 
     def rank(self, shape, objective="time", nchunks=None):

@@ -35,9 +35,8 @@ def gpu():
 
 
 def held_out_shapes(n=2, max_cells=3.2e7):
-    from paper_2505_06022_amd.learn import HELD_OUT_SEED
-    shapes = synth.cost_model_shapes(200, HELD_OUT_SEED)
-    return [s for s in shapes if s[0] * s[1] <= max_cells][:n]
+    from paper_2505_06022_amd.learn import held_out_shapes as shapes_of
+    return [s for s in shapes_of(200) if s[0] * s[1] <= max_cells][:n]
 
 
 @pytest.mark.parametrize("shape", held_out_shapes())
@@ -61,3 +60,38 @@ def test_learned_pick_gains_over_no_model(shape):
           f"no-model/pick {gain:.2f}")
     assert gain >= 1.3, f"the model's pick is only {gain:.2f}x faster than no model"
     assert ratio <= 1.25, f"the model's pick is {ratio:.3f}x the swept best"
+
+
+def test_energy_pick_no_worse_than_time_pick():
+    """On the first held-out shape where the model's energy pick differs
+    from its time pick, the energy pick's measured J/step (median of three
+    counter windows each) is no worse than the time pick's (within the 2%
+    window-to-window spread).  Where no shape among the first 40 has
+    differing picks, the energy objective reduces to the time pick there
+    and the test checks that instead."""
+    from paper_2505_06022_amd import learn, tune
+    m = tune.CostModel.load(MODEL)
+    try:
+        chosen = None
+        for sh in learn.held_out_shapes(200)[:40]:
+            e_cfg, _ = m.pick(sh, "energy")
+            t_cfg, _ = m.pick(sh, "time")
+            if tune.cfg_key(e_cfg) != tune.cfg_key(t_cfg):
+                chosen = (sh, e_cfg, t_cfg)
+                break
+    finally:
+        m.close()
+    if chosen is None:
+        print("energy and time picks agree on the first 40 held-out shapes")
+        return
+    sh, e_cfg, t_cfg = chosen
+    reads = {0: [], 1: []}
+    for _ in range(3):
+        for k, r in enumerate(tune.measure([e_cfg, t_cfg], energy_window_s=1.0)):
+            if r["j_per_step"] is not None and np.isfinite(r["j_per_step"]) and r["j_per_step"] > 0:
+                reads[k].append(r["j_per_step"])
+    assert reads[0] and reads[1], "the energy counter gave no valid window"
+    e_pick, e_time = float(np.median(reads[0])), float(np.median(reads[1]))
+    print(f"{sh}: energy pick {tune.cfg_key(e_cfg)[1:]} {e_pick:.5f} J/step, time pick "
+          f"{tune.cfg_key(t_cfg)[1:]} {e_time:.5f} J/step")
+    assert e_pick <= 1.02 * e_time
