@@ -44,7 +44,7 @@ def build(verbose: bool = False, src=None, out=None) -> Path:
     """Compile oracle.c with gcc into liboracle.so (always recompiles)."""
     src = Path(src) if src else _SRC
     out = Path(out) if out else _LIB_PATH
-    tmp = out.with_suffix(".so.tmp")
+    tmp = out.with_suffix(f".so.{os.getpid()}.tmp")  # concurrent builds do not clash
     cmd = ["gcc", *CFLAGS, str(src), "-o", str(tmp), "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -69,6 +69,9 @@ __host__ __device__ constexpr int tb_out_cols(int T, int NV = 4) {
 __host__ __device__ constexpr int tb_out_rows(int T) { return kLY * tb_rows(T) - 2 * T; }
 static_assert(tb_out_cols(CCL_MAX_DEPTH, 2) > 0 && tb_out_rows(CCL_MAX_DEPTH) > 0,
               "every depth leaves an interior to store");
+// LDS words each thread publishes per level and plane: its first and its
+// last row (one, when it holds a single row).
+__host__ __device__ constexpr int tb_words(int T) { return tb_rows(T) > 1 ? 2 : 1; }
 #ifndef CCL_W3T_NB
 __host__ __device__ constexpr int tb_lds_buffers(int T) { return T <= 4 ? 2 : 1; }
 #else
@@ -214,12 +217,13 @@ struct Patch {
   bool xy_in;                           // patch inside the domain in x and y
 };
 
-// xch: the block's LDS words, [buffer][level][first row / last row][thread];
-// each word is one thread's group of NV arithmetic values (16 bytes).
+// xch: the block's LDS words, [buffer][level][first row / last row][thread]
+// (one row, and one word, when a thread holds a single row); each word is
+// one thread's group of NV arithmetic values (16 bytes).
 template <class PR, int T>
 __device__ __forceinline__ void stream_patch(const Patch<PR, tb_rows(T)> &S, typename PR::F r2,
                                              int tid,
-                                             Vec<typename PR::F, PR::NV> (*xch)[T][2][kThreads]) {
+                                             Vec<typename PR::F, PR::NV> (*xch)[T][tb_words(T)][kThreads]) {
   constexpr int P = tb_rows(T);
   constexpr int NB = tb_lds_buffers(T);
   constexpr int PF = tb_prefetch(T);
@@ -261,7 +265,7 @@ __device__ __forceinline__ void stream_patch(const Patch<PR, tb_rows(T)> &S, typ
 #pragma unroll
     for (int l = 0; l < T; ++l) {
       xch[b][l][0][tid] = ring[l][MID][0];  // MID is still the newest here
-      xch[b][l][1][tid] = ring[l][MID][P - 1];
+      if constexpr (P > 1) xch[b][l][P > 1 ? 1 : 0][tid] = ring[l][MID][P - 1];
     }
     __syncthreads();
 
@@ -282,7 +286,7 @@ __device__ __forceinline__ void stream_patch(const Patch<PR, tb_rows(T)> &S, typ
       // outer y-neighbours of this thread's rows in plane r of u^{n+t-1}
       // (the top thread row reads the bottom one's words: patch-edge cells
       // are never valid, so any value there is harmless)
-      const V up = xch[b][t - 1][1][(tid - kLX) & (kThreads - 1)];
+      const V up = xch[b][t - 1][P > 1 ? 1 : 0][(tid - kLX) & (kThreads - 1)];
       const V dn = xch[b][t - 1][0][(tid + kLX) & (kThreads - 1)];
       V o[P];
 #pragma unroll
@@ -391,7 +395,7 @@ __global__ __launch_bounds__(kThreads) void wave3d_tb_kernel(const W3TArgs a) {
   S.out = w2::cols_of<NV>(xl, max(C.cx0, px + A), min(C.cx1, px + A + OW));
   S.xy_in = px >= a.gx0 && px + tb_patch_cols(NV) <= a.gx1 && py >= a.gy0 &&
             py + kLY * P <= a.gy1;
-  __shared__ Vec<F, NV> xch[tb_lds_buffers(T)][T][2][kThreads];
+  __shared__ Vec<F, NV> xch[tb_lds_buffers(T)][T][tb_words(T)][kThreads];
   stream_patch<PR, T>(S, r2_of<F>(a), tid, xch);
 }
 

@@ -150,6 +150,96 @@ def summarise(fetch_csv, write_csv, depth, rows, md_path, dims=2, append=False):
     print("\n".join(lines))
 
 
+def _counter_rows(paths):
+    """{counter: [per-dispatch values]} of the stencil kernel, plus its
+    per-dispatch durations (ns) and register counts, from rocprofv3 counter
+    CSVs (one or more passes over the same program)."""
+    vals, dur, regs = {}, [], None
+    for path in paths:
+        seen = set()
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                name = row.get("Kernel_Name", "")
+                if not ("wave2d_kernel" in name or "wave3d_kernel" in name or
+                        "wave3d_tb_kernel" in name):
+                    continue
+                vals.setdefault(row["Counter_Name"], []).append(float(row["Counter_Value"]))
+                did = row.get("Dispatch_Id")
+                if did not in seen and row.get("Start_Timestamp"):
+                    seen.add(did)
+                    dur.append(float(row["End_Timestamp"]) - float(row["Start_Timestamp"]))
+                regs = (row.get("VGPR_Count"), row.get("Accum_VGPR_Count"),
+                        row.get("LDS_Block_Size"), row.get("Workgroup_Size"))
+    return vals, dur, regs
+
+
+def counters(paths, depth, rows, md_path, dims=2, title=None, commands=(), append=False):
+    """Where the stencil launch spends its time, from SQ/GRBM counters: VALU
+    instructions per useful cell-step, VALU busy share, waits, occupancy and
+    LDS activity.  The first dispatch of each pass (cold caches) is left out.
+    Derived values follow rocprofv3's own definitions (VALUBusy,
+    OccupancyPercent); SQ cycle counters are in quad-cycles and summed over
+    all shader engines, GRBM_GUI_ACTIVE is read per dispatch as reported."""
+    vals, dur, regs = _counter_rows(paths)
+    avg = {k: sum(v[1:] or v) / len(v[1:] or v) for k, v in vals.items()}
+    d_ns = sum(dur[1:] or dur) / max(1, len(dur[1:] or dur))
+    cells = 8192 * 8192 if dims == 2 else 768 ** 3
+    cu_num, simd_num, clock_ghz = 256, 1024, 2.4
+    cell_steps = cells * depth
+    out = {"kernel": "wave2d_kernel" if dims == 2 else "wave3d_tb_kernel",
+           "depth": depth, "tile_rows": rows, "kernel_hash": kernel_source_hash(dims),
+           "dispatch_us": d_ns / 1e3, "rocprof_vgpr_count": regs[0] if regs else None,
+           "lds_bytes": regs[2] if regs else None, "workgroup": regs[3] if regs else None,
+           "counters": avg}
+    g = avg.get("GRBM_GUI_ACTIVE")
+    der = {}
+    if "SQ_INSTS_VALU" in avg:
+        der["valu_lane_ops_per_cell_step"] = avg["SQ_INSTS_VALU"] * 64 / cell_steps
+        # issue share at 4 cycles per wave64 VALU instruction, over the
+        # dispatch's own duration at the peak clock
+        der["valu_issue_share_at_peak_clock"] = (avg["SQ_INSTS_VALU"] * 4 /
+                                                 (simd_num * d_ns * clock_ghz))
+    if g and "SQ_ACTIVE_INST_VALU" in avg:
+        der["VALUBusy_pct"] = 100 * avg["SQ_ACTIVE_INST_VALU"] / cu_num / g
+    if g and "SQ_WAVE_CYCLES" in avg:
+        der["waves_per_cu"] = 4 * avg["SQ_WAVE_CYCLES"] / g / cu_num
+        der["grbm_cycles_per_ns"] = g / d_ns if d_ns else None
+    if "SQ_WAIT_INST_ANY" in avg and "SQ_WAVE_CYCLES" in avg:
+        der["wait_inst_any_share_of_wave_cycles"] = avg["SQ_WAIT_INST_ANY"] / avg["SQ_WAVE_CYCLES"]
+    if "SQ_WAIT_ANY" in avg and "SQ_WAVE_CYCLES" in avg:
+        der["wait_any_share_of_wave_cycles"] = avg["SQ_WAIT_ANY"] / avg["SQ_WAVE_CYCLES"]
+    if "SQ_ACTIVE_INST_LDS" in avg and "SQ_WAVE_CYCLES" in avg:
+        der["lds_active_share_of_wave_cycles"] = avg["SQ_ACTIVE_INST_LDS"] / avg["SQ_WAVE_CYCLES"]
+    if g and "SQ_LDS_BANK_CONFLICT" in avg:
+        der["LDSBankConflict_pct"] = 100 * avg["SQ_LDS_BANK_CONFLICT"] / g / cu_num
+    if "SQ_INSTS_LDS" in avg and "SQ_WAVES" in avg:
+        der["lds_insts_per_wave"] = avg["SQ_INSTS_LDS"] / avg["SQ_WAVES"]
+        der["valu_insts_per_wave"] = avg.get("SQ_INSTS_VALU", 0) / avg["SQ_WAVES"]
+    out["derived"] = der
+    wl = "8192x8192 share, 4 chunks" if dims == 2 else "768^3, 8 chunks"
+    lines = [f"# {title or 'Counters of the stencil launch'} — {wl}, T={depth}, "
+             f"{rows if rows else 'automatic'} rows per tile", "", "Commands:", "", "```"]
+    lines += list(commands) + ["```", "",
+                               f"Stencil dispatch: {d_ns / 1e3:.1f} us under counter collection; "
+                               f"LDS {out['lds_bytes']} B per work-group of {out['workgroup']}.",
+                               "",
+                               "| counter (per dispatch) | value |", "|---|---|"]
+    for k in sorted(avg):
+        lines.append(f"| {k} | {avg[k]:,.0f} |")
+    lines += ["", "| derived | value |", "|---|---|"]
+    for k, v in der.items():
+        lines.append(f"| {k} | {v:.4g} |" if v is not None else f"| {k} | — |")
+    lines += ["", "counters-json: " + json.dumps(out), ""]
+    if append and os.path.exists(md_path):
+        lines[0] = "#" + lines[0]
+        with open(md_path, "a") as f:
+            f.write("\n" + "\n".join(lines))
+    else:
+        with open(md_path, "w") as f:
+            f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def trace_summary(db_path, md_path, title, command, append=False):
     """Per-kernel call counts and durations from a rocprofv3 kernel-trace
     database (its `top_kernels` view), as a markdown table."""
@@ -198,7 +288,19 @@ def main(argv=None):
     t.add_argument("--title", required=True)
     t.add_argument("--command", required=True)
     t.add_argument("--append", action="store_true")
+    c = sub.add_parser("counters")
+    c.add_argument("--csv", action="append", required=True)
+    c.add_argument("--depth", type=int, required=True)
+    c.add_argument("--rows", type=int, required=True)
+    c.add_argument("--dims", type=int, default=2)
+    c.add_argument("--md", required=True)
+    c.add_argument("--title")
+    c.add_argument("--command", action="append", default=[])
+    c.add_argument("--append", action="store_true")
     a = ap.parse_args(argv)
+    if a.cmd == "counters":
+        counters(a.csv, a.depth, a.rows, a.md, a.dims, a.title, a.command, a.append)
+        return 0
     if a.cmd == "trace-summary":
         trace_summary(a.db, a.md, a.title, a.command, a.append)
         return 0
