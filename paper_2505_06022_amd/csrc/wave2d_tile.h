@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "prec.h"
 
@@ -371,9 +372,20 @@ __device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, type
   // kUnroll rows per loop iteration (a multiple of the ring length): the
   // compiler waits for all outstanding memory operations once per
   // iteration, at the loop head, so a longer body exposes that latency
-  // less often
-  for (int jb = 0; jb < nrows; jb += kUnroll) {
-    if constexpr (DEFER) {
+  // less often.
+  //
+  // Warm-up: level k at streamed row m (row first + m - k) feeds a stored
+  // output only if m >= 2k (level k is needed on rows [first + k, ...): the
+  // outputs' dependency cone narrows by one row per level), so the first
+  // body computes level k only at its copies uu >= 2k and the levels above
+  // a skipped one are skipped too.  Everything a computed level reads was
+  // computed (copies uu-2..uu of level k-1, and uu-2 >= 2(k-1)), so the
+  // stored values are unchanged; the skipped work is T(T+1) of the tile's
+  // T * nrows level-rows when 2T <= kUnroll, nearly as much otherwise (at
+  // T = 8 with 12-row bodies, 66 of the 72 rows the warm-up wastes).
+  auto body = [&](auto first_tag, int jb) {
+    constexpr bool FIRST = decltype(first_tag)::value;
+    if constexpr (DEFER && !FIRST) {
 #pragma unroll
       for (int uu = 0; uu < kUnroll; ++uu) {
         if (dok[uu]) {
@@ -396,6 +408,7 @@ __device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, type
                                        row_p(i + kPrefetch - 1), xgp);
 #pragma unroll
       for (int k = 1; k <= T; ++k) {
+        if (FIRST && uu < 2 * k) break;  // not needed yet (compile-time)
         const int r = i - k;  // row of level k computed now
         V nv = step_group<PR>(ring[k - 1][OLD], ring[k - 1][MID], ring[k - 1][NEW], pv, r2);
         const bool row_in = r >= D.gy0 && r < D.gy1;  // wave-uniform
@@ -415,6 +428,10 @@ __device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, type
         }
       }
     }
+  };
+  body(std::true_type(), 0);
+  for (int jb = kUnroll; jb < nrows; jb += kUnroll) {
+    body(std::false_type(), jb);
     jlast = jb;
   }
   if constexpr (DEFER) {

@@ -1,17 +1,23 @@
 // 3D seven-point leapfrog stencil, T = 2..8 steps per pass over HBM.
 //
-// Work unit: one 512-thread block owns a patch of 16*NV columns by 32*P
-// rows and streams along z through a segment of planes.  Thread (ly, lx)
-// holds NV consecutive columns (one vector group: four floats, two doubles
-// or four 16-bit values; see prec.h) of P consecutive rows; the 16 threads
-// of a patch row are one DPP row, so x-neighbours come from DPP row shifts.  A taller patch re-computes less of its overlap with the
-// neighbouring patches (at T = 6 a 64 x 64 patch stores 48 x 52 cells, a
-// 64 x 32 patch 48 x 20), at the same registers per thread.  For every level l < T the thread keeps the last three planes
+// Work unit: one block of 1024 threads (16 waves, the most a CU holds at
+// up to 128 VGPRs per lane) owns a patch of 16*NV columns by 64*P rows and
+// streams along z through a segment of planes.  Thread (ly, lx) holds NV
+// consecutive columns (one vector group: four floats, two doubles or four
+// 16-bit values; see prec.h) of P consecutive rows (P = 1); the 16 threads
+// of a patch row are one DPP row, so x-neighbours come from DPP row shifts.
+// A taller patch re-computes less of its overlap with the neighbouring
+// patches (at T = 6 a 64 x 64 patch stores 48 x 52 cells, a 64 x 32 patch
+// 48 x 20).  For every level l < T the thread keeps the last three planes
 // of u^{n+l} over its cells in registers (a rotating three-slot ring), so
 // z-neighbours are register reads.  y-neighbours inside a thread's P rows
 // are its own registers; the first and last of its rows take their outer
 // neighbour from the adjacent thread row, published in LDS once per plane
-// (two 16-byte words per thread and level, one barrier per plane).
+// (one 16-byte word per thread and level when P = 1, two when P > 1; one
+// barrier per plane).  One row per thread in 16 waves, rather than two rows
+// in 8 waves, halves the registers per lane (111 against 204 at T = 6) and
+// doubles the waves each SIMD can switch between while others wait on
+// memory or the barrier: 11-13% faster at T = 6..8 on 768^3.
 //
 // At iteration i the block loads plane i of u^n (level 0) and, level by
 // level, computes plane i-l of u^{n+l}; level T gives u^{n+T} at plane i-T,
@@ -37,7 +43,7 @@ namespace {
 // Block shape: kThreads threads in rows of kLX; a patch row is kLX groups
 // of NV columns and the patch has kThreads / kLX thread rows.
 #ifndef CCL_W3T_THREADS
-#define CCL_W3T_THREADS 512
+#define CCL_W3T_THREADS 1024
 #endif
 #ifndef CCL_W3T_LX
 #define CCL_W3T_LX 16
@@ -53,7 +59,7 @@ constexpr int kMaxChunksPerLaunch = 8;
 // Rows per thread, planes loaded ahead, overlap, output extent and LDS
 // buffering for depth T.
 #ifndef CCL_W3T_ROWS
-#define CCL_W3T_ROWS 2
+#define CCL_W3T_ROWS 1
 #endif
 __host__ __device__ constexpr int tb_rows(int) { return CCL_W3T_ROWS; }
 #ifndef CCL_W3T_PF
@@ -73,7 +79,11 @@ static_assert(tb_out_cols(CCL_MAX_DEPTH, 2) > 0 && tb_out_rows(CCL_MAX_DEPTH) > 
 // last row (one, when it holds a single row).
 __host__ __device__ constexpr int tb_words(int T) { return tb_rows(T) > 1 ? 2 : 1; }
 #ifndef CCL_W3T_NB
-__host__ __device__ constexpr int tb_lds_buffers(int T) { return T <= 4 ? 2 : 1; }
+// Two buffers (one barrier per plane) where they fit in the 160 KiB of LDS,
+// else one (a second barrier before the words are overwritten).
+__host__ __device__ constexpr int tb_lds_buffers(int T) {
+  return 2 * T * tb_words(T) * kThreads * 16 <= 160 * 1024 ? 2 : 1;
+}
 #else
 __host__ __device__ constexpr int tb_lds_buffers(int) { return CCL_W3T_NB; }
 #endif
@@ -257,8 +267,9 @@ __device__ __forceinline__ void stream_patch(const Patch<PR, tb_rows(T)> &S, typ
   // One iteration; PH = iteration count mod 3 names the ring slots: before
   // it the newest plane of every level sits in slot (PH+2)%3, after it in
   // slot PH, with the middle in (PH+2)%3 and the oldest in (PH+1)%3.
-  auto iteration = [&](auto ph, int i) {
+  auto iteration = [&](auto ph, auto warm, int i) {
     constexpr int PH = decltype(ph)::value;
+    constexpr bool WARM = decltype(warm)::value;
     constexpr int NEW = PH, MID = (PH + 2) % 3, OLD = (PH + 1) % 3;
     const int b = NB == 2 ? (i & 1) : 0;
     if (NB == 1) __syncthreads();  // every thread has read the last plane's words
@@ -281,6 +292,10 @@ __device__ __forceinline__ void stream_patch(const Patch<PR, tb_rows(T)> &S, typ
 
 #pragma unroll
     for (int t = 1; t <= T; ++t) {
+      // warm-up: level t of this iteration's plane feeds a stored output
+      // only from the 2t-th iteration on (block-uniform; levels above a
+      // skipped one are skipped too)
+      if (WARM && i - i0 < 2 * t) break;
       const int r = i - t;  // plane of u^{n+t} computed now
       const bool z_in = r >= S.gz0 && r < S.gz1;  // block-uniform
       // outer y-neighbours of this thread's rows in plane r of u^{n+t-1}
@@ -329,10 +344,30 @@ __device__ __forceinline__ void stream_patch(const Patch<PR, tb_rows(T)> &S, typ
     }
   };
 
-  for (int n = 0; n < n_iter; n += 3) {
-    iteration(std::integral_constant<int, 0>(), i0 + n);
-    if (n + 1 < n_iter) iteration(std::integral_constant<int, 1>(), i0 + n + 1);
-    if (n + 2 < n_iter) iteration(std::integral_constant<int, 2>(), i0 + n + 2);
+  // The first 2T iterations (in whole turns of the ring) skip the levels
+  // whose planes no stored output needs yet: level t at iteration i0 + m
+  // lies on plane i0 + m - t, and the outputs' dependency cone needs level
+  // t only from plane i0 + t on.  What a computed level reads was computed
+  // (levels t-1 and t-2 from iteration m-2 >= 2(t-1) on), so stored values
+  // are unchanged; T(T+1) of the segment's T * n_iter level-planes are
+  // skipped (768^3 at T = 7: 2.6% faster).  At T = 8 the second copy of the
+  // loop pushes the kernel past 128 VGPRs into spills (15% slower), so the
+  // deepest kernel keeps the single loop.
+  using warm = std::true_type;
+  using steady = std::false_type;
+  int n = 0;
+  if constexpr (T < CCL_MAX_DEPTH) {
+    const int n_warm = min(n_iter, 3 * ((2 * T + 2) / 3));
+    for (; n < n_warm; n += 3) {
+      iteration(std::integral_constant<int, 0>(), warm(), i0 + n);
+      if (n + 1 < n_iter) iteration(std::integral_constant<int, 1>(), warm(), i0 + n + 1);
+      if (n + 2 < n_iter) iteration(std::integral_constant<int, 2>(), warm(), i0 + n + 2);
+    }
+  }
+  for (; n < n_iter; n += 3) {
+    iteration(std::integral_constant<int, 0>(), steady(), i0 + n);
+    if (n + 1 < n_iter) iteration(std::integral_constant<int, 1>(), steady(), i0 + n + 1);
+    if (n + 2 < n_iter) iteration(std::integral_constant<int, 2>(), steady(), i0 + n + 2);
   }
 }
 

@@ -443,10 +443,12 @@ def summarise(out_dir, model_path=None, dims=2):
             summary[f"top{k}_verified"] = dict(geomean_over_best=gm(rk),
                                                frac_within_5pct=float(np.mean(rk <= 1.05)),
                                                worst=float(rk.max()))
-    er = []
+    by_index = {}  # a shape measured in two parts counts once (the later part)
     for p in sorted(glob.glob(os.path.join(out_dir, "energy_check_part_*.json"))):
         with open(p) as f:
-            er.extend(json.load(f))
+            for r in json.load(f):
+                by_index[r["index"]] = r
+    er = [by_index[i] for i in sorted(by_index)]
     if dims == 2 and er:
         summary["energy"] = dict(
             shapes=len(er), judge="median of 3 windows; the 10 fastest of the time sweep, the "

@@ -173,48 +173,53 @@ def _counter_rows(paths):
     return vals, dur, regs
 
 
-def counters(paths, depth, rows, md_path, dims=2, title=None, commands=(), append=False):
+def counters(paths, depth, rows, md_path, dims=2, title=None, commands=(), append=False,
+             kernel_hash=None):
     """Where the stencil launch spends its time, from SQ/GRBM counters: VALU
     instructions per useful cell-step, VALU busy share, waits, occupancy and
     LDS activity.  The first dispatch of each pass (cold caches) is left out.
-    Derived values follow rocprofv3's own definitions (VALUBusy,
-    OccupancyPercent); SQ cycle counters are in quad-cycles and summed over
-    all shader engines, GRBM_GUI_ACTIVE is read per dispatch as reported."""
+    rocprofv3 sums each counter over the device's blocks: SQ counters over
+    all shader engines (cycle counters in quad-cycles), GRBM_GUI_ACTIVE over
+    the 8 XCDs, so one XCD's active cycles are GRBM_GUI_ACTIVE / 8 (the
+    `max` that rocprofv3's own VALUBusy and OccupancyPercent divide by)."""
     vals, dur, regs = _counter_rows(paths)
     avg = {k: sum(v[1:] or v) / len(v[1:] or v) for k, v in vals.items()}
     d_ns = sum(dur[1:] or dur) / max(1, len(dur[1:] or dur))
     cells = 8192 * 8192 if dims == 2 else 768 ** 3
-    cu_num, simd_num, clock_ghz = 256, 1024, 2.4
+    cu_num, xcds = 256, 8
     cell_steps = cells * depth
     out = {"kernel": "wave2d_kernel" if dims == 2 else "wave3d_tb_kernel",
-           "depth": depth, "tile_rows": rows, "kernel_hash": kernel_source_hash(dims),
+           "depth": depth, "tile_rows": rows,
+           "kernel_hash": kernel_hash or kernel_source_hash(dims),
            "dispatch_us": d_ns / 1e3, "rocprof_vgpr_count": regs[0] if regs else None,
            "lds_bytes": regs[2] if regs else None, "workgroup": regs[3] if regs else None,
            "counters": avg}
     g = avg.get("GRBM_GUI_ACTIVE")
+    g = g / xcds if g else None  # active cycles of one XCD
     der = {}
     if "SQ_INSTS_VALU" in avg:
         der["valu_lane_ops_per_cell_step"] = avg["SQ_INSTS_VALU"] * 64 / cell_steps
-        # issue share at 4 cycles per wave64 VALU instruction, over the
-        # dispatch's own duration at the peak clock
-        der["valu_issue_share_at_peak_clock"] = (avg["SQ_INSTS_VALU"] * 4 /
-                                                 (simd_num * d_ns * clock_ghz))
+    if g and d_ns:
+        der["clock_ghz"] = g / d_ns
     if g and "SQ_ACTIVE_INST_VALU" in avg:
-        der["VALUBusy_pct"] = 100 * avg["SQ_ACTIVE_INST_VALU"] / cu_num / g
+        # quad-cycles of VALU work per CU over the dispatch's cycles: the
+        # share of time the SIMDs issue vector instructions
+        der["valu_busy_share"] = avg["SQ_ACTIVE_INST_VALU"] / cu_num / g
     if g and "SQ_WAVE_CYCLES" in avg:
         der["waves_per_cu"] = 4 * avg["SQ_WAVE_CYCLES"] / g / cu_num
-        der["grbm_cycles_per_ns"] = g / d_ns if d_ns else None
     if "SQ_WAIT_INST_ANY" in avg and "SQ_WAVE_CYCLES" in avg:
         der["wait_inst_any_share_of_wave_cycles"] = avg["SQ_WAIT_INST_ANY"] / avg["SQ_WAVE_CYCLES"]
     if "SQ_WAIT_ANY" in avg and "SQ_WAVE_CYCLES" in avg:
         der["wait_any_share_of_wave_cycles"] = avg["SQ_WAIT_ANY"] / avg["SQ_WAVE_CYCLES"]
+    if "SQ_WAIT_INST_LDS" in avg and "SQ_WAVE_CYCLES" in avg:
+        der["wait_inst_lds_share_of_wave_cycles"] = avg["SQ_WAIT_INST_LDS"] / avg["SQ_WAVE_CYCLES"]
     if "SQ_ACTIVE_INST_LDS" in avg and "SQ_WAVE_CYCLES" in avg:
         der["lds_active_share_of_wave_cycles"] = avg["SQ_ACTIVE_INST_LDS"] / avg["SQ_WAVE_CYCLES"]
     if g and "SQ_LDS_BANK_CONFLICT" in avg:
-        der["LDSBankConflict_pct"] = 100 * avg["SQ_LDS_BANK_CONFLICT"] / g / cu_num
-    if "SQ_INSTS_LDS" in avg and "SQ_WAVES" in avg:
-        der["lds_insts_per_wave"] = avg["SQ_INSTS_LDS"] / avg["SQ_WAVES"]
+        der["lds_bank_conflict_share"] = avg["SQ_LDS_BANK_CONFLICT"] / g / cu_num
+    if "SQ_WAVES" in avg:
         der["valu_insts_per_wave"] = avg.get("SQ_INSTS_VALU", 0) / avg["SQ_WAVES"]
+        der["lds_insts_per_wave"] = avg.get("SQ_INSTS_LDS", 0) / avg["SQ_WAVES"]
     out["derived"] = der
     wl = "8192x8192 share, 4 chunks" if dims == 2 else "768^3, 8 chunks"
     lines = [f"# {title or 'Counters of the stencil launch'} — {wl}, T={depth}, "
@@ -297,9 +302,12 @@ def main(argv=None):
     c.add_argument("--title")
     c.add_argument("--command", action="append", default=[])
     c.add_argument("--append", action="store_true")
+    c.add_argument("--kernel-hash", help="source hash the counters were taken on, when it "
+                                          "is not the current source's")
     a = ap.parse_args(argv)
     if a.cmd == "counters":
-        counters(a.csv, a.depth, a.rows, a.md, a.dims, a.title, a.command, a.append)
+        counters(a.csv, a.depth, a.rows, a.md, a.dims, a.title, a.command, a.append,
+                 a.kernel_hash)
         return 0
     if a.cmd == "trace-summary":
         trace_summary(a.db, a.md, a.title, a.command, a.append)

@@ -335,7 +335,7 @@ def test_batch_create_validation_no_launch():
 def test_costmodel_features_host():
     """Features of three configs written out by hand from the kernels'
     tiling (2D strips of 256 columns, 3D one-step tiles of 256 x 4, 3D
-    blocked patches of 64 x 32)."""
+    blocked patches of 64 x 64 cells streamed by 16 waves)."""
     import math
     import numpy as np
     c2 = ccl.make_tune_config((1024, 4096), 4, 8, 64)
@@ -360,10 +360,10 @@ def test_costmodel_features_host():
     s3 = ccl.ccl_wave_slots(3, 1)
     want3 = [math.log2(96), math.log2(768), math.log2(768), 1, math.log2(red3), 3, 5, 1,
              fill(waves3, s3), math.log2(1 + halo3), 12.0, math.log2(waves3)]
-    # 3D, T = 5: 8-wave patches of 64 x 64 cells writing 48 x 54; chunks of 33, 33, 34 planes
+    # 3D, T = 5: 16-wave patches of 64 x 64 cells writing 48 x 54; chunks of 33, 33, 34 planes
     segs = [math.ceil(33 / 16), math.ceil(33 / 16), math.ceil(34 / 16)]
     tiles = [s * math.ceil(300 / 48) * math.ceil(200 / 54) for s in segs]
-    waves3b = 8 * sum(tiles)
+    waves3b = 16 * sum(tiles)
     red3b = sum(t * (16 + 10) * 64 * 64 for t in tiles) / (100 * 200 * 300)
     halo3b = 2 * 2 * 9 * (4 * 200 * 300) * 2 / 5
     s3b = ccl.ccl_wave_slots(3, 5)

@@ -121,6 +121,52 @@ def test_traffic_summary_sections(tmp_path):
     assert bench.load_traffic(8, 64, str(md)) is None
 
 
+def test_counter_summary_derived_values(tmp_path):
+    """The limiter summary averages each counter over the stencil's
+    dispatches (the first, cold one left out) across passes, and derives
+    VALU work per useful cell-step, busy shares and waves per CU from them."""
+    import csv
+    import json
+    from paper_2505_06022_amd import profile_run as pr
+
+    def fake(path, counters):
+        with open(path, "w", newline="") as f:
+            w = csv.DictWriter(f, ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value",
+                                   "Start_Timestamp", "End_Timestamp", "VGPR_Count",
+                                   "Accum_VGPR_Count", "LDS_Block_Size", "Workgroup_Size"])
+            w.writeheader()
+            for d in range(3):
+                for name, vals in counters.items():
+                    w.writerow(dict(Dispatch_Id=d, Kernel_Name="wave3d_tb_kernel<P32, 6>",
+                                    Counter_Name=name, Counter_Value=vals[d],
+                                    Start_Timestamp=1000 * d, End_Timestamp=1000 * d + 500,
+                                    VGPR_Count=200, Accum_VGPR_Count=0, LDS_Block_Size=98304,
+                                    Workgroup_Size=512))
+                w.writerow(dict(Dispatch_Id=d, Kernel_Name="saxpy_kernel", Counter_Name="SQ_WAVES",
+                                Counter_Value=1, Start_Timestamp=0, End_Timestamp=1))
+
+    cells = 768 ** 3
+    a, b = tmp_path / "a.csv", tmp_path / "b.csv"
+    fake(a, {"SQ_INSTS_VALU": [1, 6 * cells / 64 * 10, 6 * cells / 64 * 12],
+             "SQ_WAVE_CYCLES": [1, 256e3, 256e3], "SQ_WAIT_INST_ANY": [1, 64e3, 64e3],
+             "SQ_ACTIVE_INST_VALU": [1, 128e3, 128e3], "GRBM_GUI_ACTIVE": [1, 2000, 2000]})
+    fake(b, {"SQ_WAVES": [1, 1000, 1000], "SQ_INSTS_LDS": [1, 5e5, 5e5]})
+    md = tmp_path / "c.md"
+    pr.counters([str(a), str(b)], 6, 0, str(md), dims=3, title="t", commands=["cmd"])
+    doc = json.loads(md.read_text().split("counters-json: ")[1].splitlines()[0])
+    d = doc["derived"]
+    assert abs(d["valu_lane_ops_per_cell_step"] - 11.0) < 1e-9
+    # GRBM_GUI_ACTIVE is summed over 8 XCDs: one XCD was active 250 cycles
+    # of the 500 ns dispatch
+    assert abs(d["clock_ghz"] - 0.5) < 1e-12
+    assert abs(d["valu_busy_share"] - 128e3 / 256 / 250) < 1e-12
+    assert abs(d["waves_per_cu"] - 4 * 256e3 / 250 / 256) < 1e-12
+    assert abs(d["wait_inst_any_share_of_wave_cycles"] - 0.25) < 1e-12
+    assert abs(d["lds_insts_per_wave"] - 500.0) < 1e-9
+    assert abs(doc["dispatch_us"] - 0.5) < 1e-12
+    assert doc["counters"]["SQ_WAVES"] == 1000
+
+
 def test_held_out_3d_shapes_are_not_trained_on():
     from paper_2505_06022_amd import learn
     trained, _ = tune.sample_space(250, learn.TRAIN_SHAPE_SEED, 1, 0, 40, 40)
