@@ -376,16 +376,21 @@ __device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, type
   //
   // Warm-up: level k at streamed row m (row first + m - k) feeds a stored
   // output only if m >= 2k (level k is needed on rows [first + k, ...): the
-  // outputs' dependency cone narrows by one row per level), so the first
-  // body computes level k only at its copies uu >= 2k and the levels above
-  // a skipped one are skipped too.  Everything a computed level reads was
-  // computed (copies uu-2..uu of level k-1, and uu-2 >= 2(k-1)), so the
-  // stored values are unchanged; the skipped work is T(T+1) of the tile's
-  // T * nrows level-rows when 2T <= kUnroll, nearly as much otherwise (at
-  // T = 8 with 12-row bodies, 66 of the 72 rows the warm-up wastes).
-  auto body = [&](auto first_tag, int jb) {
-    constexpr bool FIRST = decltype(first_tag)::value;
-    if constexpr (DEFER && !FIRST) {
+  // outputs' dependency cone narrows by one row per level), so the bodies
+  // at the start of the stream (the first, and those after it that lie
+  // wholly within the first 2T rows) are separate copies in which level k
+  // is computed only at rows m >= 2k, a compile-time condition, and the
+  // levels above a skipped one are skipped too.  Everything a computed
+  // level reads was computed (rows m-2..m of level k-1, and m-2 >= 2(k-1)),
+  // so the stored values are unchanged; the skipped work is T(T+1) of the
+  // tile's T * nrows level-rows, or nearly (at T = 8 with 12-row bodies,
+  // 66 of the 72 rows the warm-up wastes: one copy of the body covers rows
+  // 0..11).
+  constexpr int kWarmBodies = 2 * T > kUnroll ? 1 + (2 * T - kUnroll) / kUnroll : 1;
+  // JB: the compile-time first row of a warm-up body, -1 in the steady loop
+  auto body = [&](auto jb_tag, int jb) {
+    constexpr int JB = decltype(jb_tag)::value;
+    if constexpr (DEFER && JB != 0) {
 #pragma unroll
       for (int uu = 0; uu < kUnroll; ++uu) {
         if (dok[uu]) {
@@ -408,7 +413,7 @@ __device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, type
                                        row_p(i + kPrefetch - 1), xgp);
 #pragma unroll
       for (int k = 1; k <= T; ++k) {
-        if (FIRST && uu < 2 * k) break;  // not needed yet (compile-time)
+        if (JB >= 0 && JB + uu < 2 * k) break;  // not needed yet (compile-time)
         const int r = i - k;  // row of level k computed now
         V nv = step_group<PR>(ring[k - 1][OLD], ring[k - 1][MID], ring[k - 1][NEW], pv, r2);
         const bool row_in = r >= D.gy0 && r < D.gy1;  // wave-uniform
@@ -429,9 +434,18 @@ __device__ __forceinline__ void tile(const Chunk &Cref, const Domain &Dref, type
       }
     }
   };
-  body(std::true_type(), 0);
-  for (int jb = kUnroll; jb < nrows; jb += kUnroll) {
-    body(std::false_type(), jb);
+  auto warm_up = [&](auto self, auto jb_tag) {
+    constexpr int JB = decltype(jb_tag)::value;
+    if (JB == 0 || JB < nrows) {  // the first body always runs (nrows > 0)
+      body(jb_tag, JB);
+      jlast = JB;
+    }
+    if constexpr (JB / kUnroll + 1 < kWarmBodies)
+      self(self, std::integral_constant<int, JB + kUnroll>());
+  };
+  warm_up(warm_up, std::integral_constant<int, 0>());
+  for (int jb = kWarmBodies * kUnroll; jb < nrows; jb += kUnroll) {
+    body(std::integral_constant<int, -1>(), jb);
     jlast = jb;
   }
   if constexpr (DEFER) {

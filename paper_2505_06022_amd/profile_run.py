@@ -64,6 +64,127 @@ def run(depth: int, rows: int, blocks: int = 6, dims: int = 2):
           flush=True)
 
 
+def run_batch(specs_out=None):
+    """The 64-grid batch (per-grid depth from the cost model) stepped once
+    by the persistent kernel and once grid by grid (CCL_BATCH_PER_GRID),
+    both launched directly (no graph), then the calibration SAXPY.  The
+    launch specs go to `specs_out` (JSON) for the summary."""
+    sys.path.insert(0, ROOT)
+    import torch
+
+    import paper_2505_06022_amd as ccl
+    import synth
+    from paper_2505_06022_amd import tune
+    from paper_2505_06022_amd.fields import BatchedWaves
+    torch.cuda.set_device(0)
+    grids = synth.batched_grids()
+    specs, specs_pg, how = tune.batch_specs(
+        grids, os.path.join(ROOT, "paper_2505_06022_amd", "costmodel.json"))
+    if specs_out:
+        with open(specs_out, "w") as f:
+            json.dump({"persistent": specs, "per_grid": specs_pg, "how": how}, f)
+    for sp, flags in ((specs, ccl.CCL_BATCH_NO_GRAPH),
+                      (specs_pg, ccl.CCL_BATCH_NO_GRAPH | ccl.CCL_BATCH_PER_GRID)):
+        bw = BatchedWaves(sp, flags=flags)
+        for g, d in enumerate(grids):
+            u0 = synth.gaussian_field((d["ny"], d["nx"]), d["sigma"], d["seed"])
+            bw.scatter(g, u0, u0)
+        torch.cuda.synchronize()
+        bw.run()
+        torch.cuda.synchronize()
+        ccl.ccl_batch_check(bw.handle)
+        bw.close()
+        del bw
+        torch.cuda.empty_cache()
+    x = torch.rand(SAXPY_N, device="cuda")
+    y = torch.rand(SAXPY_N, device="cuda")
+    z = torch.empty(SAXPY_N, device="cuda")
+    ccl.ccl_saxpy(SAXPY_N, 2.0, x.data_ptr(), y.data_ptr(), z.data_ptr())
+    torch.cuda.synchronize()
+    print(f"profile_run: 64-grid batch, persistent and per-grid; saxpy n={SAXPY_N}", flush=True)
+
+
+def batch_algorithmic_bytes(specs):
+    """Algorithmic bytes of one pass over a batch: per grid and block of T
+    steps, 16 B per cell (two levels read, two written), 12 B for a grid
+    stepped one step at a time in place."""
+    total = 0
+    for s in specs:
+        T, steps = int(s["depth"]), int(s["steps"])
+        blocks = -(-steps // T)
+        total += int(s["ny"]) * int(s["nx"]) * blocks * (12 if T == 1 else 16)
+    return total
+
+
+def summarise_batch(fetch_csv, write_csv, specs_json, md_path):
+    """HBM bytes of the two batch modes against their algorithmic bytes,
+    from counter runs of `run --batch` and the specs it wrote: the
+    persistent kernel is one dispatch, the per-grid mode every stencil and
+    halo dispatch after it."""
+    with open(specs_json) as f:
+        sj = json.load(f)
+    specs, how = sj["persistent"], sj["how"]
+    sums = {}
+    for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+        tot = {"persistent": 0.0, "per_grid": 0.0, "saxpy": 0.0, "launches_per_grid": 0}
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name", counter) != counter:
+                    continue
+                name, val = row.get("Kernel_Name", ""), float(row.get("Counter_Value", "nan"))
+                if "batch_kernel" in name:
+                    tot["persistent"] += val
+                elif "wave2d_kernel" in name or "copy_boxes_kernel" in name:
+                    tot["per_grid"] += val
+                    tot["launches_per_grid"] += 1
+                elif "saxpy_kernel" in name:
+                    tot["saxpy"] = val
+        sums[counter] = tot
+    f_scale = 8.0 * SAXPY_N / 1024.0 / sums["FETCH_SIZE"]["saxpy"]
+    w_scale = 4.0 * SAXPY_N / 1024.0 / sums["WRITE_SIZE"]["saxpy"]
+    alg = batch_algorithmic_bytes(specs)
+    doc = {"workload": "64-grid batch", "configs": how, "fetch_scale": f_scale,
+           "write_scale": w_scale, "algorithmic_bytes": alg,
+           "launches_per_grid_mode": sums["FETCH_SIZE"]["launches_per_grid"]}
+    for mode in ("persistent", "per_grid"):
+        fb = sums["FETCH_SIZE"][mode] * f_scale * 1024.0
+        wb = sums["WRITE_SIZE"][mode] * w_scale * 1024.0
+        doc[mode] = {"fetch_bytes": fb, "write_bytes": wb, "ratio": (fb + wb) / alg}
+    lines = [
+        "# HBM traffic of the 64-grid batch: persistent kernel against per-grid launches",
+        "",
+        "Counters from two rocprofv3 runs, one per counter; the batch (per-grid depth "
+        f"from the {how}) runs once in each mode, launched directly; FETCH_SIZE and "
+        f"WRITE_SIZE are scaled by what they read for a SAXPY of {SAXPY_N} floats in the "
+        "same program:",
+        "",
+        "```",
+        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/fetch -o p -- python3 -m "
+        "paper_2505_06022_amd.profile_run run --batch --specs-out OUT/specs.json",
+        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/write -o p -- python3 -m "
+        "paper_2505_06022_amd.profile_run run --batch",
+        "python3 -m paper_2505_06022_amd.profile_run summarise-batch --fetch "
+        "OUT/fetch/p_counter_collection.csv --write OUT/write/p_counter_collection.csv "
+        f"--specs OUT/specs.json --md {os.path.relpath(md_path, ROOT)}",
+        "```",
+        "",
+        f"Algorithmic bytes of one pass (16 B per cell per block of T steps): {alg:,}.",
+        "",
+        "| mode | fetched (GB) | written (GB) | traffic / algorithmic |",
+        "|---|---|---|---|",
+    ]
+    for mode, label in (("persistent", "persistent kernel (one dispatch)"),
+                        ("per_grid", f"per grid ({doc['launches_per_grid_mode']} stencil and "
+                                     "halo dispatches)")):
+        m = doc[mode]
+        lines.append(f"| {label} | {m['fetch_bytes'] / 1e9:.2f} | {m['write_bytes'] / 1e9:.2f} | "
+                     f"{m['ratio']:.3f} |")
+    lines += ["", "batch-traffic-json: " + json.dumps(doc), ""]
+    with open(md_path, "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def _per_kernel(path, counter):
     """{kernel-name-prefix: [values per dispatch]} from a rocprofv3 counter CSV."""
     out = {}
@@ -274,8 +395,10 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     r = sub.add_parser("run")
-    r.add_argument("--depth", type=int, required=True)
-    r.add_argument("--rows", type=int, required=True)
+    r.add_argument("--depth", type=int)
+    r.add_argument("--rows", type=int)
+    r.add_argument("--batch", action="store_true", help="the 64-grid batch in both modes")
+    r.add_argument("--specs-out", help="with --batch: where to write the launch specs")
     r.add_argument("--blocks", type=int, default=6)
     r.add_argument("--dims", type=int, default=2)
     s = sub.add_parser("summarise")
@@ -287,6 +410,11 @@ def main(argv=None):
     s.add_argument("--dims", type=int, default=2)
     s.add_argument("--append", action="store_true",
                    help="add a section for this configuration to an existing summary")
+    sb = sub.add_parser("summarise-batch")
+    sb.add_argument("--fetch", required=True)
+    sb.add_argument("--write", required=True)
+    sb.add_argument("--specs", required=True)
+    sb.add_argument("--md", required=True)
     t = sub.add_parser("trace-summary")
     t.add_argument("--db", required=True)
     t.add_argument("--md", required=True)
@@ -312,8 +440,16 @@ def main(argv=None):
     if a.cmd == "trace-summary":
         trace_summary(a.db, a.md, a.title, a.command, a.append)
         return 0
+    if a.cmd == "summarise-batch":
+        summarise_batch(a.fetch, a.write, a.specs, a.md)
+        return 0
     if a.cmd == "run":
-        run(a.depth, a.rows, a.blocks, a.dims)
+        if a.batch:
+            run_batch(a.specs_out)
+        elif a.depth is None or a.rows is None:
+            ap.error("run needs --depth and --rows, or --batch")
+        else:
+            run(a.depth, a.rows, a.blocks, a.dims)
     else:
         summarise(a.fetch, a.write, a.depth, a.rows, a.md, a.dims, a.append)
     return 0

@@ -167,6 +167,48 @@ def test_counter_summary_derived_values(tmp_path):
     assert doc["counters"]["SQ_WAVES"] == 1000
 
 
+def test_batch_traffic_summary(tmp_path):
+    """The batch summary sums the persistent kernel's dispatch and the
+    per-grid mode's stencil and halo dispatches separately, scales them by
+    the SAXPY's factors and divides by the batch's algorithmic bytes (16 B
+    per cell per block of T steps, 12 B per in-place step)."""
+    import csv
+    import json
+    from paper_2505_06022_amd import profile_run as pr
+    specs = [dict(ny=10, nx=20, steps=9, depth=4), dict(ny=8, nx=8, steps=5, depth=1)]
+    alg = 10 * 20 * 3 * 16 + 8 * 8 * 5 * 12
+    assert pr.batch_algorithmic_bytes(specs) == alg
+    sj = tmp_path / "specs.json"
+    sj.write_text(json.dumps({"persistent": specs, "per_grid": specs, "how": "test"}))
+
+    def fake(path, counter, persistent_kib, per_grid_kib):
+        with open(path, "w", newline="") as f:
+            w = csv.DictWriter(f, ["Kernel_Name", "Counter_Name", "Counter_Value"])
+            w.writeheader()
+            w.writerow(dict(Kernel_Name="ccl::batch_kernel<8>", Counter_Name=counter,
+                            Counter_Value=persistent_kib))
+            for v in per_grid_kib:
+                w.writerow(dict(Kernel_Name="ccl::wave2d_kernel<P32, 4, false>",
+                                Counter_Name=counter, Counter_Value=v))
+            w.writerow(dict(Kernel_Name="copy_boxes_kernel", Counter_Name=counter,
+                            Counter_Value=0.5))
+            # the SAXPY counted at 4 B per element for both counters
+            w.writerow(dict(Kernel_Name="saxpy_kernel", Counter_Name=counter,
+                            Counter_Value=4.0 * pr.SAXPY_N / 1024.0))
+
+    fc, wc = tmp_path / "f.csv", tmp_path / "w.csv"
+    fake(fc, "FETCH_SIZE", 10.0, [1.0, 2.0])
+    fake(wc, "WRITE_SIZE", 6.0, [1.5, 0.5])
+    md = tmp_path / "b.md"
+    pr.summarise_batch(str(fc), str(wc), str(sj), str(md))
+    doc = json.loads(md.read_text().split("batch-traffic-json: ")[1].splitlines()[0])
+    assert doc["launches_per_grid_mode"] == 3
+    assert abs(doc["persistent"]["fetch_bytes"] - 2 * 10.0 * 1024) < 1e-6
+    assert abs(doc["persistent"]["write_bytes"] - 6.0 * 1024) < 1e-6
+    assert abs(doc["per_grid"]["fetch_bytes"] - 2 * 3.5 * 1024) < 1e-6
+    assert abs(doc["per_grid"]["ratio"] - (2 * 3.5 + 2.5) * 1024 / alg) < 1e-9
+
+
 def test_held_out_3d_shapes_are_not_trained_on():
     from paper_2505_06022_amd import learn
     trained, _ = tune.sample_space(250, learn.TRAIN_SHAPE_SEED, 1, 0, 40, 40)
