@@ -337,6 +337,30 @@ ccl_status ccl_parallel_for(const ccl_kernel_fn *fn, int32_t nchunks, const ccl_
 ccl_status ccl_saxpy(int64_t n, float a, const float *x, const float *y,
                      float *z, void *hip_stream);
 
+/* Discrete energy of the leapfrog scheme, computed on the device:
+ *   E^{n+1/2} = sum_i (a_i - b_i)^2 + r2 * sum_{edges (p,q)} (a_p - a_q)(b_p - b_q)
+ * with a = u^{n+1}, b = u^n, over every edge of the dims-D grid, the edges
+ * to the zero cells just outside the domain included.  In exact arithmetic
+ * the update conserves it (take the update's inner product with
+ * u^{n+1} - u^{n-1}; the discrete Laplacian is symmetric), and it is
+ * positive under the step-size condition r2 < 1/dims, so it monitors a
+ * run's stability and rounding drift.  The scheme is the chunk kernel that
+ * stands in for the paper's data-parallel kernels (section 3); this is an
+ * optional monitor, not a step of the path.
+ * u_new, u_old: device pointers to the whole domain in one buffer each,
+ * shape[0..dims-1] elements (slowest first) of type dtype (CCL_DTYPE_*),
+ * element strides pitch[0..dims-2] of the outer dimensions (rows: pitch of
+ * the last-but-one dimension >= the row length; 3D planes >= rows x pitch).
+ * energy_out: device pointer to one double, written in stream order.  The
+ * terms are formed in double from the exactly widened elements and summed
+ * in a fixed order (deterministic for a given shape; the summation order is
+ * not the oracle's, so the two agree to rounding in double).  The call
+ * allocates and frees a small workspace in stream order.
+ * Errors: INVALID (NULL, dims, dtype, shape < 1, pitches), HIP. */
+ccl_status ccl_wave_energy(int32_t dims, const int64_t *shape, const int64_t *pitch,
+                           int32_t dtype, double r2, const void *u_new, const void *u_old,
+                           double *energy_out, void *hip_stream);
+
 /* ---- Batched grids ------------------------------------------------------
  * Many independent 2D grids (each its own domain, Dirichlet zero outside)
  * advanced by one persistent kernel launch, captured once in a HIP graph so

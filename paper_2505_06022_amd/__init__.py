@@ -153,6 +153,9 @@ _SIGS = {
                                           ctypes.c_int32, _P(ccl_accessor), ctypes.c_void_p]),
     "ccl_saxpy": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_float, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "ccl_wave_energy": (ctypes.c_int32, [ctypes.c_int32, _P(ctypes.c_int64), _P(ctypes.c_int64),
+                                         ctypes.c_int32, ctypes.c_double, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "ccl_batch_create": (ctypes.c_int32, [ctypes.c_int32, _P(ccl_batch_grid), ctypes.c_int32,
                                           _P(ctypes.c_void_p)]),
     "ccl_batch_run": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -388,6 +391,20 @@ def ccl_saxpy(n: int, a: float, x_ptr: int, y_ptr: int, z_ptr: int, stream=None)
     _check("ccl_saxpy", lib().ccl_saxpy(int(n), float(a), ctypes.c_void_p(x_ptr),
                                         ctypes.c_void_p(y_ptr), ctypes.c_void_p(z_ptr),
                                         _stream(stream)))
+
+
+def ccl_wave_energy(shape, pitch, dtype: str, r2: float, u_new_ptr: int, u_old_ptr: int,
+                    out_ptr: int, stream=None):
+    """Discrete leapfrog energy of (u^{n+1}, u^n) held in one device buffer
+    each; written as one double to the device pointer `out_ptr`.  `pitch`:
+    element strides of the outer dimensions; `dtype`: "f32", "f64", "bf16"
+    or "f16"."""
+    dims = len(shape)
+    sh = (ctypes.c_int64 * 3)(*[int(v) for v in shape])
+    pt = (ctypes.c_int64 * 3)(*([int(v) for v in pitch] + [0] * (3 - len(pitch))))
+    _check("ccl_wave_energy", lib().ccl_wave_energy(
+        dims, sh, pt, DTYPES[dtype], float(r2), ctypes.c_void_p(u_new_ptr),
+        ctypes.c_void_p(u_old_ptr), ctypes.c_void_p(out_ptr), _stream(stream)))
 
 
 def ccl_timing_enable(on: bool = True):

@@ -12,7 +12,7 @@ import numpy as np
 
 from . import (NEIGHBORHOOD, ccl_batch_create, ccl_batch_destroy, ccl_batch_grid,
                ccl_batch_result, ccl_batch_run, ccl_chunk_buffer, ccl_region_of, ccl_split_grid,
-               ccl_split_range, ccl_wave_step, make_subrange, make_wave_params)
+               ccl_split_range, ccl_wave_energy, ccl_wave_step, make_subrange, make_wave_params)
 
 PITCH_ALIGN = 64  # elements; keeps every row start 256-byte aligned
 
@@ -93,6 +93,8 @@ class ChunkedWave:
         self.u_prev, self.u_cur, self.w_prev, self.w_cur = arrays
         if nbuf == 2:
             self.w_prev = self.w_cur = None
+        self.r2 = float(r2)
+        self.n = 0  # leapfrog steps taken since the state was set
 
     def chunk_box(self, k):
         return self.chunks[k].box()
@@ -127,6 +129,29 @@ class ChunkedWave:
             out[self._local(box)] = v.cpu().numpy()
         return out
 
+    def gather_device(self, which="cur"):
+        """The domain's cells of u^n ("cur") or u^{n-1} ("prev") copied into
+        one contiguous device tensor of the element type."""
+        import torch
+        arr = self.u_cur if which == "cur" else self.u_prev
+        first = self.tensors[arr[0].base][0]
+        out = torch.empty(self.domain_shape, dtype=first.dtype, device=first.device)
+        for k in range(self.nchunks):
+            box = self.chunk_box(k)
+            t, reg = self.tensors[arr[k].base]
+            out[self._local(box)].copy_(view_of(t, reg, box))
+        return out
+
+    def energy(self, stream=None):
+        """Discrete energy E^{n-1/2} of the state (u^{n-1}, u^n), computed on
+        the device by ccl_wave_energy (u^n as the newer level)."""
+        import torch
+        a, b = self.gather_device("cur"), self.gather_device("prev")
+        out = torch.zeros(1, dtype=torch.float64, device=a.device)
+        ccl_wave_energy(self.domain_shape, [a.stride(d) for d in range(self.dims - 1)],
+                        self.dtype, self.r2, a.data_ptr(), b.data_ptr(), out.data_ptr(), stream)
+        return float(out.item())
+
     def gather_points(self, points, which="cur"):
         """Values at global indices `points` (list of tuples) of u_cur / u_prev."""
         arr = self.u_cur if which == "cur" else self.u_prev
@@ -146,6 +171,37 @@ class ChunkedWave:
     def step(self, nsteps: int, stream=None):
         ccl_wave_step(self.params, self.chunks, self.u_prev, self.u_cur, self.w_prev, self.w_cur,
                       nsteps, stream)
+        self.n += int(nsteps)
+
+    # Checkpoint / resume.  The leapfrog's whole state is its last two levels
+    # (u^{n-1}, u^n) and the step count n: a run resumed from a checkpoint
+    # continues exactly as the uninterrupted run (the halos are refilled by
+    # the exchange before the next block).  With 16-bit storage the fields
+    # are rounded at the end of every block of T steps, so a resumed run
+    # matches the uninterrupted one when the checkpoint falls on a block
+    # boundary of it.
+    def save(self, path):
+        """Writes the state to `path` (.npz): both levels of the domain as
+        gathered (exact: 16-bit values widen exactly to float32), n, r2, the
+        element type and the domain."""
+        np.savez(path, u_prev=self.gather("prev"), u_cur=self.gather("cur"),
+                 n=np.int64(self.n), r2=np.float64(self.r2), dtype=np.str_(self.dtype),
+                 domain_offset=np.array(self.domain_offset, np.int64),
+                 domain_shape=np.array(self.domain_shape, np.int64))
+
+    def restore(self, path):
+        """Sets the state from a checkpoint written by `save` for the same
+        domain, element type and r2 (any chunking, depth or tile rows);
+        returns n."""
+        with np.load(path, allow_pickle=False) as f:
+            if (tuple(f["domain_offset"].tolist()) != self.domain_offset or
+                    tuple(f["domain_shape"].tolist()) != self.domain_shape):
+                raise ValueError("checkpoint of another domain")
+            if str(f["dtype"]) != self.dtype or float(f["r2"]) != self.r2:
+                raise ValueError("checkpoint of another element type or r2")
+            self.scatter(f["u_prev"], f["u_cur"])
+            self.n = int(f["n"])
+        return self.n
 
 
 class BatchedWaves:

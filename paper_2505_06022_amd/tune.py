@@ -164,9 +164,15 @@ class CostModel:
         return self.ys.invert(yd.cpu().numpy().astype(np.float64))
 
     # A predicted energy (or EDP) saving over the time pick smaller than
-    # this (log units) is not acted on: the power head's error on held-out
-    # labels is about 1%, so smaller predicted savings are noise.
-    MIN_SAVING = 0.02
+    # this (log units) is not acted on.  A predicted energy is predicted
+    # time times predicted power, and the time head's error on its training
+    # samples is about 4.6% (rmse of log t; the power head's about 1%), so
+    # smaller predicted savings are within the model's own error.  The rule
+    # does not make the raw energy pick reliable: on 24 held-out shapes the
+    # pick differed from the time pick on 14 (predicted savings above 5% on
+    # all of them) and measured more energy on 11; the launcher's energy
+    # choice is therefore measured (pick_verified).
+    MIN_SAVING = 0.05
 
     def pick(self, shape, objective="time", nchunks=None, shortlist=8):
         """Best candidate of `shape` by the model (only those with `nchunks`
@@ -213,15 +219,39 @@ class CostModel:
         score = w[0] * y[:, 0] + w[1] * y[:, 1]
         return [idx[j] for j in np.argsort(score, kind="stable")]
 
-    def pick_verified(self, shape, objective="time", k=3, r2=0.25, nchunks=None):
+    def pick_verified(self, shape, objective="time", k=3, r2=0.25, nchunks=None, repeats=3):
         """The model's k best candidates measured by the autotuner; returns
-        the fastest (or least-energy) of them and its measurement."""
+        the fastest (or least-energy) of them and its measurement.  For
+        energy and EDP the model's time pick is measured with them, each
+        config as the median of `repeats` counter windows (a single window
+        now and then reads far low): the model's energy ranking is not
+        reliable enough on its own (on 24 held-out shapes its three best by
+        predicted energy measured 1.07 x the least energy, its time pick
+        1.06 x, the least of the two sets 1.04 x), so the choice is never
+        the model's word against a measured time pick."""
         cfgs = candidates(shape)
-        top = [cfgs[i] for i in self.rank(shape, objective, nchunks)[:k]]
-        res = measure(top, r2, energy_window_s=1.0 if objective != "time" else 0.0)
-        key = "s_per_step" if objective == "time" else "j_per_step"
-        j = int(np.argmin([r[key] if objective != "edp" else r["s_per_step"] * r["j_per_step"]
-                           for r in res]))
+        order = self.rank(shape, objective, nchunks)[:k]
+        if objective == "time":
+            top = [cfgs[i] for i in order]
+            res = measure(top, r2)
+            j = int(np.argmin([r["s_per_step"] for r in res]))
+            return top[j], res[j]
+        tcfg, _ = self.pick(shape, "time", nchunks)
+        keys = [cfg_key(cfgs[i]) for i in order]
+        top = [cfgs[i] for i in order] + ([tcfg] if cfg_key(tcfg) not in keys else [])
+        runs = [measure(top, r2, energy_window_s=1.0) for _ in range(max(1, repeats))]
+        res = []
+        for j in range(len(top)):
+            rr = [run[j] for run in runs if run[j]["j_per_step"] is not None and
+                  np.isfinite(run[j]["j_per_step"]) and run[j]["j_per_step"] > 0]
+            if not rr:
+                res.append(dict(runs[0][j], j_per_step=float("inf")))
+                continue
+            rr.sort(key=lambda r: r["j_per_step"])
+            res.append(rr[len(rr) // 2])  # the median window
+        score = [r["j_per_step"] if objective == "energy" else r["s_per_step"] * r["j_per_step"]
+                 for r in res]
+        j = int(np.argmin(score))
         return top[j], res[j]
 
     def to_json(self):

@@ -424,3 +424,28 @@ def test_parallel_for_validation_no_launch():
     regs = [ccl.ccl_region_of(c, sl, None, shape).box() for c in chunks]
     xs = ccl.make_accessor(sl, R, shape, fb(regs, 0x10000000))
     assert call(ccl.CCL_FN_SUM_ALONG, [xs, out], dim=1) == ccl.CCL_E_RANGE  # slice(0) for dim 1
+
+
+def test_wave_energy_validates_before_launch():
+    """ccl_wave_energy refuses malformed arguments before touching a device
+    (no GPU needed): NULL pointers, dims, dtype, empty extents, pitches
+    smaller than the rows or planes they hold."""
+    L = ccl.lib()
+    I64 = ctypes.c_int64 * 3
+    dev = ctypes.c_void_p(0x10000)  # never dereferenced: every call below is refused
+    shape, pitch = I64(4, 8, 8), I64(64, 8, 0)
+    assert L.ccl_wave_energy(3, shape, pitch, ccl.CCL_DTYPE_F32, 0.1, None, dev, dev,
+                             None) == ccl.CCL_E_INVALID
+    assert L.ccl_wave_energy(3, shape, pitch, ccl.CCL_DTYPE_F32, 0.1, dev, dev, None,
+                             None) == ccl.CCL_E_INVALID
+    assert L.ccl_wave_energy(4, shape, pitch, ccl.CCL_DTYPE_F32, 0.1, dev, dev, dev,
+                             None) == ccl.CCL_E_INVALID
+    assert L.ccl_wave_energy(3, shape, pitch, 9, 0.1, dev, dev, dev, None) == ccl.CCL_E_INVALID
+    assert L.ccl_wave_energy(3, I64(4, 0, 8), pitch, ccl.CCL_DTYPE_F32, 0.1, dev, dev, dev,
+                             None) == ccl.CCL_E_INVALID
+    assert L.ccl_wave_energy(3, shape, I64(64, 7, 0), ccl.CCL_DTYPE_F32, 0.1, dev, dev, dev,
+                             None) == ccl.CCL_E_INVALID
+    assert L.ccl_wave_energy(3, shape, I64(63, 8, 0), ccl.CCL_DTYPE_F32, 0.1, dev, dev, dev,
+                             None) == ccl.CCL_E_INVALID
+    assert L.ccl_wave_energy(2, I64(8, 8, 0), I64(7, 0, 0), ccl.CCL_DTYPE_F64, 0.1, dev, dev,
+                             dev, None) == ccl.CCL_E_INVALID
