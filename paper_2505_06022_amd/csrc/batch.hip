@@ -92,16 +92,21 @@ __device__ __forceinline__ int upper_index(const int32_t *a, int lo, int n, int3
   return lo;
 }
 
-__device__ __forceinline__ int32_t load_acquire(const int32_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Counter and flag reads while waiting are relaxed device-scope loads
+// (they read the coherent value without cache maintenance); the single
+// acquire fence after the last wait makes the neighbours' data visible.  An
+// acquire load per poll would invalidate the XCD's L2 on every iteration
+// of every waiting wave, evicting the rows the other waves stream.
+__device__ __forceinline__ int32_t load_relaxed(const int32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Waits until counters[idx] >= want.  Returns false if the batch's error
 // flag is (or gets) raised, or the wait limit passes (then raises it).
 __device__ bool wait_for(const BatchTables &t, int idx, int32_t want, uint64_t t0,
                          int64_t limit) {
-  while (load_acquire(&t.counters[idx]) < want) {
-    if (load_acquire(&t.ctl[1]) != 0) return false;
+  while (load_relaxed(&t.counters[idx]) < want) {
+    if (load_relaxed(&t.ctl[1]) != 0) return false;
     if (static_cast<int64_t>(wall_clock64() - t0) > limit) {
       __hip_atomic_store(&t.ctl[1], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       return false;
@@ -145,7 +150,7 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(const BatchTables t) {
     const int seg = tl / G.nstrips;
     const int strip = tl - seg * G.nstrips;
 
-    bool ok = load_acquire(&t.ctl[1]) == 0;
+    bool ok = load_relaxed(&t.ctl[1]) == 0;
     if (ok && b > 0) {
       const uint64_t t0 = wall_clock64();
       for (int ds = -1; ds <= 1 && ok; ++ds) {
@@ -159,6 +164,8 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(const BatchTables t) {
       }
     }
     if (!ok) continue;  // error raised: drain the queue without computing
+    // the neighbours' block b-1 (written on any XCD) is visible from here
+    if (b > 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 
     const int set = b & 1;
     w2::Chunk C;
@@ -180,11 +187,11 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(const BatchTables t) {
     const w2::Domain D{0, G.ny, 0, G.nx};
     const int tb = (b == G.nblocks - 1) ? G.last_T : G.T;
     dispatch_depth<TMAX>(tb, C, D, G.r2, G.tile_rows, seg, strip, lane, G.A);
-    // publish: every lane's stores complete and visible device-wide, then
-    // the counter moves to b+1
-    __threadfence();
+    // publish: one release fence (every lane's stores complete and written
+    // back device-wide), then the counter moves to b+1
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (lane == 0)
-      __hip_atomic_store(&t.counters[G.counter_base + tl], b + 1, __ATOMIC_RELEASE,
+      __hip_atomic_store(&t.counters[G.counter_base + tl], b + 1, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
   }
 }
