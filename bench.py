@@ -316,10 +316,10 @@ def wave3d_forms(with_energy=False):
     w = synth.WORKLOADS["wave3d_768_k8"]
     shape = w["shape"]
     # every candidate is timed over the workload's own step count, so a
-    # depth that does not divide it pays for its shorter last block
-    cands = [c for c in tune.candidates(shape) if c.nchunks == w["chunks"]]
-    res = tune.measure(cands, w["r2"], reps=3, steps=w["steps"])
-    swept = cands[int(np.argmin([r["s_per_step"] for r in res]))]
+    # depth that does not divide it pays for its shorter last block (the
+    # library's sweep, ccl_autotune_sweep)
+    cands, res, best = tune.sweep(shape, w["chunks"], w["r2"], steps=w["steps"], reps=3)
+    swept = cands[best]
     learned = verified = None
     if os.path.exists(MODEL_PATH):
         m = tune.CostModel.load(MODEL_PATH)

@@ -467,6 +467,35 @@ ccl_status ccl_autotune_measure(int32_t n, const ccl_tune_config *cfgs, float r2
                                 int32_t steps, int32_t reps, double energy_window_s,
                                 int32_t device, void *hip_stream, ccl_tune_sample *out);
 
+/* The autotuner's candidate set for a shape (dims 2 or 3, extents shape[0..
+ * dims-1]): K device-local chunks in {1, 2, 4, 8, 16} (at most shape[0]),
+ * tile rows / planes in {0 = automatic, 16, 32, 64, 128} and T in 1..8, in
+ * that nesting order (K slowest); only K == nchunks when nchunks > 0.
+ * Writes min(count, max_out) configs to out (host) and the count to *n_out.
+ * Host only.  Errors: INVALID, RANGE (count > max_out; *n_out still set). */
+ccl_status ccl_autotune_candidates(int32_t dims, const int64_t *shape, int32_t nchunks,
+                                   int32_t max_out, ccl_tune_config *out, int32_t *n_out);
+
+/* Objectives of a sweep: time per step, energy per step, their product. */
+#define CCL_OBJECTIVE_TIME 0
+#define CCL_OBJECTIVE_ENERGY 1
+#define CCL_OBJECTIVE_EDP 2
+
+/* The exhaustive sweep of the paper's per-kernel tuning (section 4: picking
+ * a launch configuration per kernel by a target metric): every candidate of
+ * ccl_autotune_candidates measured by ccl_autotune_measure (with the same
+ * r2, steps, reps, energy window, device and stream), the configs and
+ * samples written to cfgs_out / out (host, room for max_out), their count
+ * to *n_out, and to *best the index of the smallest measured objective
+ * (CCL_OBJECTIVE_*; ties: the lowest index).  Energy objectives need
+ * energy_window_s > 0.  Synchronises the stream.
+ * Errors: INVALID, RANGE, UNSUPPORTED (no energy read), HIP. */
+ccl_status ccl_autotune_sweep(int32_t dims, const int64_t *shape, int32_t nchunks, float r2,
+                              int32_t steps, int32_t reps, double energy_window_s,
+                              int32_t objective, int32_t device, void *hip_stream,
+                              int32_t max_out, ccl_tune_config *cfgs_out, ccl_tune_sample *out,
+                              int32_t *n_out, int32_t *best);
+
 /* Rows (2D) / planes (3D) per tile that ccl_wave_step uses for `c` when its
  * tile_rows is 0: the value minimising (resident-wave rounds) x (rows + 2
  * halo rows) for the device's occupancy of the depth-T kernel; tile_rows
@@ -538,6 +567,15 @@ ccl_status ccl_mlp_train(ccl_mlp *m, int32_t n, const float *x, const float *t,
  * `scores` (device, n floats) may be NULL. */
 ccl_status ccl_mlp_pick(ccl_mlp *m, int32_t n, const float *x, float w_time, float w_energy,
                         float *scores, int32_t *best, void *hip_stream);
+
+/* The k candidates with the smallest scores score_i = w_time*y_i0 +
+ * w_energy*y_i1 (the same scores as ccl_mlp_pick), in ascending order of
+ * score (ties: lower index first), as indices into x's n rows written to
+ * order (device int32, k entries); order[0] is ccl_mlp_pick's choice.
+ * 1 <= k <= n <= 4096 (one block holds every score in LDS).
+ * Errors: INVALID, RANGE, HIP. */
+ccl_status ccl_mlp_rank(ccl_mlp *m, int32_t n, const float *x, float w_time, float w_energy,
+                        int32_t k, int32_t *order, void *hip_stream);
 
 /* Kernel launch timing, for measurement.  While enabled, every launch of
  * the kernel families below is bracketed by HIP events recorded on the

@@ -193,6 +193,18 @@ _SIGS = {
     "ccl_mlp_pick": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                       ctypes.c_float, ctypes.c_float, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p]),
+    "ccl_mlp_rank": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.c_float, ctypes.c_float, ctypes.c_int32,
+                                      ctypes.c_void_p, ctypes.c_void_p]),
+    "ccl_autotune_candidates": (ctypes.c_int32, [ctypes.c_int32, _P(ctypes.c_int64),
+                                                 ctypes.c_int32, ctypes.c_int32,
+                                                 _P(ccl_tune_config), _P(ctypes.c_int32)]),
+    "ccl_autotune_sweep": (ctypes.c_int32, [ctypes.c_int32, _P(ctypes.c_int64), ctypes.c_int32,
+                                            ctypes.c_float, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_void_p, ctypes.c_int32, _P(ccl_tune_config),
+                                            _P(ccl_tune_sample), _P(ctypes.c_int32),
+                                            _P(ctypes.c_int32)]),
     "ccl_timing_enable": (ctypes.c_int32, [ctypes.c_int32]),
     "ccl_timing_query": (ctypes.c_int32, [ctypes.c_int32, _P(ctypes.c_int64),
                                           _P(ctypes.c_double)]),
@@ -489,6 +501,44 @@ def ccl_autotune_measure(cfgs, r2: float, steps: int, reps: int = 3,
     return list(out)
 
 
+CCL_OBJECTIVE_TIME, CCL_OBJECTIVE_ENERGY, CCL_OBJECTIVE_EDP = 0, 1, 2
+OBJECTIVE_CODES = {"time": CCL_OBJECTIVE_TIME, "energy": CCL_OBJECTIVE_ENERGY,
+                   "edp": CCL_OBJECTIVE_EDP}
+
+
+def ccl_autotune_candidates(shape, nchunks: int = 0):
+    """The library's candidate configs for a domain shape (K, tile rows, T;
+    only K == nchunks when nchunks > 0)."""
+    dims = len(shape)
+    sh = (ctypes.c_int64 * 3)(*([int(v) for v in shape] + [0] * (3 - dims)))
+    n = ctypes.c_int32(0)
+    st = lib().ccl_autotune_candidates(dims, sh, int(nchunks), 0, None, ctypes.byref(n))
+    if st not in (CCL_OK, CCL_E_RANGE):
+        _check("ccl_autotune_candidates", st)
+    out = (ccl_tune_config * max(1, n.value))()
+    _check("ccl_autotune_candidates", lib().ccl_autotune_candidates(
+        dims, sh, int(nchunks), n.value, out, ctypes.byref(n)))
+    return list(out)[:n.value]
+
+
+def ccl_autotune_sweep(shape, nchunks: int, r2: float, steps: int, reps: int = 3,
+                       energy_window_s: float = 0.0, objective: str = "time", device: int = 0,
+                       stream=None):
+    """Every candidate of the shape (K == nchunks when nchunks > 0) measured;
+    returns (configs, samples, index of the best by `objective`)."""
+    dims = len(shape)
+    sh = (ctypes.c_int64 * 3)(*([int(v) for v in shape] + [0] * (3 - dims)))
+    cap = len(ccl_autotune_candidates(shape, nchunks))
+    cfgs = (ccl_tune_config * max(1, cap))()
+    out = (ccl_tune_sample * max(1, cap))()
+    n, best = ctypes.c_int32(0), ctypes.c_int32(-1)
+    _check("ccl_autotune_sweep", lib().ccl_autotune_sweep(
+        dims, sh, int(nchunks), float(r2), int(steps), int(reps), float(energy_window_s),
+        OBJECTIVE_CODES[objective], int(device), _stream(stream), cap, cfgs, out,
+        ctypes.byref(n), ctypes.byref(best)))
+    return list(cfgs)[:n.value], list(out)[:n.value], best.value
+
+
 def ccl_wave_plan_rows(cfg) -> int:
     r = ctypes.c_int32(0)
     _check("ccl_wave_plan_rows", lib().ccl_wave_plan_rows(ctypes.byref(cfg), ctypes.byref(r)))
@@ -560,6 +610,13 @@ def ccl_mlp_train(h, n: int, x_ptr: int, t_ptr: int, epochs: int, lr: float = 1e
                                                 ctypes.c_void_p(t_ptr),
                                                 ctypes.c_void_p(w_ptr) if w_ptr else None,
                                                 int(epochs), float(lr), _stream(stream)))
+
+
+def ccl_mlp_rank(h, n: int, x_ptr: int, w_time: float, w_energy: float, k: int,
+                 order_ptr: int, stream=None):
+    _check("ccl_mlp_rank", lib().ccl_mlp_rank(h, int(n), ctypes.c_void_p(x_ptr), float(w_time),
+                                              float(w_energy), int(k),
+                                              ctypes.c_void_p(order_ptr), _stream(stream)))
 
 
 def ccl_mlp_pick(h, n: int, x_ptr: int, w_time: float, w_energy: float, scores_ptr: int,

@@ -192,6 +192,80 @@ extern "C" ccl_status ccl_autotune_measure(int32_t n, const ccl_tune_config *cfg
   return st;
 }
 
+// The library's candidate set for a shape: K in {1, 2, 4, 8, 16} (at most
+// the extent along dimension 0), tile rows / planes in {0 (automatic), 16,
+// 32, 64, 128}, T in 1..8, in that nesting order (K slowest).
+static const int32_t kCandK[] = {1, 2, 4, 8, 16};
+static const int32_t kCandRows[] = {0, 16, 32, 64, 128};
+
+extern "C" ccl_status ccl_autotune_candidates(int32_t dims, const int64_t *shape, int32_t nchunks,
+                                              int32_t max_out, ccl_tune_config *out,
+                                              int32_t *n_out) {
+  clear_error();
+  if ((dims != 2 && dims != 3) || !shape || !n_out || max_out < 0 || (max_out > 0 && !out))
+    return fail(CCL_E_INVALID, "bad arguments");
+  for (int d = 0; d < dims; ++d)
+    if (shape[d] < 1) return fail(CCL_E_INVALID, "empty extent");
+  int32_t n = 0;
+  for (int32_t K : kCandK) {
+    if (K > shape[0] || (nchunks > 0 && K != nchunks)) continue;
+    for (int32_t rows : kCandRows)
+      for (int32_t T = 1; T <= CCL_MAX_DEPTH; ++T) {
+        if (n < max_out) {
+          ccl_tune_config &c = out[n];
+          memset(&c, 0, sizeof(c));
+          c.dims = dims;
+          for (int d = 0; d < dims; ++d) c.shape[d] = shape[d];
+          c.nchunks = K;
+          c.temporal_depth = T;
+          c.tile_rows = rows;
+        }
+        ++n;
+      }
+  }
+  *n_out = n;
+  if (n > max_out) return fail(CCL_E_RANGE, "%d candidates, room for %d", n, max_out);
+  return CCL_OK;
+}
+
+extern "C" ccl_status ccl_autotune_sweep(int32_t dims, const int64_t *shape, int32_t nchunks,
+                                         float r2, int32_t steps, int32_t reps,
+                                         double energy_window_s, int32_t objective,
+                                         int32_t device, void *hip_stream, int32_t max_out,
+                                         ccl_tune_config *cfgs_out, ccl_tune_sample *out,
+                                         int32_t *n_out, int32_t *best) {
+  clear_error();
+  if (!best || !out) return fail(CCL_E_INVALID, "NULL argument");
+  if (objective < CCL_OBJECTIVE_TIME || objective > CCL_OBJECTIVE_EDP)
+    return fail(CCL_E_INVALID, "objective %d", objective);
+  if (objective != CCL_OBJECTIVE_TIME && !(energy_window_s > 0.0))
+    return fail(CCL_E_INVALID, "an energy objective needs energy_window_s > 0");
+  ccl_status st = ccl_autotune_candidates(dims, shape, nchunks, max_out, cfgs_out, n_out);
+  if (st != CCL_OK) return st;
+  const int32_t n = *n_out;
+  if (n == 0) return fail(CCL_E_RANGE, "no candidate has %d chunks", nchunks);
+  st = ccl_autotune_measure(n, cfgs_out, r2, steps, reps, energy_window_s, device, hip_stream,
+                            out);
+  if (st != CCL_OK) return st;
+  // the smallest measured objective; ties and unmeasured energies: the
+  // lower index is kept
+  int32_t b = -1;
+  double bv = std::numeric_limits<double>::infinity();
+  for (int32_t i = 0; i < n; ++i) {
+    const double t = out[i].seconds_per_step, j = out[i].joules_per_step;
+    const double v = objective == CCL_OBJECTIVE_TIME     ? t
+                     : objective == CCL_OBJECTIVE_ENERGY ? j
+                                                         : t * j;
+    if (std::isfinite(v) && v < bv) {
+      bv = v;
+      b = i;
+    }
+  }
+  if (b < 0) return fail(CCL_E_UNSUPPORTED, "no candidate was measured for this objective");
+  *best = b;
+  return CCL_OK;
+}
+
 extern "C" ccl_status ccl_wave_plan_rows(const ccl_tune_config *c, int32_t *rows) {
   clear_error();
   if (!c || !rows) return fail(CCL_E_INVALID, "NULL argument");

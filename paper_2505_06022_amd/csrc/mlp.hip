@@ -221,6 +221,63 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const float *__restric
   y[static_cast<int64_t>(i) * kOut + 1] = out[1];
 }
 
+constexpr int kMaxRank = 4096;
+
+// One block: the score of every candidate (as mlp_pick_kernel computes it)
+// kept in LDS, then k rounds of a block argmin (ties: the lowest index),
+// each removing its winner: the k best in ascending order.  k <= n, so every
+// round finds a candidate (scores of +inf included).
+__global__ __launch_bounds__(256) void mlp_rank_kernel(const float *__restrict__ params,
+                                                       const float *__restrict__ x, int n,
+                                                       float w0, float w1, int k,
+                                                       int32_t *__restrict__ order) {
+  __shared__ float P[kParams];
+  __shared__ float sc[kMaxRank];
+  __shared__ float bs[256];
+  __shared__ int bi[256];
+  load_params(P, params);
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    float xs[kIn];
+    for (int q = 0; q < kIn; ++q) xs[q] = x[static_cast<int64_t>(i) * kIn + q];
+    float out[kOut];
+    forward_one(P, xs, out);
+    const float s = fmaf(w1, out[1], w0 * out[0]);
+    sc[i] = s == s ? s : INFINITY;  // a NaN score ranks with +inf (lowest index first)
+  }
+  __syncthreads();
+  for (int r = 0; r < k; ++r) {
+    float my_s = INFINITY;
+    int my_i = INT32_MAX;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const float s = sc[i];
+      if (s < my_s || (s == my_s && i < my_i)) {
+        my_s = s;
+        my_i = i;
+      }
+    }
+    bs[threadIdx.x] = my_s;
+    bi[threadIdx.x] = my_i;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) {
+        const float os = bs[threadIdx.x + w];
+        const int oi = bi[threadIdx.x + w];
+        if (os < bs[threadIdx.x] || (os == bs[threadIdx.x] && oi < bi[threadIdx.x])) {
+          bs[threadIdx.x] = os;
+          bi[threadIdx.x] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      order[r] = bi[0];
+      sc[bi[0]] = NAN;  // removed: no comparison selects a NaN
+    }
+    __syncthreads();
+  }
+}
+
 // One block: score_i = w0*y_i0 + w1*y_i1 for every candidate, then the index
 // of the smallest score (ties: the lowest index).
 __global__ __launch_bounds__(256) void mlp_pick_kernel(const float *__restrict__ params,
@@ -400,6 +457,17 @@ extern "C" ccl_status ccl_mlp_train(ccl_mlp *M, int32_t n, const float *x, const
     if (st != CCL_OK) return st;
   }
   return CCL_OK;
+}
+
+extern "C" ccl_status ccl_mlp_rank(ccl_mlp *M, int32_t n, const float *x, float w_time,
+                                   float w_energy, int32_t k, int32_t *order,
+                                   void *hip_stream) {
+  clear_error();
+  if (!M || n < 1 || !x || !order || k < 1 || k > n) return fail(CCL_E_INVALID, "bad argument");
+  if (n > kMaxRank) return fail(CCL_E_RANGE, "n=%d above %d", n, kMaxRank);
+  hipLaunchKernelGGL(mlp_rank_kernel, dim3(1), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
+                     M->params, x, n, w_time, w_energy, k, order);
+  return hip_check(hipGetLastError(), "mlp_rank_kernel launch");
 }
 
 extern "C" ccl_status ccl_mlp_pick(ccl_mlp *M, int32_t n, const float *x, float w_time,

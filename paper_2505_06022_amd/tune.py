@@ -1,8 +1,9 @@
 """Autotuner and learned cost model for ccl_wave_step launch configs.
 
-* ``candidates(shape)`` — the discrete config space of one shape: chunk
-  counts K in {1, 2, 4, 8, 16} (K <= rows), rows per tile in
-  {auto, 16, 32, 64, 128}, temporal depth T in 1..8 (2D and 3D).
+* ``candidates(shape)`` — the discrete config space of one shape, as the
+  library enumerates it (ccl_autotune_candidates): chunk counts K in
+  {1, 2, 4, 8, 16} (K <= rows), rows per tile in {auto, 16, 32, 64, 128},
+  temporal depth T in 1..8 (2D and 3D).
 * ``measure(cfgs)`` — time (and device energy) per step of each config,
   measured by the library's autotuner on the GPU (ccl_autotune_measure).
 * ``CostModel`` — the 12-64-64-2 MLP, trained on the GPU by the library's
@@ -10,8 +11,9 @@
   standardised targets [log s/cell-step, log W (device power)]; ``pick`` scores
   every candidate of a shape on the GPU (ccl_mlp_pick) and returns the best
   by time, energy or energy-delay product.
-* ``sweep`` — the exhaustive measurement of every candidate: the fallback
-  when no model is available and the judge of a model's picks.
+* ``sweep`` — the exhaustive measurement of every candidate
+  (ccl_autotune_sweep): the fallback when no model is available and the
+  judge of a model's picks.
 
 The sample and held-out shape sets are drawn from ``synth`` (seeded).
 """
@@ -25,13 +27,10 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import (CCL_MLP_NPARAMS, CCL_MLP_PARAMS, CCL_MLP_LOSS, ccl_autotune_measure,
-               ccl_costmodel_features, ccl_mlp_create, ccl_mlp_destroy, ccl_mlp_get,
-               ccl_mlp_pick, ccl_mlp_train, make_tune_config)
-
-K_SET = (1, 2, 4, 8, 16)
-ROWS_SET = (0, 16, 32, 64, 128)  # 0: the library's occupancy-aware choice
-T_SET = tuple(range(1, 9))
+from . import (CCL_MLP_NPARAMS, CCL_MLP_PARAMS, CCL_MLP_LOSS, ccl_autotune_candidates,
+               ccl_autotune_measure, ccl_autotune_sweep, ccl_costmodel_features,
+               ccl_mlp_create, ccl_mlp_destroy, ccl_mlp_get, ccl_mlp_pick, ccl_mlp_rank,
+               ccl_mlp_train, make_tune_config)
 
 # weights on the model's outputs [log s/cell-step, log W]: log energy =
 # log time + log power, log (energy x delay) = 2 log time + log power
@@ -39,14 +38,23 @@ OBJECTIVES = {"time": (1.0, 0.0), "energy": (1.0, 1.0), "edp": (2.0, 1.0)}
 
 
 def candidates(shape):
-    out = []
-    for K in K_SET:
-        if K > shape[0]:
-            continue
-        for rows in ROWS_SET:
-            for T in T_SET:
-                out.append(make_tune_config(shape, K, T, rows))
-    return out
+    return ccl_autotune_candidates(tuple(int(v) for v in shape))
+
+
+def sweep(shape, nchunks=0, r2=0.25, steps=None, reps=3, objective="time",
+          energy_window_s=0.0):
+    """Every candidate of `shape` (only K == nchunks when nchunks > 0)
+    measured by the library (ccl_autotune_sweep); returns (configs, one dict
+    per config as measure() gives them, index of the best by `objective`)."""
+    st = steps or steps_for(shape)
+    cfgs, samples, best = ccl_autotune_sweep(shape, nchunks, r2, st, reps, energy_window_s,
+                                             objective)
+    cells = float(np.prod(shape))
+    res = [dict(key=cfg_key(c), steps=st, s_per_step=o.seconds_per_step,
+                j_per_step=o.joules_per_step, s_per_cell_step=o.seconds_per_step / cells,
+                j_per_cell_step=o.joules_per_step / cells, window_s=o.window_seconds)
+           for c, o in zip(cfgs, samples)]
+    return cfgs, res, best
 
 
 def cfg_key(c):
@@ -74,11 +82,6 @@ def measure(cfgs, r2=0.25, reps=3, energy_window_s=0.0, steps=None, target_cell_
                           j_per_step=r.joules_per_step, s_per_cell_step=r.seconds_per_step / cells,
                           j_per_cell_step=r.joules_per_step / cells, window_s=r.window_seconds)
     return out
-
-
-def sweep(shape, r2=0.25, reps=3, energy_window_s=0.0):
-    cfgs = candidates(shape)
-    return cfgs, measure(cfgs, r2, reps, energy_window_s)
 
 
 def targets_of(samples):
@@ -209,15 +212,22 @@ class CostModel:
                 return tcfg, ti
         return cfgs[i], i
 
-    def rank(self, shape, objective="time", nchunks=None):
+    def rank(self, shape, objective="time", nchunks=None, k=None):
         """Indices into candidates(shape) (restricted to `nchunks` when
-        given) ordered by the model's predicted objective, best first."""
+        given) ordered by the model's predicted objective, best first (the
+        first k of them when k is given); scored and ordered on the GPU
+        (ccl_mlp_rank, the scores ccl_mlp_pick minimises)."""
+        import torch
         cfgs = candidates(shape)
         idx = [i for i, c in enumerate(cfgs) if nchunks is None or c.nchunks == nchunks]
-        y = self.predict(ccl_costmodel_features([cfgs[i] for i in idx]))
+        k = len(idx) if k is None else max(1, min(int(k), len(idx)))
         w = OBJECTIVES[objective]
-        score = w[0] * y[:, 0] + w[1] * y[:, 1]
-        return [idx[j] for j in np.argsort(score, kind="stable")]
+        wt, we = w[0] * float(self.ys.std[0]), w[1] * float(self.ys.std[1])
+        X = ccl_costmodel_features([cfgs[i] for i in idx])
+        xd = torch.from_numpy(self.xs.apply(X)).cuda()
+        order = torch.zeros(k, dtype=torch.int32, device="cuda")
+        ccl_mlp_rank(self.handle, len(idx), xd.data_ptr(), wt, we, k, order.data_ptr())
+        return [idx[j] for j in order.cpu().tolist()]
 
     def pick_verified(self, shape, objective="time", k=3, r2=0.25, nchunks=None, repeats=3):
         """The model's k best candidates measured by the autotuner; returns
@@ -361,9 +371,7 @@ def launch_config(shape, nchunks, steps, r2=0.25, model_path=MODEL_PATH, verify=
         res = measure(cfgs, r2, reps=3, steps=steps)
         i = int(np.argmin([r["s_per_step"] for r in res]))
         return top[i][0], top[i][1], f"cost model, fastest of its top {len(top)} measured"
-    cands = [c for c in candidates(shape) if c.nchunks == nchunks]
-    res = measure(cands, r2, reps=3, steps=steps)
-    i = int(np.argmin([r["s_per_step"] for r in res]))
+    cands, _, i = sweep(shape, nchunks, r2, steps=steps, reps=3)
     return cands[i].temporal_depth, cands[i].tile_rows, "autotuner sweep"
 
 

@@ -449,3 +449,38 @@ def test_wave_energy_validates_before_launch():
                              None) == ccl.CCL_E_INVALID
     assert L.ccl_wave_energy(2, I64(8, 8, 0), I64(7, 0, 0), ccl.CCL_DTYPE_F64, 0.1, dev, dev,
                              dev, None) == ccl.CCL_E_INVALID
+
+
+def test_autotune_candidates_enumeration():
+    """The library's candidate set: K in {1, 2, 4, 8, 16} up to the extent
+    along dimension 0, tile rows in {0, 16, 32, 64, 128}, T in 1..8, K
+    slowest; the nchunks filter; RANGE (with the count) when the room is
+    short; argument errors.  The sweep refuses an energy objective without
+    an energy window before it measures anything."""
+    for shape in [(512, 1024), (3, 700), (20, 40, 70), (1, 5, 5)]:
+        want = [(K, rows, T) for K in (1, 2, 4, 8, 16) if K <= shape[0]
+                for rows in (0, 16, 32, 64, 128) for T in range(1, 9)]
+        got = ccl.ccl_autotune_candidates(shape)
+        assert [(c.nchunks, c.tile_rows, c.temporal_depth) for c in got] == want
+        assert all(c.dims == len(shape) and tuple(c.shape[:c.dims]) == shape for c in got)
+        only4 = ccl.ccl_autotune_candidates(shape, 4)
+        assert [(c.nchunks, c.tile_rows, c.temporal_depth) for c in only4] == \
+            [w for w in want if w[0] == 4]
+    L = ccl.lib()
+    sh = (ctypes.c_int64 * 3)(64, 64, 0)
+    n = ctypes.c_int32(0)
+    out = (ccl.ccl_tune_config * 10)()
+    assert L.ccl_autotune_candidates(2, sh, 0, 10, out, ctypes.byref(n)) == ccl.CCL_E_RANGE
+    assert n.value == 5 * 5 * 8
+    assert L.ccl_autotune_candidates(4, sh, 0, 10, out, ctypes.byref(n)) == ccl.CCL_E_INVALID
+    assert L.ccl_autotune_candidates(2, None, 0, 10, out, ctypes.byref(n)) == ccl.CCL_E_INVALID
+    assert L.ccl_autotune_candidates(2, (ctypes.c_int64 * 3)(0, 64, 0), 0, 10, out,
+                                     ctypes.byref(n)) == ccl.CCL_E_INVALID
+    samples = (ccl.ccl_tune_sample * 200)()
+    cfgs = (ccl.ccl_tune_config * 200)()
+    best = ctypes.c_int32(-1)
+    assert L.ccl_autotune_sweep(2, sh, 0, 0.25, 8, 1, 0.0, ccl.CCL_OBJECTIVE_ENERGY, 0, None,
+                                200, cfgs, samples, ctypes.byref(n),
+                                ctypes.byref(best)) == ccl.CCL_E_INVALID
+    assert L.ccl_autotune_sweep(2, sh, 0, 0.25, 8, 1, 0.0, 7, 0, None, 200, cfgs, samples,
+                                ctypes.byref(n), ctypes.byref(best)) == ccl.CCL_E_INVALID

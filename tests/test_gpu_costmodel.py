@@ -168,6 +168,48 @@ def test_pick_is_oracle_argmin():
     ccl.ccl_mlp_destroy(h)
 
 
+@pytest.mark.parametrize("n,k", [(777, 10), (200, 200), (1, 1), (300, 3)])
+def test_rank_orders_the_pick_scores(n, k):
+    """ccl_mlp_rank: the k smallest of the scores ccl_mlp_pick writes, in
+    ascending order with ties to the lower index; its first entry is the
+    pick.  The scores are checked against the oracle's forward pass."""
+    import paper_2505_06022_amd as ccl
+    ws, bs, x, t, p = make(11, n)
+    h = ccl.ccl_mlp_create(p)
+    xd = torch.from_numpy(x.astype(np.float32)).cuda()
+    best = torch.zeros(1, dtype=torch.int32, device="cuda")
+    scores = torch.empty(n, device="cuda")
+    order = torch.full((k,), -1, dtype=torch.int32, device="cuda")
+    for w0, w1 in ((1.0, 0.0), (1.0, 1.0), (2.0, 1.0)):
+        ccl.ccl_mlp_pick(h, n, xd.data_ptr(), w0, w1, scores.data_ptr(), best.data_ptr())
+        ccl.ccl_mlp_rank(h, n, xd.data_ptr(), w0, w1, k, order.data_ptr())
+        torch.cuda.synchronize()
+        sc = scores.cpu().numpy()
+        got = order.cpu().numpy().tolist()
+        assert got == np.argsort(sc, kind="stable")[:k].tolist()
+        assert got[0] == int(best.item())
+        y = omlp.forward(ws, bs, x)[-1]
+        s = w0 * y[:, 0] + w1 * y[:, 1]
+        assert np.allclose(sc, s, rtol=1e-4, atol=1e-4)
+    with pytest.raises(ccl.CclError):
+        ccl.ccl_mlp_rank(h, n, xd.data_ptr(), 1.0, 0.0, n + 1, order.data_ptr())
+    ccl.ccl_mlp_destroy(h)
+
+
+def test_autotune_sweep():
+    """ccl_autotune_sweep measures exactly the library's candidates (K fixed
+    here) and returns the index of the fastest it measured."""
+    import paper_2505_06022_amd as ccl
+    shape = (256, 512)
+    cfgs, samples, best = ccl.ccl_autotune_sweep(shape, 2, 0.25, 16, reps=1)
+    want = ccl.ccl_autotune_candidates(shape, 2)
+    key = lambda c: (c.dims, tuple(c.shape[:c.dims]), c.nchunks, c.temporal_depth, c.tile_rows)
+    assert [key(c) for c in cfgs] == [key(c) for c in want] and len(cfgs) == 40
+    t = [o.seconds_per_step for o in samples]
+    assert all(v > 0 for v in t)
+    assert best == int(np.argmin(t))
+
+
 def test_autotune_measure():
     import paper_2505_06022_amd as ccl
     cfgs = [ccl.make_tune_config((512, 1024), K, T, rows)
