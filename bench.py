@@ -429,6 +429,7 @@ def main():
 
     import paper_2505_06022_amd as ccl
     import synth
+    from paper_2505_06022_amd import tune
     from paper_2505_06022_amd.fields import ChunkedWave
 
     if not ccl.LIB_PATH.exists():
@@ -505,8 +506,15 @@ def main():
         del cw
         torch.cuda.empty_cache()
         log("plain form (T=1)")
+        # the plain form's tile rows as the launcher would choose them: the
+        # fastest of the autotuner's T = 1 candidates for this split, measured
+        pcands = [c for c in tune.candidates(w["shape"])
+                  if c.nchunks == w["chunks"] and c.temporal_depth == 1]
+        pres = tune.measure(pcands, w["r2"], reps=3, steps=200)
+        prow = pcands[int(np.argmin([r["s_per_step"] for r in pres]))].tile_rows
+        out["plain_tile_rows"] = prow
         cp = ChunkedWave(w["share_offset"], w["shape"], w["chunks"], w["r2"], depth=1,
-                         buffer_range=w["global_shape"])
+                         tile_rows=prow, buffer_range=w["global_shape"])
         cp.scatter(u0, u0)
         cp.step(w["steps"])
         t_plain = time_runs(cp, w["steps"], 2)
