@@ -12,7 +12,6 @@ import os
 import numpy as np
 import pytest
 
-import synth
 
 pytestmark = pytest.mark.gpu
 

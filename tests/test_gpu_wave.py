@@ -9,7 +9,6 @@ re-orderings only: bitwise equal to the unchunked run.
 All buffers start NaN-poisoned (halos, padding, cells outside the domain), so
 a read of anything the halo exchange did not fill shows up as a NaN.
 """
-import math
 
 import numpy as np
 import pytest

@@ -1,7 +1,6 @@
 """Plants plausible mistakes in a copy of the oracle's C source and checks
 that the pins reject every one of them (CPU only; the copy is compiled into
 a temporary folder and never touches the real oracle build)."""
-import math
 
 import numpy as np
 import pytest
